@@ -1,0 +1,216 @@
+/*
+ * Plain CPU reference for the block-sparse product -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may load this library.
+ * It shares no code with the GPU library: no headers, helpers or tables in common.
+ *
+ * What it computes (paper Sec. 2.1, the rank-k update C_ij <- A_ik B_kj + C_ij summed over k, and
+ * Alg. 1's local update C <- alpha A(*,k) B(k,*) + C; Sec. 3.2 splits each update into a product
+ * C^(k)_ij = A_ik B_kj and a reduction C_ij += C^(k)_ij, which changes only when the terms are
+ * added, not which terms are added):
+ *
+ *   tilings r[0..M), s[0..K), t[0..N) (block sizes, Sec. 3.2 "arbitrarily sized blocks");
+ *   block-shape masks Ahat (M x K) and Bhat (K x N);
+ *   C-shape   Chat_ij = OR_k (Ahat_ik AND Bhat_kj);
+ *   values    C_ij = alpha * sum_{k : Ahat_ik and Bhat_kj} A_ik B_kj  (+ C_ij when accumulating),
+ *             for every (i,j) with Chat_ij; absent blocks are zero and are not stored.
+ *
+ * Storage (the library's input format): bit (i,j) of a shape is bit j%64 of word
+ * i*ceil(ncols/64) + j/64; present blocks are packed in row-major block order, each block
+ * row-major with leading dimension equal to its column count.
+ *
+ * Arithmetic: FP64, built without contraction (-ffp-contract=off, no fast-math), plain loops in
+ * i-k-j order, k blocks ascending, one OpenMP thread per whole C block, so the result does not
+ * depend on the thread count.  An optional long-double accumulator gives a tighter reference.
+ *
+ * Also here: the paper's two closed forms, the concurrent-iteration limit (Eq. 1) and the
+ * per-node memory overhead of one SUMMA iteration (Eq. 2).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+static int64_t words_of(int64_t ncols) { return (ncols + 63) / 64; }
+
+static int bit_at(const uint64_t* bits, int64_t ncols, int64_t i, int64_t j) {
+  return (int)((bits[i * words_of(ncols) + j / 64] >> (j % 64)) & 1u);
+}
+
+int64_t oracle_words(int64_t ncols) { return words_of(ncols); }
+
+/* Chat = boolean product of the two shapes, by the definition: a triple loop over (i, j, k). */
+int oracle_shape_product(int64_t M, int64_t K, int64_t N, const uint64_t* a_bits,
+                         const uint64_t* b_bits, uint64_t* c_bits) {
+  int64_t wn = words_of(N);
+  memset(c_bits, 0, (size_t)(M * wn) * sizeof(uint64_t));
+  for (int64_t i = 0; i < M; ++i)
+    for (int64_t j = 0; j < N; ++j) {
+      int present = 0;
+      for (int64_t k = 0; k < K && !present; ++k)
+        present = bit_at(a_bits, K, i, k) && bit_at(b_bits, N, k, j);
+      if (present) c_bits[i * wn + j / 64] |= (uint64_t)1 << (j % 64);
+    }
+  return 0;
+}
+
+/* Offsets (in elements) of the present blocks of an R x C block matrix in the packed layout;
+ * off[i*C + j] = -1 for an absent block.  Returns the total number of stored elements. */
+int64_t oracle_block_offsets(int64_t R, int64_t C, const int64_t* rsz, const int64_t* csz,
+                             const uint64_t* bits, int64_t* off) {
+  int64_t pos = 0;
+  for (int64_t i = 0; i < R; ++i)
+    for (int64_t j = 0; j < C; ++j) {
+      if (bit_at(bits, C, i, j)) {
+        off[i * C + j] = pos;
+        pos += rsz[i] * csz[j];
+      } else {
+        off[i * C + j] = -1;
+      }
+    }
+  return pos;
+}
+
+/* Useful flops: 2 r_i s_k t_j summed over every triple with both blocks present. */
+double oracle_useful_flops(int64_t M, int64_t K, int64_t N, const int64_t* r, const int64_t* s,
+                           const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits) {
+  double f = 0.0;
+  for (int64_t i = 0; i < M; ++i)
+    for (int64_t k = 0; k < K; ++k) {
+      if (!bit_at(a_bits, K, i, k)) continue;
+      for (int64_t j = 0; j < N; ++j)
+        if (bit_at(b_bits, N, k, j)) f += 2.0 * (double)r[i] * (double)s[k] * (double)t[j];
+    }
+  return f;
+}
+
+typedef struct {
+  int64_t M, K, N;
+  const int64_t *r, *s, *t;
+  const uint64_t *a_bits, *b_bits;
+  int64_t *a_off, *b_off; /* M*K and K*N, -1 = absent */
+} problem;
+
+static int setup(problem* p, int64_t M, int64_t K, int64_t N, const int64_t* r, const int64_t* s,
+                 const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits) {
+  p->M = M; p->K = K; p->N = N; p->r = r; p->s = s; p->t = t;
+  p->a_bits = a_bits; p->b_bits = b_bits;
+  p->a_off = (int64_t*)malloc((size_t)(M * K > 0 ? M * K : 1) * sizeof(int64_t));
+  p->b_off = (int64_t*)malloc((size_t)(K * N > 0 ? K * N : 1) * sizeof(int64_t));
+  if (!p->a_off || !p->b_off) return -1;
+  oracle_block_offsets(M, K, r, s, a_bits, p->a_off);
+  oracle_block_offsets(K, N, s, t, b_bits, p->b_off);
+  return 0;
+}
+
+static void teardown(problem* p) { free(p->a_off); free(p->b_off); }
+
+/* One C block: out (r_i x t_j, row-major) = sum over present k of A_ik B_kj, k ascending,
+ * elements in i-k-j order. Returns 1 if the block is present in Chat. */
+static int block_product(const problem* p, const double* A, const double* B, int64_t i, int64_t j,
+                         double* out, int extended) {
+  int64_t h = p->r[i], w = p->t[j];
+  int present = 0;
+  long double* acc = NULL;
+  if (extended) acc = (long double*)calloc((size_t)(h * w > 0 ? h * w : 1), sizeof(long double));
+  for (int64_t e = 0; e < h * w; ++e) out[e] = 0.0;
+  for (int64_t k = 0; k < p->K; ++k) {
+    int64_t ao = p->a_off[i * p->K + k], bo = p->b_off[k * p->N + j];
+    if (ao < 0 || bo < 0) continue;
+    present = 1;
+    int64_t d = p->s[k];
+    const double* a = A + ao; /* h x d */
+    const double* b = B + bo; /* d x w */
+    for (int64_t x = 0; x < h; ++x)
+      for (int64_t y = 0; y < d; ++y) {
+        double av = a[x * d + y];
+        for (int64_t z = 0; z < w; ++z) {
+          if (extended) acc[x * w + z] += (long double)av * (long double)b[y * w + z];
+          else out[x * w + z] += av * b[y * w + z];
+        }
+      }
+  }
+  if (extended) {
+    for (int64_t e = 0; e < h * w; ++e) out[e] = (double)acc[e];
+    free(acc);
+  }
+  return present;
+}
+
+/* Full product.  C is the packed C buffer (layout from the C-shape); with accumulate = 0 it is
+ * overwritten, with accumulate = 1 it must hold the previous C and receives alpha*AB + C. */
+int oracle_bsmm(int64_t M, int64_t K, int64_t N, const int64_t* r, const int64_t* s,
+                const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits, const double* A,
+                const double* B, double alpha, int accumulate, double* C, int extended) {
+  problem p;
+  if (setup(&p, M, K, N, r, s, t, a_bits, b_bits)) { teardown(&p); return -1; }
+  int64_t wn = words_of(N);
+  uint64_t* c_bits = (uint64_t*)calloc((size_t)(M * wn > 0 ? M * wn : 1), sizeof(uint64_t));
+  int64_t* c_off = (int64_t*)malloc((size_t)(M * N > 0 ? M * N : 1) * sizeof(int64_t));
+  if (!c_bits || !c_off) { free(c_bits); free(c_off); teardown(&p); return -1; }
+  oracle_shape_product(M, K, N, a_bits, b_bits, c_bits);
+  oracle_block_offsets(M, N, r, t, c_bits, c_off);
+  int status = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < M * N; ++q) {
+    int64_t i = q / N, j = q % N;
+    int64_t co = c_off[q];
+    if (co < 0) continue;
+    int64_t hw = r[i] * t[j];
+    double* tmp = (double*)malloc((size_t)(hw > 0 ? hw : 1) * sizeof(double));
+    if (!tmp) { status = -1; continue; }
+    block_product(&p, A, B, i, j, tmp, extended);
+    for (int64_t e = 0; e < hw; ++e) {
+      double v = alpha * tmp[e];
+      C[co + e] = accumulate ? v + C[co + e] : v;
+    }
+    free(tmp);
+  }
+  free(c_bits); free(c_off); teardown(&p);
+  return status;
+}
+
+/* Selected C blocks only: out receives the blocks (i_q, j_q) concatenated, each r_i x t_j
+ * row-major, value alpha * sum_k A_ik B_kj (no accumulation).  present[q] tells whether the block
+ * belongs to the C-shape (an absent block is written as zeros). */
+int oracle_bsmm_blocks(int64_t M, int64_t K, int64_t N, const int64_t* r, const int64_t* s,
+                       const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits,
+                       const double* A, const double* B, double alpha, int64_t nsel,
+                       const int64_t* sel_i, const int64_t* sel_j, double* out, int32_t* present,
+                       int extended) {
+  problem p;
+  if (setup(&p, M, K, N, r, s, t, a_bits, b_bits)) { teardown(&p); return -1; }
+  int64_t* pos = (int64_t*)malloc((size_t)(nsel + 1) * sizeof(int64_t));
+  if (!pos) { teardown(&p); return -1; }
+  pos[0] = 0;
+  for (int64_t q = 0; q < nsel; ++q) {
+    if (sel_i[q] < 0 || sel_i[q] >= M || sel_j[q] < 0 || sel_j[q] >= N) { free(pos); teardown(&p); return -2; }
+    pos[q + 1] = pos[q] + r[sel_i[q]] * t[sel_j[q]];
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < nsel; ++q) {
+    double* o = out + pos[q];
+    present[q] = block_product(&p, A, B, sel_i[q], sel_j[q], o, extended);
+    int64_t hw = r[sel_i[q]] * t[sel_j[q]];
+    for (int64_t e = 0; e < hw; ++e) o[e] = alpha * o[e];
+  }
+  free(pos); teardown(&p);
+  return 0;
+}
+
+/* Eq. 1: the number of SUMMA iterations issued at once on a P_row x P_col grid with K blocks
+ * along the inner dimension: 2 when either grid dimension is below 2, K when both reach K, and
+ * min(P_row, P_col) otherwise. */
+int64_t oracle_concurrent_iterations(int64_t prow, int64_t pcol, int64_t K) {
+  if (prow < 2 || pcol < 2) return 2;
+  if (prow >= K && pcol >= K) return K;
+  return prow < pcol ? prow : pcol;
+}
+
+/* Eq. 2: average memory (in elements) one process holds per SUMMA iteration: the A column panel
+ * share M m k / P_row, the B row panel share N k n / P_col and the local result
+ * M N m n / (P_row P_col). */
+double oracle_memory_overhead(double M, double N, double m, double n, double k, double prow,
+                              double pcol) {
+  return M * m * k / prow + N * k * n / pcol + M * N * m * n / (prow * pcol);
+}

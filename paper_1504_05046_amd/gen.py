@@ -1,0 +1,274 @@
+"""Seeded synthetic inputs for block-sparse products (shared by the tests and the benchmark).
+
+This module only *draws* inputs; it holds none of the multiply's arithmetic.  A problem is
+described the way the library consumes it:
+
+* three tilings (vectors of block sizes): ``rows`` (M blocks of C and A), ``inner`` (K blocks
+  shared by A's columns and B's rows) and ``cols`` (N blocks of C and B) -- the problem-given,
+  possibly nonuniform blocking of the matrix dimensions (paper Sec. 3.2, over-decomposition into
+  arbitrarily sized blocks);
+* two block-shape masks ``a_mask`` (M x K) and ``b_mask`` (K x N) saying which blocks are present
+  (block sparsity, paper Sec. 1);
+* the present blocks' values, packed: blocks in row-major block order (i, then k), each block
+  row-major with leading dimension equal to its column count.
+
+Every block's values come from its own counter-addressed numpy stream
+``SeedSequence(entropy=seed, spawn_key=(VALUES, matrix, i, k))`` so that any block can be
+regenerated on its own.
+
+Workloads (sizes and distributions), one function each:
+
+* ``uniform_1024``      N=1024, 16x16 blocks of 64, Bernoulli(0.5) per A and B block, U[-1,1].
+* ``nonuniform_16384``  N=16384, sizes U{32..256} (last adjusted), Bernoulli(0.3), N(0,1).
+* ``batch64``           64 independent products, N in {1024,2048,4096,8192}, sizes U{16..192},
+                        density U[0.1,0.9] per product, N(0,1).
+* ``precision_32768``   N=32768, sizes U{64..256}, Bernoulli(0.4), N(0,1)*10^U(-4,0) per block.
+* ``decay_cloud``       4000 points in a 60-unit cube, block size per point from {10,25,40,60},
+                        block (i,j) present iff exp(-r_ij/2) > 1e-8, values N(0,1)*exp(-r_ij/2);
+                        C = A*A.
+* ``paper_dense``       the paper's dense square experiment shape (Sec. 4.1): uniform blocks, or
+                        the add-one-row-at-a-time nonuniform blocking with the same block count.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+# spawn-key tags, so that the streams for tilings, shapes and values never coincide
+_TILING, _SHAPE, _VALUES, _SCALE, _POINTS = 1, 2, 3, 4, 5
+MAT_A, MAT_B = 0, 1
+
+
+def _rng(seed: int, *key: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence(entropy=int(seed), spawn_key=tuple(int(k) for k in key)))
+
+
+# --------------------------------------------------------------------------------------------
+# tilings
+# --------------------------------------------------------------------------------------------
+def tiling_uniform(n: int, b: int) -> np.ndarray:
+    """n split into blocks of b (the last one smaller if b does not divide n)."""
+    q, r = divmod(n, b)
+    sizes = [b] * q + ([r] if r else [])
+    return np.asarray(sizes, dtype=np.int64)
+
+
+def tiling_random(n: int, lo: int, hi: int, rng: np.random.Generator) -> np.ndarray:
+    """Block sizes drawn uniformly from the integers lo..hi until the rest fits in one block;
+    the last block takes the remainder (so it may be smaller than lo)."""
+    sizes: List[int] = []
+    rest = n
+    while rest > hi:
+        s = int(rng.integers(lo, hi + 1))
+        sizes.append(s)
+        rest -= s
+    if rest > 0:
+        sizes.append(rest)
+    return np.asarray(sizes, dtype=np.int64)
+
+
+def tiling_add_one(n: int, nblocks: int, rng: np.random.Generator) -> np.ndarray:
+    """The paper's nonuniform blocking (Sec. 4.1): start from nblocks empty blocks and add one
+    row to a uniformly chosen block until the sizes sum to n.  Blocks that stay empty are
+    dropped (a block needs at least one row)."""
+    counts = rng.multinomial(n, [1.0 / nblocks] * nblocks)
+    return np.asarray([c for c in counts if c > 0], dtype=np.int64)
+
+
+# --------------------------------------------------------------------------------------------
+# problems
+# --------------------------------------------------------------------------------------------
+@dataclasses.dataclass
+class Problem:
+    """One block-sparse product C = alpha * A * B (+ C)."""
+    name: str
+    rows: np.ndarray      # int64[M]
+    inner: np.ndarray     # int64[K]
+    cols: np.ndarray      # int64[N]
+    a_mask: np.ndarray    # bool[M, K]
+    b_mask: np.ndarray    # bool[K, N]
+    a_data: np.ndarray    # float64, packed present blocks of A
+    b_data: np.ndarray    # float64, packed present blocks of B (same object as a_data when aliased)
+    b_is_a: bool = False  # C = A * A
+
+    @property
+    def M(self) -> int:
+        return int(self.rows.shape[0])
+
+    @property
+    def K(self) -> int:
+        return int(self.inner.shape[0])
+
+    @property
+    def N(self) -> int:
+        return int(self.cols.shape[0])
+
+    def a_bits(self) -> np.ndarray:
+        return pack_bits(self.a_mask)
+
+    def b_bits(self) -> np.ndarray:
+        return pack_bits(self.b_mask)
+
+
+def pack_bits(mask: np.ndarray) -> np.ndarray:
+    """Block-shape bitmap in the library's word layout: bit (i, j) is bit j % 64 of word
+    i * ceil(cols / 64) + j // 64; padding bits are zero."""
+    mask = np.asarray(mask, dtype=bool)
+    r, c = mask.shape
+    w = (c + 63) // 64
+    padded = np.zeros((r, w * 64), dtype=bool)
+    padded[:, :c] = mask
+    bits = np.packbits(padded.reshape(r, w, 8, 8)[:, :, :, ::-1], axis=-1).reshape(r, w, 8)
+    # packbits gives big-endian bit order inside a byte; bytes are little-endian in the word
+    return bits.view("<u8").reshape(r * w).astype(np.uint64) if r * w else np.zeros(0, np.uint64)
+
+
+def unpack_bits(words: np.ndarray, r: int, c: int) -> np.ndarray:
+    w = (c + 63) // 64
+    if r * w == 0:
+        return np.zeros((r, c), dtype=bool)
+    b = np.asarray(words, dtype="<u8").reshape(r, w).view(np.uint8).reshape(r, w, 8)
+    bits = np.unpackbits(b, axis=-1).reshape(r, w, 8, 8)[:, :, :, ::-1].reshape(r, w * 64)
+    return bits[:, :c].astype(bool)
+
+
+def _fill_blocks(seed: int, mat: int, mask: np.ndarray, rsz: np.ndarray, csz: np.ndarray,
+                 draw) -> np.ndarray:
+    """Concatenate the present blocks in row-major block order; draw(rng, i, j, h, w) -> values."""
+    total = int(sum(int(rsz[i]) * int(csz[j]) for i, j in zip(*np.nonzero(mask))))
+    out = np.empty(total, dtype=np.float64)
+    pos = 0
+    for i, j in zip(*np.nonzero(mask)):
+        h, w = int(rsz[i]), int(csz[j])
+        out[pos:pos + h * w] = draw(_rng(seed, _VALUES, mat, i, j), int(i), int(j), h, w).reshape(-1)
+        pos += h * w
+    return out
+
+
+def block_values(p: Problem, seed: int, mat: int, i: int, j: int, draw) -> np.ndarray:
+    """Regenerate one block on its own (same stream as the packed buffer)."""
+    rsz, csz = (p.rows, p.inner) if mat == MAT_A else (p.inner, p.cols)
+    return draw(_rng(seed, _VALUES, mat, i, j), i, j, int(rsz[i]), int(csz[j]))
+
+
+def _normal(rng, i, j, h, w):
+    return rng.standard_normal((h, w))
+
+
+def _uniform_pm1(rng, i, j, h, w):
+    return rng.uniform(-1.0, 1.0, (h, w))
+
+
+def make_problem(name: str, seed: int, rows, inner, cols, a_mask, b_mask, draw=_normal,
+                 b_is_a: bool = False) -> Problem:
+    rows = np.asarray(rows, dtype=np.int64)
+    inner = np.asarray(inner, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    a_mask = np.asarray(a_mask, dtype=bool)
+    b_mask = np.asarray(b_mask, dtype=bool)
+    a = _fill_blocks(seed, MAT_A, a_mask, rows, inner, draw)
+    b = a if b_is_a else _fill_blocks(seed, MAT_B, b_mask, inner, cols, draw)
+    return Problem(name, rows, inner, cols, a_mask, b_mask, a, b, b_is_a)
+
+
+def random_problem(seed: int, M: int, K: int, N: int, lo: int, hi: int, pa: float, pb: float,
+                   draw=_normal, name: str = "random") -> Problem:
+    """Small random problem: M x K x N blocks with sizes U{lo..hi}, Bernoulli masks."""
+    t = _rng(seed, _TILING)
+    rows = t.integers(lo, hi + 1, M)
+    inner = t.integers(lo, hi + 1, K)
+    cols = t.integers(lo, hi + 1, N)
+    s = _rng(seed, _SHAPE)
+    a_mask = s.random((M, K)) < pa
+    b_mask = s.random((K, N)) < pb
+    return make_problem(name, seed, rows, inner, cols, a_mask, b_mask, draw)
+
+
+def integer_problem(seed: int, M: int, K: int, N: int, lo: int, hi: int, pa: float, pb: float,
+                    vmax: int = 8) -> Problem:
+    """Random problem with integer values in [-vmax, vmax]: exact in bf16 and fp32, so every
+    precision form must reproduce the FP64 result bit for bit while partial sums stay < 2^24."""
+    def draw(rng, i, j, h, w):
+        return rng.integers(-vmax, vmax + 1, (h, w)).astype(np.float64)
+    return random_problem(seed, M, K, N, lo, hi, pa, pb, draw, name="integer")
+
+
+# ---- the five workloads -----------------------------------------------------------------------
+def uniform_1024(seed: int = 1000) -> Problem:
+    rows = tiling_uniform(1024, 64)
+    s = _rng(seed, _SHAPE)
+    a_mask = s.random((16, 16)) < 0.5
+    b_mask = s.random((16, 16)) < 0.5
+    return make_problem("uniform_1024", seed, rows, rows, rows, a_mask, b_mask, _uniform_pm1)
+
+
+def nonuniform(seed: int, n: int, lo: int, hi: int, density: float, draw=_normal,
+               name: Optional[str] = None) -> Problem:
+    rows = tiling_random(n, lo, hi, _rng(seed, _TILING, 0))
+    inner = tiling_random(n, lo, hi, _rng(seed, _TILING, 1))
+    cols = tiling_random(n, lo, hi, _rng(seed, _TILING, 2))
+    s = _rng(seed, _SHAPE)
+    a_mask = s.random((rows.size, inner.size)) < density
+    b_mask = s.random((inner.size, cols.size)) < density
+    return make_problem(name or f"nonuniform_{n}", seed, rows, inner, cols, a_mask, b_mask, draw)
+
+
+def nonuniform_16384(seed: int = 2000) -> Problem:
+    return nonuniform(seed, 16384, 32, 256, 0.3, name="nonuniform_16384")
+
+
+def batch64(seed: int = 3000, count: int = 64, sizes: Sequence[int] = (1024, 2048, 4096, 8192)) -> List[Problem]:
+    out = []
+    for b in range(count):
+        ps = seed * 1000 + b
+        c = _rng(ps, _SHAPE, 99)
+        n = int(sizes[int(c.integers(0, len(sizes)))])
+        dens = float(c.uniform(0.1, 0.9))
+        out.append(nonuniform(ps, n, 16, 192, dens, name=f"batch{b}_{n}_{dens:.2f}"))
+    return out
+
+
+def _scaled_normal(seed: int):
+    def draw(rng, i, j, h, w):
+        # one continuous factor 10^U(-4,0) per block, drawn from the block's own stream
+        f = 10.0 ** rng.uniform(-4.0, 0.0)
+        return rng.standard_normal((h, w)) * f
+    return draw
+
+
+def precision_32768(seed: int = 4000, n: int = 32768) -> Problem:
+    return nonuniform(seed, n, 64, 256, 0.4, draw=_scaled_normal(seed), name=f"precision_{n}")
+
+
+def decay_cloud(seed: int = 5000, npts: int = 4000, box: float = 60.0,
+                sizes: Sequence[int] = (10, 25, 40, 60), cutoff: float = 1e-8) -> Problem:
+    p = _rng(seed, _POINTS)
+    pts = p.uniform(0.0, box, (npts, 3))
+    bs = np.asarray(sizes, dtype=np.int64)[p.integers(0, len(sizes), npts)]
+    # pairwise distances, row by row to bound memory
+    mask = np.zeros((npts, npts), dtype=bool)
+    rmax = -2.0 * math.log(cutoff)
+    for i in range(npts):
+        d = np.sqrt(((pts - pts[i]) ** 2).sum(axis=1))
+        mask[i] = d < rmax
+    def draw(rng, i, j, h, w):
+        r = float(np.sqrt(((pts[i] - pts[j]) ** 2).sum()))
+        return rng.standard_normal((h, w)) * math.exp(-0.5 * r)
+    return make_problem(f"decay_cloud_{npts}", seed, bs, bs, bs, mask, mask, draw, b_is_a=True)
+
+
+def paper_dense(seed: int, n: int, block: int, nonuniform_blocks: bool) -> Problem:
+    if nonuniform_blocks:
+        nb = n // block
+        rows = tiling_add_one(n, nb, _rng(seed, _TILING, 0))
+        inner = tiling_add_one(n, nb, _rng(seed, _TILING, 1))
+        cols = tiling_add_one(n, nb, _rng(seed, _TILING, 2))
+    else:
+        rows = inner = cols = tiling_uniform(n, block)
+    a_mask = np.ones((rows.size, inner.size), dtype=bool)
+    b_mask = np.ones((inner.size, cols.size), dtype=bool)
+    return make_problem(f"paper_dense_{n}_{'nonuni' if nonuniform_blocks else 'uni'}", seed,
+                        rows, inner, cols, a_mask, b_mask)

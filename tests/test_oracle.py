@@ -1,0 +1,320 @@
+"""Pins for the CPU oracle (no GPU): each test checks it against something other than itself --
+a library routine, an exact special case, a brute-force count, a closed form or the paper's
+equations -- so that a dropped term, a wrong sign or index or a transposed operand fails."""
+import itertools
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_05046_amd import gen
+from tests.helpers import from_dense, higham_gamma, packed_offsets, to_dense
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _dense_product_check(p: gen.Problem, alpha=1.0):
+    """Oracle vs numpy's matmul of the zero-filled dense matrices (elementwise Higham bound)."""
+    A = to_dense(p.rows, p.inner, p.a_mask, p.a_data)
+    B = to_dense(p.inner, p.cols, p.b_mask, p.b_data)
+    c_mask = (p.a_mask.astype(np.int64) @ p.b_mask.astype(np.int64)) > 0
+    ref = alpha * (A @ B)
+    bound = 2 * higham_gamma(max(1, int(p.inner.sum()))) * (np.abs(A) @ np.abs(B)) * abs(alpha) + 1e-300
+    got = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data, alpha)
+    got_dense = to_dense(p.rows, p.cols, c_mask, got)
+    assert got.size == packed_offsets(p.rows, p.cols, c_mask)[1]
+    assert np.all(np.abs(got_dense - ref) <= bound)
+    # blocks outside the C-shape are zero in the dense product too
+    assert np.all(ref[got_dense == 0] == 0) or np.all(np.abs(ref - got_dense) <= bound)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_matches_numpy_dense(seed):
+    rng = np.random.default_rng(seed)
+    M, K, N = (int(x) for x in rng.integers(1, 6, 3))
+    p = gen.random_problem(seed, M, K, N, 1, 8, float(rng.uniform(0.2, 1.0)), float(rng.uniform(0.2, 1.0)))
+    _dense_product_check(p, alpha=float(rng.choice([1.0, -0.75, 3.0])))
+
+
+def test_matches_numpy_dense_ragged_sizes():
+    # block sizes that are not multiples of any tile: 1, 3, 15, 17, 31, 33
+    rows = [1, 17, 33]
+    inner = [3, 31, 15, 1]
+    cols = [17, 1, 33]
+    rng = np.random.default_rng(5)
+    a_mask = rng.random((3, 4)) < 0.7
+    b_mask = rng.random((4, 3)) < 0.7
+    p = gen.make_problem("ragged", 5, rows, inner, cols, a_mask, b_mask)
+    _dense_product_check(p)
+
+
+def test_shape_product_exhaustive_2x2x2():
+    """All 2^4 x 2^4 pairs of 2x2 block shapes: C-shape is the boolean product (numpy), bit-exact,
+    and the values agree with the dense product."""
+    sizes = [2, 3]
+    for abits in range(16):
+        for bbits in range(16):
+            a_mask = np.array([[(abits >> (2 * i + k)) & 1 for k in range(2)] for i in range(2)], bool)
+            b_mask = np.array([[(bbits >> (2 * k + j)) & 1 for j in range(2)] for k in range(2)], bool)
+            c_ref = (a_mask.astype(int) @ b_mask.astype(int)) > 0
+            c = oracle.shape_product(2, 2, 2, gen.pack_bits(a_mask), gen.pack_bits(b_mask))
+            assert np.array_equal(gen.unpack_bits(c, 2, 2), c_ref)
+            p = gen.make_problem("x", abits * 16 + bbits, sizes, sizes, sizes, a_mask, b_mask)
+            _dense_product_check(p)
+
+
+def test_shape_product_random_wide():
+    """Shapes wider than one 64-bit word (bitmap row padding) vs numpy's boolean product."""
+    rng = np.random.default_rng(3)
+    for M, K, N in [(5, 70, 130), (64, 64, 64), (1, 129, 1), (3, 1, 65)]:
+        a = rng.random((M, K)) < 0.1
+        b = rng.random((K, N)) < 0.1
+        c = oracle.shape_product(M, K, N, gen.pack_bits(a), gen.pack_bits(b))
+        assert np.array_equal(gen.unpack_bits(c, M, N), (a.astype(int) @ b.astype(int)) > 0)
+        # padding bits stay zero
+        full = np.asarray(c, dtype=np.uint64).reshape(M, -1)
+        if N % 64:
+            assert np.all((full[:, -1] >> np.uint64(N % 64)) == 0)
+
+
+def test_identity_blocks_give_b_bitwise():
+    """A = block-diagonal identity (row tiling = inner tiling) => C = B exactly, and C's shape is
+    B's shape."""
+    rng = np.random.default_rng(11)
+    inner = np.array([4, 1, 7, 3, 5])
+    cols = np.array([2, 6, 3])
+    a_mask = np.eye(5, dtype=bool)
+    b_mask = rng.random((5, 3)) < 0.6
+    b_mask[0, 0] = True
+    p = gen.make_problem("id", 11, inner, inner, cols, a_mask, b_mask)
+    # overwrite A's packed data with identity blocks
+    a = np.concatenate([np.eye(int(s)).reshape(-1) for s in inner])
+    c = oracle.bsmm(inner, inner, cols, p.a_bits(), p.b_bits(), a, p.b_data)
+    c_bits = oracle.shape_product(5, 5, 3, p.a_bits(), p.b_bits())
+    assert np.array_equal(gen.unpack_bits(c_bits, 5, 3), b_mask)
+    assert np.array_equal(c, p.b_data)
+
+
+def test_permutation_blocks_bitwise():
+    """A = a block permutation (equal-size blocks) with an element permutation inside each block
+    => C is B with its rows permuted, exactly."""
+    rng = np.random.default_rng(12)
+    nb, bs = 6, 5
+    sizes = np.full(nb, bs)
+    cols = np.array([3, 4, 2, 7])
+    perm = rng.permutation(nb)
+    a_mask = np.zeros((nb, nb), bool)
+    a_blocks = []
+    for i in range(nb):
+        a_mask[i, perm[i]] = True
+    inner_perm = [rng.permutation(bs) for _ in range(nb)]
+    for i in range(nb):
+        P = np.zeros((bs, bs))
+        P[np.arange(bs), inner_perm[i]] = 1.0
+        a_blocks.append(P.reshape(-1))
+    a = np.concatenate(a_blocks)
+    b_mask = rng.random((nb, 4)) < 0.7
+    p = gen.make_problem("perm", 12, sizes, sizes, cols, a_mask, b_mask)
+    c = oracle.bsmm(sizes, sizes, cols, gen.pack_bits(a_mask), p.b_bits(), a, p.b_data)
+    Bd = to_dense(sizes, cols, b_mask, p.b_data)
+    rows_src = np.concatenate([perm[i] * bs + inner_perm[i] for i in range(nb)])
+    Cd = Bd[rows_src]
+    c_mask = b_mask[perm]
+    assert np.array_equal(c, from_dense(sizes, cols, c_mask, Cd))
+
+
+def test_integer_inputs_exact():
+    """Integer values: the FP64 sum is exact, so it equals numpy's int64 product exactly."""
+    p = gen.integer_problem(21, 4, 5, 3, 1, 19, 0.6, 0.6)
+    A = to_dense(p.rows, p.inner, p.a_mask, p.a_data).astype(np.int64)
+    B = to_dense(p.inner, p.cols, p.b_mask, p.b_data).astype(np.int64)
+    c_mask = (p.a_mask.astype(int) @ p.b_mask.astype(int)) > 0
+    ref = from_dense(p.rows, p.cols, c_mask, (A @ B).astype(np.float64))
+    got = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    assert np.array_equal(got, ref)
+
+
+def test_alpha_power_of_two_and_accumulate():
+    p = gen.random_problem(31, 3, 4, 3, 2, 9, 0.6, 0.6)
+    args = (p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    c1 = oracle.bsmm(*args)
+    assert np.array_equal(oracle.bsmm(*args, alpha=0.25), 0.25 * c1)
+    assert np.array_equal(oracle.bsmm(*args, alpha=-8.0), -8.0 * c1)
+    # C <- AB + C applied to C = AB gives exactly 2 AB
+    assert np.array_equal(oracle.bsmm(*args, C=c1), 2.0 * c1)
+    # and accumulation adds alpha*AB to an arbitrary C elementwise
+    c0 = np.random.default_rng(0).standard_normal(c1.size)
+    assert np.array_equal(oracle.bsmm(*args, alpha=0.5, C=c0), 0.5 * c1 + c0)
+
+
+def test_aliased_a_times_a():
+    rows = np.array([3, 5, 2, 4])
+    rng = np.random.default_rng(4)
+    mask = rng.random((4, 4)) < 0.6
+    np.fill_diagonal(mask, True)
+    p = gen.make_problem("alias", 4, rows, rows, rows, mask, mask, b_is_a=True)
+    assert p.b_data is p.a_data
+    _dense_product_check(p)
+
+
+def test_selected_blocks_match_full_product():
+    p = gen.random_problem(41, 5, 4, 6, 1, 12, 0.5, 0.5)
+    args = (p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    full = oracle.bsmm(*args, alpha=1.5)
+    c_bits = oracle.shape_product(p.M, p.K, p.N, p.a_bits(), p.b_bits())
+    c_mask = gen.unpack_bits(c_bits, p.M, p.N)
+    off, _ = packed_offsets(p.rows, p.cols, c_mask)
+    sel = [(i, j) for i in range(p.M) for j in range(p.N)]
+    blocks, present = oracle.bsmm_blocks(*args, sel, alpha=1.5)
+    for (i, j), blk, pr in zip(sel, blocks, present):
+        assert pr == bool(c_mask[i, j])
+        if pr:
+            o = off[(i, j)]
+            assert np.array_equal(blk.reshape(-1), full[o:o + blk.size])
+        else:
+            assert not np.any(blk)
+
+
+def test_extended_accumulator_vs_exact_rationals():
+    """Long-double accumulation agrees with exact rational arithmetic to within an FP64 ulp or two,
+    and the FP64 accumulation to within its Higham bound."""
+    p = gen.random_problem(51, 2, 3, 2, 2, 6, 1.0, 1.0)
+    args = (p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    ext = oracle.bsmm(*args, extended=True)
+    dbl = oracle.bsmm(*args)
+    A = to_dense(p.rows, p.inner, p.a_mask, p.a_data)
+    B = to_dense(p.inner, p.cols, p.b_mask, p.b_data)
+    n = A.shape[1]
+    exact = np.array([[float(sum(Fraction(A[r, k]) * Fraction(B[k, c]) for k in range(n)))
+                       for c in range(B.shape[1])] for r in range(A.shape[0])])
+    c_mask = np.ones((p.M, p.N), bool)
+    ref = from_dense(p.rows, p.cols, c_mask, exact)
+    absab = from_dense(p.rows, p.cols, c_mask, np.abs(A) @ np.abs(B))
+    assert np.all(np.abs(ext - ref) <= 2 * np.spacing(np.abs(ref)) + 1e-300)
+    assert np.all(np.abs(dbl - ref) <= higham_gamma(n) * absab)
+
+
+def test_useful_flops_closed_form():
+    """2 * sum over present triples of r_i s_k t_j = 2 r^T ((Ahat * s) Bhat) t, a matrix
+    expression evaluated by numpy (brute force is the oracle's triple loop)."""
+    for seed in range(5):
+        p = gen.random_problem(60 + seed, 7, 9, 5, 1, 30, 0.4, 0.5)
+        f = oracle.useful_flops(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits())
+        Ah = p.a_mask.astype(np.int64)
+        Bh = p.b_mask.astype(np.int64)
+        closed = 2 * int(p.rows @ ((Ah * p.inner[None, :]) @ Bh) @ p.cols)
+        assert f == closed
+
+
+def test_block_offsets_layout():
+    rows = [2, 3]
+    cols = [4, 1, 2]
+    mask = np.array([[1, 0, 1], [1, 1, 0]], bool)
+    off, total = oracle.block_offsets(rows, cols, gen.pack_bits(mask))
+    # row-major block order: (0,0) 8 elems, (0,2) 4, (1,0) 12, (1,1) 3
+    assert total == 8 + 4 + 12 + 3
+    assert off.tolist() == [[0, -1, 8], [12, 24, -1]]
+
+
+# ---- the paper's closed forms ------------------------------------------------------------------
+def test_eq1_concurrent_iterations_golden():
+    with open(os.path.join(GOLDEN, "eq1_concurrent_iterations.txt")) as f:
+        rows = [list(map(int, ln.split())) for ln in f if ln.strip() and not ln.startswith("#")]
+    assert len(rows) >= 10
+    for prow, pcol, K, want in rows:
+        assert oracle.concurrent_iterations(prow, pcol, K) == want, (prow, pcol, K)
+
+
+def test_eq2_memory_overhead_vs_cyclic_count():
+    """Eq. 2 against a brute-force count: distribute an M x N block grid (uniform blocks m x n,
+    inner blocks k) cyclically over a P_row x P_col grid; in one SUMMA iteration every process
+    holds its rows' A(*,k) blocks, its columns' B(k,*) blocks and its local C blocks.  The average
+    over processes equals the closed form exactly (also when the grid does not divide M, N)."""
+    for (M, N, m, n, k, prow, pcol) in [(8, 8, 4, 4, 3, 2, 2), (7, 5, 3, 2, 6, 3, 2),
+                                        (16, 12, 5, 7, 2, 4, 3), (3, 3, 1, 1, 1, 1, 1),
+                                        (10, 9, 2, 3, 4, 5, 4)]:
+        total = 0
+        for p in range(prow):
+            for q in range(pcol):
+                my_rows = sum(1 for i in range(M) if i % prow == p)
+                my_cols = sum(1 for j in range(N) if j % pcol == q)
+                total += my_rows * m * k + k * my_cols * n + my_rows * my_cols * m * n
+        avg = Fraction(total, prow * pcol)
+        got = oracle.memory_overhead(M, N, m, n, k, prow, pcol)
+        assert abs(got - float(avg)) <= 1e-12 * float(avg)
+
+
+# ---- cost-model network ------------------------------------------------------------------------
+F, H1, H2 = 5, 32, 32
+
+
+def _rand_params(seed, F=F, H1=H1, H2=H2):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(oracle.mlp_param_count(F, H1, H2)) * 0.3
+
+
+def test_mlp_param_count():
+    assert oracle.mlp_param_count(5, 32, 32) == 32 * 5 + 32 + 32 * 32 + 32 + 32 + 1
+
+
+def test_mlp_forward_exact_network():
+    """A network built to return x_2 exactly: h1 = (relu(x_2), relu(-x_2), 0...),
+    h2 = h1 (identity block), y = h2_0 - h2_1.  A transposed weight or a wrong offset in the
+    parameter layout breaks it."""
+    Fi, A1, A2 = 5, 4, 3
+    p = np.zeros(oracle.mlp_param_count(Fi, A1, A2))
+    W1 = np.zeros((A1, Fi)); W1[0, 2] = 1.0; W1[1, 2] = -1.0; W1[3, 0] = 0.0
+    b1 = np.zeros(A1)
+    W2 = np.zeros((A2, A1)); W2[0, 0] = 1.0; W2[1, 1] = 1.0
+    b2 = np.zeros(A2)
+    w3 = np.array([1.0, -1.0, 0.0])
+    b3 = np.array([0.25])
+    p[:] = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3, b3])
+    X = np.random.default_rng(0).standard_normal((50, Fi))
+    y = oracle.mlp_forward(Fi, A1, A2, p, X)
+    assert np.array_equal(y, X[:, 2] + 0.25)
+
+
+def test_mlp_gradient_vs_central_differences():
+    rng = np.random.default_rng(7)
+    params = _rand_params(7)
+    X = rng.standard_normal((64, F))
+    T = rng.standard_normal(64)
+    loss, g = oracle.mlp_loss_grad(F, H1, H2, params, X, T)
+    y = oracle.mlp_forward(F, H1, H2, params, X)
+    assert abs(loss - np.mean((y - T) ** 2)) <= 1e-12 * loss
+    h = 1e-6
+    idx = rng.choice(params.size, 120, replace=False)
+    for q in idx:
+        pp = params.copy(); pp[q] += h
+        pm = params.copy(); pm[q] -= h
+        fd = (oracle.mlp_loss_grad(F, H1, H2, pp, X, T)[0] - oracle.mlp_loss_grad(F, H1, H2, pm, X, T)[0]) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-6 * max(1.0, abs(g[q])), (q, fd, g[q])
+
+
+def test_adam_closed_form_constant_gradient():
+    """With a constant gradient g the bias-corrected moments are exactly g and g^2, so every step
+    moves a parameter by lr * g / (|g| + eps)."""
+    P = 7
+    g = np.array([1.0, -2.0, 0.5, 3.0, -0.125, 1e-3, 0.0])
+    p = np.zeros(P); m = np.zeros(P); v = np.zeros(P)
+    lr, eps = 0.01, 1e-8
+    for step in range(1, 6):
+        before = p.copy()
+        oracle.adam_step(p, g.copy(), m, v, step, lr=lr, eps=eps)
+        assert np.allclose(before - p, lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-18)
+
+
+def test_adam_decreases_loss():
+    rng = np.random.default_rng(9)
+    params = _rand_params(9)
+    X = rng.standard_normal((256, F))
+    T = np.sin(X[:, 0]) + 0.5 * X[:, 1]
+    m = np.zeros_like(params); v = np.zeros_like(params)
+    first = oracle.mlp_loss_grad(F, H1, H2, params, X, T)[0]
+    for step in range(1, 301):
+        loss, g = oracle.mlp_loss_grad(F, H1, H2, params, X, T)
+        oracle.adam_step(params, g, m, v, step, lr=3e-3)
+    assert loss < 0.2 * first
