@@ -1,0 +1,133 @@
+/*
+ * bsm -- block-sparse matrix multiply with nonuniform, problem-given block sizes, on one
+ * MI355X (gfx950).  C ABI.
+ *
+ * The operation (Calvin & Valeev, "Task-Based Algorithm for Matrix Multiplication", SC15):
+ * SUMMA computes C = A B as a series of rank-k updates C_ij <- A_ik B_kj + C_ij (Sec. 2.1;
+ * Alg. 1's local step C <- alpha A(*,k) B(k,*) + C).  The task-based form over-decomposes the
+ * matrices into arbitrarily sized blocks (Sec. 3.2), splits every update into a block product and
+ * a reduction into C, and lets many k-iterations run at once (multiple issue, Eq. 1).  This
+ * library executes that local multiply for block-sparse operands: for every (i, j) in the
+ * C-shape  Chat_ij = OR_k (Ahat_ik AND Bhat_kj)
+ *     C_ij = alpha * sum_{k : Ahat_ik and Bhat_kj} A_ik B_kj   (+ C_ij when accumulating).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Tilings   int64 vectors of block sizes: rows (M blocks), inner (K blocks, A's columns and B's
+ *           rows), cols (N blocks).  Every size is in [1, 65535].
+ * Shapes    bitmaps, row-major, each row padded to whole 64-bit words: bit (i, j) of an R x C
+ *           shape is bit j % 64 of word i * ceil(C / 64) + j / 64.  Padding bits must be 0.
+ * Tiles     the present blocks, packed in row-major block order (i, then j); each block is
+ *           row-major with leading dimension equal to its own column count.  A block's offset is
+ *           the number of elements of the present blocks before it.  The same layout holds for
+ *           C, whose shape is Chat.
+ * Memory    host arguments are copied before the call returns.  Device buffers (dA, dB, dC) are
+ *           owned by the caller and must stay valid until the work queued on the stream is done.
+ *           dA and dB may be the same buffer (C = A A); dC must not overlap either.
+ * Streams   `stream` is a hipStream_t (NULL = the default stream); work is queued on it and the
+ *           call returns without waiting.  A plan runs on one stream at a time.
+ * Errors    every call returns a bsm_status; nothing is thrown across the ABI.  The text of the
+ *           last failure on the calling thread is available from bsm_last_error().  Device faults
+ *           appear as BSM_E_HIP at the next call that synchronises.
+ */
+#ifndef BSM_H
+#define BSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BSM_OK = 0,
+  BSM_E_INVALID = -1,     /* malformed argument: null pointer, size out of range, padding bit set */
+  BSM_E_MISMATCH = -2,    /* arguments disagree with each other or with the plan */
+  BSM_E_NOMEM = -3,       /* host or device allocation failed, or a stated limit was exceeded */
+  BSM_E_HIP = -4,         /* a HIP runtime call failed (text in bsm_last_error) */
+  BSM_E_UNSUPPORTED = -5, /* no gfx950 device, or an option this build does not provide */
+  BSM_E_STATE = -6        /* call out of order, e.g. timings requested but never recorded */
+} bsm_status;
+
+/* Arithmetic of the block products.  The result is FP64 in every form. */
+typedef enum {
+  BSM_FP64 = 0,  /* FP64 MFMA, FP64 accumulation */
+  BSM_FP32 = 1,  /* operands rounded to FP32, FP32 MFMA within a block product, FP64 across k */
+  BSM_BF16X3 = 2 /* each operand split into three bf16 slices, the six slice products of order
+                    <= 2 on bf16 MFMA with FP32 accumulation within a block product, FP64
+                    across k */
+} bsm_precision;
+
+/* How tasks are ordered (never changes the numbers). */
+typedef enum {
+  BSM_SCHED_FLOPS = 0, /* cost = flop count */
+  BSM_SCHED_MLP = 1    /* cost = the learned model's prediction (set with bsm_plan_set_costmodel) */
+} bsm_sched;
+
+typedef struct {
+  int32_t precision;      /* bsm_precision */
+  int32_t sched;          /* bsm_sched */
+  int64_t k_window;       /* k-iterations in flight at once (multiple issue, Sec. 3.2): 0 = all K */
+  int32_t record_timings; /* 1 = record each task's start/end clock for bsm_plan_timings */
+  int32_t tile;           /* 0 = chosen by the library; otherwise a tile variant id (bsm_tile_*) */
+} bsm_options;
+
+typedef struct {
+  int64_t M, K, N;         /* block counts */
+  int64_t a_blocks, b_blocks, c_blocks;
+  int64_t a_elems, b_elems, c_elems; /* packed buffer sizes in elements */
+  int64_t triples;         /* (i,k,j) with both A_ik and B_kj present */
+  int64_t tasks;           /* work items the GPU executes (C sub-tiles) */
+  double useful_flops;     /* 2 * sum over triples of r_i s_k t_j */
+  int64_t workspace_bytes; /* device memory the plan holds besides the caller's buffers */
+} bsm_plan_info;
+
+typedef struct bsm_plan bsm_plan;
+
+/* Fill opt with the defaults: FP64, flop-count scheduling, all k-iterations in flight,
+ * no timings, library-chosen tiles. */
+void bsm_options_default(bsm_options* opt);
+
+/* Build a plan for C = alpha A B (+ C).  Host-only work: validates the tilings and shapes,
+ * forms the C-shape (the boolean product of the two shapes), the packed offsets, the task list
+ * (each present C block, cut into sub-tiles; its k-list = the k with A_ik and B_kj present, in
+ * ascending order) and the task order.  Device memory is allocated at the first execute.
+ * opt may be NULL (defaults).  Errors: BSM_E_INVALID for a null pointer, a negative count, a
+ * block size outside [1, 65535] or a padding bit set; BSM_E_NOMEM if the host runs out. */
+bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, int64_t K,
+                           const int64_t* inner_sizes, int64_t N, const int64_t* col_sizes,
+                           const uint64_t* a_bits, const uint64_t* b_bits,
+                           const bsm_options* opt);
+
+/* Sizes and counts of a plan (host memory, no device work). */
+bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info);
+
+/* The C-shape Chat as a bitmap (M * ceil(N/64) words, host memory). */
+bsm_status bsm_plan_c_shape(const bsm_plan* plan, uint64_t* c_bits);
+
+/* Packed element offset of every C block, -1 for an absent block (M * N int64, host memory). */
+bsm_status bsm_plan_c_offsets(const bsm_plan* plan, int64_t* c_offsets);
+
+/* C = alpha A B (+ C if accumulate), queued on `stream`.  dA, dB, dC: device pointers to the
+ * packed FP64 tiles (a_elems, b_elems, c_elems elements).  With accumulate = 0 every element of
+ * C is written (present blocks only); with accumulate = 1 C must hold the previous values.
+ * Errors: BSM_E_INVALID for null pointers or overlapping C; BSM_E_UNSUPPORTED without a gfx950
+ * device; BSM_E_HIP if a launch fails. */
+bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
+                       double* dC, int accumulate, void* stream);
+
+/* Release the plan (waits for its device work first).  NULL is accepted. */
+bsm_status bsm_plan_destroy(bsm_plan* plan);
+
+/* Eq. 1: how many SUMMA iterations are issued at once on a P_row x P_col process grid with K
+ * inner blocks: 2 if either grid dimension is below 2, K if both are at least K, else
+ * min(P_row, P_col). */
+int64_t bsm_concurrent_iterations(int64_t p_row, int64_t p_col, int64_t K);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* bsm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSM_H */

@@ -1,0 +1,176 @@
+"""Python binding of the bsm C ABI (argument marshalling only).
+
+Every step of the multiply runs in libbsm.so; torch only provides device memory and the
+stream.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbsm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bsm.h")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+SCHED_FLOPS, SCHED_MLP = 0, 1
+
+OK, E_INVALID, E_MISMATCH, E_NOMEM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_MISMATCH", -3: "E_NOMEM", -4: "E_HIP",
+          -5: "E_UNSUPPORTED", -6: "E_STATE"}
+
+
+class BsmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("sched", ctypes.c_int32),
+                ("k_window", ctypes.c_int64), ("record_timings", ctypes.c_int32),
+                ("tile", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("a_blocks", ctypes.c_int64), ("b_blocks", ctypes.c_int64),
+                ("c_blocks", ctypes.c_int64), ("a_elems", ctypes.c_int64),
+                ("b_elems", ctypes.c_int64), ("c_elems", ctypes.c_int64),
+                ("triples", ctypes.c_int64), ("tasks", ctypes.c_int64),
+                ("useful_flops", ctypes.c_double), ("workspace_bytes", ctypes.c_int64)]
+
+
+_lib: Optional[ctypes.CDLL] = None
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1504_05046_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    L.bsm_last_error.restype = ctypes.c_char_p
+    L.bsm_options_default.argtypes = [ctypes.POINTER(Options)]
+    L.bsm_options_default.restype = None
+    L.bsm_concurrent_iterations.restype = _i64
+    L.bsm_concurrent_iterations.argtypes = [_i64, _i64, _i64]
+    L.bsm_plan_create.argtypes = [ctypes.POINTER(_p), _i64, _p, _i64, _p, _i64, _p, _p, _p,
+                                  ctypes.POINTER(Options)]
+    L.bsm_plan_query.argtypes = [_p, ctypes.POINTER(PlanInfo)]
+    L.bsm_plan_c_shape.argtypes = [_p, _p]
+    L.bsm_plan_c_offsets.argtypes = [_p, _p]
+    L.bsm_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
+    L.bsm_plan_destroy.argtypes = [_p]
+    for name in ("bsm_plan_create", "bsm_plan_query", "bsm_plan_c_shape", "bsm_plan_c_offsets",
+                 "bsm_execute", "bsm_plan_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def declared_symbols() -> list:
+    """Names of the functions include/bsm.h declares."""
+    import re
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(bsm_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(code: int):
+    if code != OK:
+        raise BsmError(code, load().bsm_last_error().decode())
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, tile=0) -> Options:
+    o = Options()
+    load().bsm_options_default(ctypes.byref(o))
+    o.precision, o.sched, o.k_window, o.record_timings, o.tile = precision, sched, k_window, record_timings, tile
+    return o
+
+
+def concurrent_iterations(p_row: int, p_col: int, K: int) -> int:
+    return int(load().bsm_concurrent_iterations(p_row, p_col, K))
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t) -> int:
+    if t is None:
+        return 0
+    return t.data_ptr()
+
+
+class Plan:
+    """A planned block-sparse product (host planning happens in the constructor)."""
+
+    def __init__(self, rows, inner, cols, a_bits, b_bits, opts: Optional[Options] = None, **kw):
+        L = load()
+        self._rows = _arr(rows, np.int64)
+        self._inner = _arr(inner, np.int64)
+        self._cols = _arr(cols, np.int64)
+        self._a = _arr(a_bits, np.uint64)
+        self._b = _arr(b_bits, np.uint64)
+        o = opts if opts is not None else options(**kw)
+        h = _p()
+        _check(L.bsm_plan_create(ctypes.byref(h), self._rows.size, self._rows.ctypes.data,
+                                 self._inner.size, self._inner.ctypes.data, self._cols.size,
+                                 self._cols.ctypes.data, self._a.ctypes.data, self._b.ctypes.data,
+                                 ctypes.byref(o)))
+        self._h = h
+
+    @classmethod
+    def from_problem(cls, p, **kw) -> "Plan":
+        return cls(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), **kw)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> PlanInfo:
+        i = PlanInfo()
+        _check(load().bsm_plan_query(self._h, ctypes.byref(i)))
+        return i
+
+    def c_shape(self) -> np.ndarray:
+        out = np.zeros(self._rows.size * ((self._cols.size + 63) // 64), dtype=np.uint64)
+        _check(load().bsm_plan_c_shape(self._h, out.ctypes.data))
+        return out
+
+    def c_offsets(self) -> np.ndarray:
+        out = np.zeros(self._rows.size * self._cols.size, dtype=np.int64)
+        _check(load().bsm_plan_c_offsets(self._h, out.ctypes.data))
+        return out.reshape(self._rows.size, self._cols.size)
+
+    def execute(self, A, B, C, alpha: float = 1.0, accumulate: bool = False, stream=None):
+        """C = alpha*A*B (+C); A, B, C are FP64 device tensors holding the packed tiles."""
+        _check(load().bsm_execute(self._h, float(alpha), _dev_ptr(A), _dev_ptr(B), _dev_ptr(C),
+                                  int(bool(accumulate)), _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().bsm_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

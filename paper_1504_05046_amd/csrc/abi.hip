@@ -1,0 +1,195 @@
+// C ABI of the library (declared in include/bsm.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/bsm.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace bsm;
+
+static thread_local std::string g_error;
+
+static bsm_status fail(bsm_status code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+static bsm_status hip_fail(hipError_t e, const char* what) {
+  return fail(BSM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct bsm_plan {
+  HostPlan hp;
+  Item* d_items = nullptr;
+  Triple* d_tri = nullptr;
+  int device = -1;
+  bool uploaded = false;
+};
+
+extern "C" {
+
+const char* bsm_last_error(void) { return g_error.c_str(); }
+
+void bsm_options_default(bsm_options* opt) {
+  if (!opt) return;
+  opt->precision = BSM_FP64;
+  opt->sched = BSM_SCHED_FLOPS;
+  opt->k_window = 0;
+  opt->record_timings = 0;
+  opt->tile = 0;
+}
+
+int64_t bsm_concurrent_iterations(int64_t p_row, int64_t p_col, int64_t K) {
+  if (p_row < 2 || p_col < 2) return 2;
+  if (p_row >= K && p_col >= K) return K;
+  return p_row < p_col ? p_row : p_col;
+}
+
+bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, int64_t K,
+                           const int64_t* inner_sizes, int64_t N, const int64_t* col_sizes,
+                           const uint64_t* a_bits, const uint64_t* b_bits,
+                           const bsm_options* opt) {
+  if (!out) return fail(BSM_E_INVALID, "out is null");
+  *out = nullptr;
+  bsm_options o;
+  bsm_options_default(&o);
+  if (opt) o = *opt;
+  PlanConfig cfg;
+  cfg.precision = o.precision;
+  cfg.sched = o.sched;
+  cfg.k_window = o.k_window;
+  cfg.record_timings = o.record_timings;
+  cfg.tile = o.tile;
+  if (const char* s = getenv("BSM_ORDER")) cfg.order = atoi(s);
+  bsm_plan* p = new (std::nothrow) bsm_plan;
+  if (!p) return fail(BSM_E_NOMEM, "host allocation failed");
+  int code = BSM_OK;
+  std::string err;
+  try {
+    err = build_plan(p->hp, M, row_sizes, K, inner_sizes, N, col_sizes, a_bits, b_bits, cfg, &code);
+  } catch (const std::bad_alloc&) {
+    code = BSM_E_NOMEM;
+    err = "host allocation failed while planning";
+  }
+  if (code != BSM_OK) {
+    delete p;
+    return fail(bsm_status(code), err);
+  }
+  *out = p;
+  return BSM_OK;
+}
+
+bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
+  if (!plan || !info) return fail(BSM_E_INVALID, "null argument");
+  const HostPlan& h = plan->hp;
+  info->M = h.M;
+  info->K = h.K;
+  info->N = h.N;
+  info->a_blocks = h.a_blocks;
+  info->b_blocks = h.b_blocks;
+  info->c_blocks = h.c_blocks;
+  info->a_elems = h.a_elems;
+  info->b_elems = h.b_elems;
+  info->c_elems = h.c_elems;
+  info->triples = int64_t(h.tri.size());
+  info->tasks = int64_t(h.items.size());
+  info->useful_flops = h.useful_flops;
+  info->workspace_bytes = int64_t(h.items.size() * sizeof(Item) + h.tri.size() * sizeof(Triple));
+  return BSM_OK;
+}
+
+bsm_status bsm_plan_c_shape(const bsm_plan* plan, uint64_t* c_bits) {
+  if (!plan || (!c_bits && !plan->hp.c_bits.empty())) return fail(BSM_E_INVALID, "null argument");
+  if (!plan->hp.c_bits.empty())
+    std::memcpy(c_bits, plan->hp.c_bits.data(), plan->hp.c_bits.size() * sizeof(uint64_t));
+  return BSM_OK;
+}
+
+bsm_status bsm_plan_c_offsets(const bsm_plan* plan, int64_t* c_offsets) {
+  if (!plan || (!c_offsets && !plan->hp.c_off.empty())) return fail(BSM_E_INVALID, "null argument");
+  if (!plan->hp.c_off.empty())
+    std::memcpy(c_offsets, plan->hp.c_off.data(), plan->hp.c_off.size() * sizeof(int64_t));
+  return BSM_OK;
+}
+
+static bsm_status check_device(int* dev) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return fail(BSM_E_UNSUPPORTED, std::string("no HIP device: ") + hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, *dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(BSM_E_UNSUPPORTED, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+  return BSM_OK;
+}
+
+static bsm_status upload(bsm_plan* p) {
+  if (p->uploaded) return BSM_OK;
+  int dev;
+  bsm_status st = check_device(&dev);
+  if (st != BSM_OK) return st;
+  const HostPlan& h = p->hp;
+  hipError_t e;
+  if (!h.items.empty()) {
+    if ((e = hipMalloc(&p->d_items, h.items.size() * sizeof(Item))) != hipSuccess) return hip_fail(e, "hipMalloc(tasks)");
+    if ((e = hipMemcpy(p->d_items, h.items.data(), h.items.size() * sizeof(Item), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy(tasks)");
+  }
+  if (!h.tri.empty()) {
+    if ((e = hipMalloc(&p->d_tri, h.tri.size() * sizeof(Triple))) != hipSuccess) return hip_fail(e, "hipMalloc(triples)");
+    if ((e = hipMemcpy(p->d_tri, h.tri.data(), h.tri.size() * sizeof(Triple), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy(triples)");
+  }
+  p->device = dev;
+  p->uploaded = true;
+  return BSM_OK;
+}
+
+static bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {
+  if (na <= 0 || nb <= 0) return false;
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
+                       double* dC, int accumulate, void* stream) {
+  if (!plan) return fail(BSM_E_INVALID, "plan is null");
+  const HostPlan& h = plan->hp;
+  if ((h.a_elems > 0 && !dA) || (h.b_elems > 0 && !dB) || (h.c_elems > 0 && !dC))
+    return fail(BSM_E_INVALID, "null tile buffer");
+  if (overlaps(dC, h.c_elems * 8, dA, h.a_elems * 8) || overlaps(dC, h.c_elems * 8, dB, h.b_elems * 8))
+    return fail(BSM_E_INVALID, "C overlaps A or B");
+  if (accumulate != 0 && accumulate != 1) return fail(BSM_E_INVALID, "accumulate must be 0 or 1");
+  if (h.cfg.precision != BSM_FP64) return fail(BSM_E_UNSUPPORTED, "precision form not built yet");
+  bsm_status st = upload(plan);
+  if (st != BSM_OK) return st;
+  if (h.items.empty()) return BSM_OK;
+  XcdMap map;
+  for (int x = 0; x <= kXcds; ++x) map.begin[x] = h.xcd_begin[x];
+  ProductArgs single{dA, dB, dC, alpha};
+  int variant = h.items[0].variant;
+  hipError_t e = launch_f64(variant, h.grid, plan->d_items, plan->d_tri, map, nullptr, single,
+                            accumulate, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return BSM_OK;
+}
+
+bsm_status bsm_plan_destroy(bsm_plan* plan) {
+  if (!plan) return BSM_OK;
+  bsm_status st = BSM_OK;
+  if (plan->uploaded) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize");
+    if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->d_tri) (void)hipFree(plan->d_tri);
+  }
+  delete plan;
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+// Host planner.  Paper Sec. 3.2: the matrices are over-decomposed into problem-given blocks and
+// each rank-k update is split into per-block multiply tasks; Fig. 3 decomposes one iteration so
+// that every task computes a small sub-block of the local result.  Here a task is a sub-tile of
+// one present C block together with that block's whole k-list, so the multiply and the reduction
+// into C are one task (no temporaries, one writer per C element).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "../../include/bsm.h"
+
+namespace bsm {
+
+int64_t words_for(int64_t ncols) { return (ncols + 63) / 64; }
+
+static inline bool test_bit(const uint64_t* bits, int64_t wpr, int64_t i, int64_t j) {
+  return (bits[i * wpr + (j >> 6)] >> (j & 63)) & 1u;
+}
+
+static std::string check_tiling(const char* name, int64_t n, const int64_t* sz) {
+  if (n < 0) return std::string(name) + ": negative block count";
+  if (n > 0 && !sz) return std::string(name) + ": null size vector";
+  for (int64_t i = 0; i < n; ++i)
+    if (sz[i] < 1 || sz[i] > kMaxBlock)
+      return std::string(name) + ": block " + std::to_string(i) + " has size " +
+             std::to_string(sz[i]) + " (allowed 1.." + std::to_string(kMaxBlock) + ")";
+  return "";
+}
+
+static std::string check_bits(const char* name, int64_t r, int64_t c, const uint64_t* bits) {
+  int64_t w = words_for(c);
+  if (r * w == 0) return "";
+  if (!bits) return std::string(name) + ": null bitmap";
+  if (c % 64) {
+    uint64_t pad = ~uint64_t(0) << (c % 64);
+    for (int64_t i = 0; i < r; ++i)
+      if (bits[i * w + w - 1] & pad)
+        return std::string(name) + ": padding bit set in row " + std::to_string(i);
+  }
+  return "";
+}
+
+// Packed offsets of the present blocks (row-major block order); returns the element count.
+static int64_t pack_offsets(int64_t R, int64_t C, const std::vector<int64_t>& rsz,
+                            const std::vector<int64_t>& csz, const std::vector<uint64_t>& bits,
+                            std::vector<int64_t>& off, int64_t& nblocks) {
+  off.assign(size_t(R * C), -1);
+  int64_t w = words_for(C), pos = 0;
+  nblocks = 0;
+  for (int64_t i = 0; i < R; ++i)
+    for (int64_t j = 0; j < C; ++j)
+      if (test_bit(bits.data(), w, i, j)) {
+        off[size_t(i * C + j)] = pos;
+        pos += rsz[size_t(i)] * csz[size_t(j)];
+        ++nblocks;
+      }
+  return pos;
+}
+
+// Cut a block dimension of `m` rows into near-equal pieces of at most `t` rows, each a
+// multiple of 16 rows except where the block ends.
+static void split_dim(int m, int t, std::vector<std::pair<int, int>>& out) {
+  out.clear();
+  int nb16 = (m + 15) / 16, per = t / 16;
+  int pieces = (nb16 + per - 1) / per;
+  int base = nb16 / pieces, extra = nb16 % pieces, off = 0;
+  for (int p = 0; p < pieces; ++p) {
+    int nbl = base + (p < extra ? 1 : 0);
+    int size = std::min(nbl * 16, m - off);
+    out.emplace_back(off, size);
+    off += nbl * 16;
+  }
+}
+
+// Library-chosen tile variant for a C block (largest tile for large blocks).
+static int pick_variant(int m, int n, int forced) {
+  if (forced > 0) return forced - 1;
+  int d = std::max(m, n);
+  (void)d;
+  return 0;
+}
+
+std::vector<double> flop_costs(const HostPlan& p) {
+  std::vector<double> c(p.items.size());
+  for (size_t q = 0; q < p.items.size(); ++q) {
+    const Item& it = p.items[q];
+    double sk = 0;
+    for (uint32_t t = 0; t < it.tri_count; ++t) sk += tri_ks(p.tri[it.tri_begin + t]);
+    c[q] = 2.0 * it.h * it.w * sk;
+  }
+  return c;
+}
+
+void schedule(HostPlan& p, const std::vector<double>& cost) {
+  size_t n = p.items.size();
+  std::vector<size_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::vector<std::vector<size_t>> bins(kXcds);
+  if (p.cfg.order == ORDER_LPT) {
+    // longest processing time first: largest task to the least-loaded XCD, each XCD then runs
+    // its tasks largest first (its 32 CUs pick them up in that order)
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<double> load(kXcds, 0.0);
+    for (size_t q : idx) {
+      int x = int(std::min_element(load.begin(), load.end()) - load.begin());
+      bins[size_t(x)].push_back(q);
+      load[size_t(x)] += cost[q];
+    }
+  } else {
+    // keep the C-block order (sub-tiles of a block and blocks of a block row stay together, so
+    // they share A and B tiles in one XCD's L2) and cut it into kXcds runs of equal cost
+    double total = 0;
+    for (size_t q = 0; q < n; ++q) total += cost[q];
+    double acc = 0;
+    int x = 0;
+    for (size_t q = 0; q < n; ++q) {
+      while (x < kXcds - 1 && acc >= total * (x + 1) / kXcds) ++x;
+      bins[size_t(x)].push_back(q);
+      acc += cost[q];
+    }
+  }
+  std::vector<Item> items;
+  std::vector<double> c2;
+  std::vector<float> f2;
+  items.reserve(n);
+  c2.reserve(n);
+  f2.reserve(p.features.size());
+  int64_t maxc = 0;
+  for (int x = 0; x < kXcds; ++x) {
+    p.xcd_begin[x] = int32_t(items.size());
+    for (size_t q : bins[size_t(x)]) {
+      items.push_back(p.items[q]);
+      c2.push_back(cost[q]);
+      for (int f = 0; f < 5; ++f) f2.push_back(p.features[q * 5 + size_t(f)]);
+    }
+    maxc = std::max<int64_t>(maxc, int64_t(bins[size_t(x)].size()));
+  }
+  p.xcd_begin[kXcds] = int32_t(items.size());
+  p.items.swap(items);
+  p.cost.swap(c2);
+  p.features.swap(f2);
+  p.grid = maxc * kXcds;
+}
+
+std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
+                       const int64_t* inner, int64_t N, const int64_t* cols,
+                       const uint64_t* a_bits, const uint64_t* b_bits, const PlanConfig& cfg,
+                       int* code) {
+  *code = BSM_E_INVALID;
+  std::string e;
+  if (!(e = check_tiling("row_sizes", M, rows)).empty()) return e;
+  if (!(e = check_tiling("inner_sizes", K, inner)).empty()) return e;
+  if (!(e = check_tiling("col_sizes", N, cols)).empty()) return e;
+  if (!(e = check_bits("a_bits", M, K, a_bits)).empty()) return e;
+  if (!(e = check_bits("b_bits", K, N, b_bits)).empty()) return e;
+  if (cfg.precision < 0 || cfg.precision > 2) return "unknown precision";
+  if (cfg.sched < 0 || cfg.sched > 1) return "unknown scheduler";
+  if (cfg.k_window < 0) return "negative k_window";
+  if (cfg.tile < 0 || cfg.tile > kNumVariants) return "unknown tile variant";
+
+  p.cfg = cfg;
+  p.M = M; p.K = K; p.N = N;
+  p.rows.assign(rows, rows + M);
+  p.inner.assign(inner, inner + K);
+  p.cols.assign(cols, cols + N);
+  int64_t wk = words_for(K), wn = words_for(N);
+  p.a_bits.assign(a_bits, a_bits + M * wk);
+  p.b_bits.assign(b_bits, b_bits + K * wn);
+
+  // S1: packed offsets of A and B
+  p.a_elems = pack_offsets(M, K, p.rows, p.inner, p.a_bits, p.a_off, p.a_blocks);
+  p.b_elems = pack_offsets(K, N, p.inner, p.cols, p.b_bits, p.b_off, p.b_blocks);
+
+  // S2: C-shape, row i = OR of B's rows k over A's present (i, k)
+  p.c_bits.assign(size_t(M * wn), 0);
+  for (int64_t i = 0; i < M; ++i) {
+    uint64_t* crow = p.c_bits.data() + i * wn;
+    for (int64_t w = 0; w < wk; ++w) {
+      uint64_t x = p.a_bits[size_t(i * wk + w)];
+      while (x) {
+        int64_t k = w * 64 + __builtin_ctzll(x);
+        x &= x - 1;
+        const uint64_t* brow = p.b_bits.data() + k * wn;
+        for (int64_t v = 0; v < wn; ++v) crow[v] |= brow[v];
+      }
+    }
+  }
+  p.c_elems = pack_offsets(M, N, p.rows, p.cols, p.c_bits, p.c_off, p.c_blocks);
+  if (p.a_elems >= kMaxElems || p.b_elems >= kMaxElems || p.c_elems >= kMaxElems) {
+    *code = BSM_E_NOMEM;
+    return "a tile buffer exceeds 2^48 elements";
+  }
+
+  // S3: k-lists (A row AND B column) and tasks
+  std::vector<uint64_t> bt(size_t(N * wk), 0);  // B's shape transposed: column j's k bits
+  for (int64_t k = 0; k < K; ++k)
+    for (int64_t j = 0; j < N; ++j)
+      if (test_bit(p.b_bits.data(), wn, k, j)) bt[size_t(j * wk + (k >> 6))] |= uint64_t(1) << (k & 63);
+  p.tri.clear();
+  p.items.clear();
+  p.features.clear();
+  p.useful_flops = 0;
+  std::vector<std::pair<int, int>> rs, cs;
+  double ktot = 0;
+  for (int64_t k = 0; k < K; ++k) ktot += double(p.inner[size_t(k)]);
+  for (int64_t i = 0; i < M; ++i) {
+    for (int64_t j = 0; j < N; ++j) {
+      int64_t co = p.c_off[size_t(i * N + j)];
+      if (co < 0) continue;
+      size_t tb = p.tri.size();
+      double sk = 0;
+      for (int64_t w = 0; w < wk; ++w) {
+        uint64_t x = p.a_bits[size_t(i * wk + w)] & bt[size_t(j * wk + w)];
+        while (x) {
+          int64_t k = w * 64 + __builtin_ctzll(x);
+          x &= x - 1;
+          Triple t;
+          t.a = uint64_t(p.a_off[size_t(i * K + k)]) | (uint64_t(p.inner[size_t(k)]) << 48);
+          t.b = uint64_t(p.b_off[size_t(k * N + j)]) | (uint64_t(k) << 48);
+          p.tri.push_back(t);
+          sk += double(p.inner[size_t(k)]);
+        }
+      }
+      size_t tc = p.tri.size() - tb;
+      if (p.tri.size() >= (size_t(1) << 32)) {
+        *code = BSM_E_NOMEM;
+        return "more than 2^32 block triples";
+      }
+      int m = int(p.rows[size_t(i)]), n = int(p.cols[size_t(j)]);
+      p.useful_flops += 2.0 * m * n * sk;
+      int v = pick_variant(m, n, cfg.tile);
+      split_dim(m, kVariants[v].tm, rs);
+      split_dim(n, kVariants[v].tn, cs);
+      for (auto& r : rs)
+        for (auto& c : cs) {
+          Item it;
+          it.c_off = co;
+          it.tri_begin = uint32_t(tb);
+          it.tri_count = uint32_t(tc);
+          it.r0 = uint16_t(r.first);
+          it.h = uint16_t(r.second);
+          it.c0 = uint16_t(c.first);
+          it.w = uint16_t(c.second);
+          it.ldc = uint16_t(n);
+          it.variant = uint16_t(v);
+          it.product = 0;
+          p.items.push_back(it);
+          p.features.push_back(std::log(float(it.h)));
+          p.features.push_back(std::log(float(it.w)));
+          p.features.push_back(std::log(float(std::max(1.0, sk))));
+          p.features.push_back(std::log(float(std::max<size_t>(1, tc))));
+          p.features.push_back(float(ktot > 0 ? sk / ktot : 0.0));
+        }
+    }
+  }
+  // S4: cost and order
+  schedule(p, flop_costs(p));
+  *code = BSM_OK;
+  return "";
+}
+
+}  // namespace bsm

@@ -1,0 +1,63 @@
+// Host planner: validation, C-shape, packing offsets, task expansion and task order.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "types.hpp"
+
+namespace bsm {
+
+// Tile variants: the largest C sub-tile one workgroup computes.  Every variant runs 4 waves of
+// 64 lanes; sub-tiles are cut in multiples of 16 rows/columns.
+struct Variant {
+  int tm, tn;
+};
+constexpr int kNumVariants = 3;
+constexpr Variant kVariants[kNumVariants] = {{128, 128}, {64, 64}, {32, 32}};
+
+enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1 };
+
+struct PlanConfig {
+  int precision = 0;
+  int sched = 0;
+  int64_t k_window = 0;
+  int record_timings = 0;
+  int tile = 0;       // 0 = auto, else variant id + 1
+  int order = ORDER_LOCALITY;
+};
+
+struct HostPlan {
+  PlanConfig cfg;
+  int64_t M = 0, K = 0, N = 0;
+  std::vector<int64_t> rows, inner, cols;
+  std::vector<uint64_t> a_bits, b_bits, c_bits;  // shapes in the ABI word layout
+  std::vector<int64_t> a_off, b_off, c_off;      // block offsets, -1 = absent
+  int64_t a_blocks = 0, b_blocks = 0, c_blocks = 0;
+  int64_t a_elems = 0, b_elems = 0, c_elems = 0;
+  double useful_flops = 0.0;
+
+  std::vector<Triple> tri;       // k-lists of all C blocks, C blocks in row-major order
+  std::vector<Item> items;       // tasks in execution order, grouped by XCD
+  std::vector<double> cost;      // scheduler cost of items[q]
+  std::vector<float> features;   // 5 per item: log h, log w, log sum_k, log #k, density
+  int32_t xcd_begin[kXcds + 1] = {0};
+  int64_t grid = 0;              // workgroups of the launch
+};
+
+int64_t words_for(int64_t ncols);
+
+// Returns "" on success, else an error text; *code receives the status.
+std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
+                       const int64_t* inner, int64_t N, const int64_t* cols,
+                       const uint64_t* a_bits, const uint64_t* b_bits, const PlanConfig& cfg,
+                       int* code);
+
+// Re-order and re-partition the tasks from per-item costs (never changes the task set).
+void schedule(HostPlan& p, const std::vector<double>& cost);
+
+// Flop-count cost of every item.
+std::vector<double> flop_costs(const HostPlan& p);
+
+}  // namespace bsm

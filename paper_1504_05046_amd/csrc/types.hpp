@@ -1,0 +1,51 @@
+// Task and operand descriptors shared by the host planner and the device kernels.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define BSM_HD __host__ __device__
+#else
+#define BSM_HD
+#endif
+
+namespace bsm {
+
+// Limits that the packed descriptors impose.
+constexpr int64_t kMaxBlock = 65535;          // block sizes fit 16 bits
+constexpr int64_t kMaxElems = int64_t(1) << 48;  // tile offsets fit 48 bits
+constexpr int kXcds = 8;                       // MI355X: 8 accelerator dies, each with its own L2
+
+// One (i,k,j) block triple of a C block's k-list: where A_ik and B_kj start and the inner block
+// size.  a = A offset | (s_k << 48);  b = B offset | (k << 48).
+struct Triple {
+  uint64_t a;
+  uint64_t b;
+};
+
+BSM_HD inline int64_t tri_a_off(const Triple& t) { return int64_t(t.a & 0xFFFFFFFFFFFFull); }
+BSM_HD inline int tri_ks(const Triple& t) { return int(t.a >> 48); }
+BSM_HD inline int64_t tri_b_off(const Triple& t) { return int64_t(t.b & 0xFFFFFFFFFFFFull); }
+BSM_HD inline int tri_k(const Triple& t) { return int(t.b >> 48); }
+
+// One task: a sub-tile (rows r0..r0+h, cols c0..c0+w) of the C block at c_off (a block of
+// `ldc` columns), and its k-list tri[tri_begin .. tri_begin + tri_count).
+struct Item {
+  int64_t c_off;
+  uint32_t tri_begin;
+  uint32_t tri_count;
+  uint16_t r0, c0, h, w;
+  uint16_t ldc;       // C block width = width of every B_kj of the k-list
+  uint16_t variant;   // tile variant that executes it
+  uint32_t product;   // index into the batch's operand table (0 for a single product)
+};
+static_assert(sizeof(Item) == 32, "Item layout");
+
+// Operands of one product in a batch.
+struct ProductArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  double alpha;
+};
+
+}  // namespace bsm

@@ -1,0 +1,125 @@
+"""The C ABI without a GPU: the library loads and exports every declared function, and the
+host-side planning (validation, C-shape, packing, counts) agrees with the oracle."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_05046_amd import bsm, gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_library_exports_every_declared_symbol():
+    L = bsm.load()
+    names = bsm.declared_symbols()
+    assert "bsm_plan_create" in names and "bsm_execute" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _problems():
+    yield gen.random_problem(1, 5, 7, 6, 1, 40, 0.4, 0.5)
+    yield gen.random_problem(2, 1, 1, 1, 1, 3, 1.0, 1.0)
+    yield gen.random_problem(3, 9, 70, 3, 1, 9, 0.05, 0.3)   # inner shape wider than one word
+    yield gen.random_problem(4, 66, 3, 130, 1, 5, 0.5, 0.2)
+    yield gen.uniform_1024()
+
+
+@pytest.mark.parametrize("p", list(_problems()), ids=lambda p: p.name)
+def test_plan_matches_oracle_shape_and_layout(p):
+    plan = bsm.Plan.from_problem(p)
+    info = plan.info()
+    c_bits = oracle.shape_product(p.M, p.K, p.N, p.a_bits(), p.b_bits())
+    assert np.array_equal(plan.c_shape(), c_bits)
+    off, total = oracle.block_offsets(p.rows, p.cols, c_bits)
+    assert np.array_equal(plan.c_offsets(), off)
+    assert info.c_elems == total
+    assert info.a_elems == p.a_data.size and info.b_elems == p.b_data.size
+    assert info.a_blocks == int(p.a_mask.sum()) and info.b_blocks == int(p.b_mask.sum())
+    assert info.c_blocks == int(gen.unpack_bits(c_bits, p.M, p.N).sum())
+    assert info.useful_flops == oracle.useful_flops(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits())
+    assert info.triples == int((p.a_mask.astype(np.int64) @ p.b_mask.astype(np.int64)).sum())
+    assert info.tasks >= info.c_blocks
+    plan.close()
+
+
+def test_tasks_cover_each_c_block_once():
+    """Sub-tiles partition every C block: the task count equals the sum over C blocks of the
+    number of pieces the cutting rule gives (at most 128 rows/cols, multiples of 16)."""
+    p = gen.random_problem(7, 6, 4, 5, 1, 300, 0.6, 0.6)
+    info = bsm.Plan.from_problem(p).info()
+    c_mask = gen.unpack_bits(oracle.shape_product(p.M, p.K, p.N, p.a_bits(), p.b_bits()), p.M, p.N)
+    pieces = lambda m: -(-(-(-m // 16)) // 8)
+    want = sum(pieces(int(p.rows[i])) * pieces(int(p.cols[j])) for i, j in zip(*np.nonzero(c_mask)))
+    assert info.tasks == want
+
+
+def test_empty_and_degenerate_plans():
+    # no blocks at all
+    plan = bsm.Plan([], [], [], [], [])
+    i = plan.info()
+    assert (i.M, i.K, i.N, i.c_elems, i.tasks) == (0, 0, 0, 0, 0)
+    # all-absent shapes: C empty
+    p = gen.make_problem("none", 0, [3, 4], [5], [2, 2], np.zeros((2, 1), bool), np.zeros((1, 2), bool))
+    i = bsm.Plan.from_problem(p).info()
+    assert i.c_blocks == 0 and i.tasks == 0 and i.useful_flops == 0
+    # K = 0: nothing to contract, C-shape empty
+    p = gen.make_problem("k0", 0, [3], [], [2], np.zeros((1, 0), bool), np.zeros((0, 1), bool))
+    assert bsm.Plan.from_problem(p).info().c_blocks == 0
+
+
+def _expect(code, fn):
+    with pytest.raises(bsm.BsmError) as ei:
+        fn()
+    assert ei.value.code == code
+    return str(ei.value)
+
+
+def test_invalid_inputs_rejected():
+    ok_bits = gen.pack_bits(np.ones((1, 1), bool))
+    msg = _expect(bsm.E_INVALID, lambda: bsm.Plan([0], [1], [1], ok_bits, ok_bits))
+    assert "row_sizes" in msg
+    _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [70000], [1], ok_bits, ok_bits))
+    _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [-3], ok_bits, ok_bits))
+    # stray padding bit in a 1-column shape
+    bad = np.array([3], dtype=np.uint64)
+    msg = _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], bad, ok_bits))
+    assert "padding" in msg
+    _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], ok_bits, bad))
+    L = bsm.load()
+    h = ctypes.c_void_p()
+    rows = np.array([1], np.int64)
+    assert L.bsm_plan_create(ctypes.byref(h), 1, None, 1, rows.ctypes.data, 1, rows.ctypes.data,
+                             ok_bits.ctypes.data, ok_bits.ctypes.data, None) == bsm.E_INVALID
+    assert L.bsm_plan_create(None, 1, rows.ctypes.data, 1, rows.ctypes.data, 1, rows.ctypes.data,
+                             ok_bits.ctypes.data, ok_bits.ctypes.data, None) == bsm.E_INVALID
+    assert L.bsm_plan_query(None, None) == bsm.E_INVALID
+    _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], ok_bits, ok_bits, k_window=-1))
+    _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], ok_bits, ok_bits, precision=7))
+
+
+def test_execute_argument_errors_need_no_device():
+    p = gen.random_problem(8, 2, 2, 2, 2, 4, 1.0, 1.0)
+    plan = bsm.Plan.from_problem(p)
+    L = bsm.load()
+    # null C
+    assert L.bsm_execute(plan.handle, 1.0, 16, 4096, None, 0, None) == bsm.E_INVALID
+    info = plan.info()
+    # C overlapping A
+    assert L.bsm_execute(plan.handle, 1.0, 4096, 1 << 30, 4096 + 8, 0, None) == bsm.E_INVALID
+    assert L.bsm_execute(plan.handle, 1.0, 4096, 1 << 30, 1 << 40, 3, None) == bsm.E_INVALID
+    assert info.c_elems > 0
+
+
+def test_eq1_matches_golden_table():
+    with open(os.path.join(GOLDEN, "eq1_concurrent_iterations.txt")) as f:
+        rows = [list(map(int, ln.split())) for ln in f if ln.strip() and not ln.startswith("#")]
+    for prow, pcol, K, want in rows:
+        assert bsm.concurrent_iterations(prow, pcol, K) == want
+
+
+def test_destroy_null_is_ok():
+    assert bsm.load().bsm_plan_destroy(None) == bsm.OK

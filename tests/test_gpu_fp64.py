@@ -1,0 +1,179 @@
+"""FP64 GPU path vs the CPU oracle, through the C ABI.
+
+Gates: relative Frobenius error <= 1e-12 per product, every element inside twice the Higham bound
+gamma_n |A||B| (n = the C block's summed inner size), bit-exact C-shape, and bit-exact values for
+integer inputs and for identity blocks."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_05046_amd import bsm, gen
+from tests.helpers import higham_gamma, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(p: gen.Problem, alpha=1.0, C0=None, plan=None, **kw):
+    plan = plan or bsm.Plan.from_problem(p, **kw)
+    info = plan.info()
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(p.a_data).to(dev)
+    B = A if p.b_is_a else torch.from_numpy(p.b_data).to(dev)
+    if C0 is None:
+        C = torch.full((max(1, info.c_elems),), float("nan"), dtype=torch.float64, device=dev)
+    else:
+        C = torch.from_numpy(C0.copy()).to(dev)
+    plan.execute(A, B, C, alpha=alpha, accumulate=C0 is not None)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()[:info.c_elems], plan
+
+
+def _abs_bound(p: gen.Problem, alpha=1.0):
+    """Elementwise 2 gamma_n |alpha| |A||B| with n = the total inner dimension (an upper bound on
+    every C block's summed inner size)."""
+    absab = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), np.abs(p.a_data),
+                        np.abs(p.b_data), abs(alpha))
+    return 2 * higham_gamma(max(1, int(p.inner.sum()))) * absab
+
+
+def check(p: gen.Problem, alpha=1.0, **kw):
+    _say(f"[fp64] {p.name} M={p.M} K={p.K} N={p.N} kw={kw}")
+    got, plan = run_gpu(p, alpha=alpha, **kw)
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data, alpha)
+    assert got.shape == ref.shape
+    assert np.all(np.isfinite(got))
+    err = rel_fro(got, ref)
+    assert err <= 1e-12, err
+    assert np.all(np.abs(got - ref) <= _abs_bound(p, alpha) + 1e-300)
+    return got, ref, plan
+
+
+def test_uniform_1024_full():
+    check(gen.uniform_1024())
+
+
+@pytest.mark.parametrize("sizes", [
+    [1, 3, 15], [16, 17, 31], [33, 63, 64], [65, 127, 128], [129, 255, 256], [1, 256, 17, 100],
+])
+def test_ragged_block_sizes(sizes):
+    rng = np.random.default_rng(len(sizes) * 100 + sizes[0])
+    rows = rng.permutation(sizes)
+    inner = rng.permutation(sizes)
+    cols = rng.permutation(sizes)
+    a_mask = rng.random((len(rows), len(inner))) < 0.7
+    b_mask = rng.random((len(inner), len(cols))) < 0.7
+    a_mask[0, 0] = b_mask[0, 0] = True
+    p = gen.make_problem(f"ragged{sizes}", 7, rows, inner, cols, a_mask, b_mask)
+    check(p)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_nonuniform(seed):
+    check(gen.random_problem(100 + seed, 9, 11, 8, 1, 200, 0.35, 0.4))
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_every_tile_variant(tile):
+    check(gen.random_problem(200 + tile, 6, 7, 6, 1, 300, 0.5, 0.5), tile=tile)
+
+
+@pytest.mark.parametrize("order", ["0", "1"])
+def test_task_orders_bitwise_identical(order, monkeypatch):
+    p = gen.random_problem(300, 8, 8, 8, 20, 200, 0.5, 0.5)
+    monkeypatch.setenv("BSM_ORDER", "0")
+    a, _ = run_gpu(p)
+    monkeypatch.setenv("BSM_ORDER", order)
+    b, _ = run_gpu(p)
+    assert np.array_equal(a, b)
+
+
+def test_integer_inputs_bit_exact():
+    p = gen.integer_problem(400, 7, 9, 6, 1, 150, 0.6, 0.6)
+    got, _ = run_gpu(p)
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    assert np.array_equal(got, ref)
+
+
+def test_identity_blocks_give_b():
+    rng = np.random.default_rng(5)
+    inner = np.array([40, 17, 130, 64, 1])
+    cols = np.array([33, 128, 7])
+    a_mask = np.eye(5, dtype=bool)
+    b_mask = rng.random((5, 3)) < 0.6
+    b_mask[2, 1] = True
+    p = gen.make_problem("id", 5, inner, inner, cols, a_mask, b_mask)
+    p.a_data = np.concatenate([np.eye(int(s)).reshape(-1) for s in inner])
+    got, _ = run_gpu(p)
+    assert np.array_equal(got, p.b_data)
+
+
+def test_alpha_and_accumulate():
+    p = gen.random_problem(500, 5, 6, 5, 10, 140, 0.6, 0.6)
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    c1, plan = run_gpu(p)
+    c2, _ = run_gpu(p, alpha=0.25, plan=plan)
+    assert np.array_equal(c2, 0.25 * c1)
+    C0 = np.random.default_rng(1).standard_normal(c1.size)
+    c3, _ = run_gpu(p, alpha=-1.5, C0=C0, plan=plan)
+    ref3 = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data, -1.5, C=C0)
+    assert rel_fro(c3, ref3) <= 1e-12
+    assert rel_fro(c1, ref) <= 1e-12
+
+
+def test_aliased_c_equals_a_times_a():
+    rows = np.array([10, 25, 40, 60, 25, 10])
+    rng = np.random.default_rng(6)
+    mask = rng.random((6, 6)) < 0.5
+    np.fill_diagonal(mask, True)
+    p = gen.make_problem("alias", 6, rows, rows, rows, mask, mask, b_is_a=True)
+    check(p)
+
+
+def test_empty_products_are_no_ops():
+    p = gen.make_problem("none", 0, [3, 4], [5], [2, 2], np.zeros((2, 1), bool), np.zeros((1, 2), bool))
+    got, _ = run_gpu(p)
+    assert got.size == 0
+
+
+def test_repeat_launches_bitwise_stable():
+    p = gen.random_problem(600, 10, 10, 10, 30, 250, 0.4, 0.4)
+    a, plan = run_gpu(p)
+    for _ in range(3):
+        b, _ = run_gpu(p, plan=plan)
+        assert np.array_equal(a, b)
+
+
+def _sampled_check(p: gen.Problem, nsample: int, seed: int, **kw):
+    """Full-size product on the GPU; a random sample of C blocks recomputed by the oracle."""
+    _say(f"[fp64 sampled] {p.name} M={p.M} K={p.K} N={p.N}")
+    got, plan = run_gpu(p, **kw)
+    off = plan.c_offsets()
+    present = np.argwhere(off >= 0)
+    rng = np.random.default_rng(seed)
+    sel = [tuple(int(v) for v in present[q]) for q in rng.choice(len(present), nsample, replace=False)]
+    blocks, pres = oracle.bsmm_blocks(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data,
+                                      p.b_data, sel)
+    num = den = 0.0
+    for (i, j), blk, pr in zip(sel, blocks, pres):
+        assert pr
+        o = int(off[i, j])
+        g = got[o:o + blk.size].reshape(blk.shape)
+        num += float(np.sum((g - blk) ** 2))
+        den += float(np.sum(blk ** 2))
+    err = (num / den) ** 0.5
+    assert err <= 1e-12, err
+    return got
+
+
+def test_nonuniform_16384_sampled():
+    _sampled_check(gen.nonuniform_16384(), nsample=64, seed=1)
