@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Benchmark: useful TFLOP/s of the block-sparse multiply on one MI355X.
+
+Default workload: N = 16384, row/inner/col block sizes drawn from U{32..256} (last block takes the
+remainder), Bernoulli(0.3) block shapes for A and B, N(0,1) FP64 values, C = A*B.  One step = one
+execution of the planned multiply (every task of every k-iteration, one launch) on inputs that
+already sit in HBM; the plan (host: validation, C-shape, packing, tasks, order) is built once and
+reported separately as plan_ms.
+
+Prints ONE JSON line.  --gpus above 1 is refused: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "useful TFLOP/s, block-sparse MM: FP64 vs split-BF16 at ≤1e-6 rel err, 1 GPU"
+FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 MFMA (datasheet)
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "nonuniform_16384": ("N=16384, block sizes U{32..256} (last = remainder), Bernoulli(0.3) "
+                         "A and B block shapes, N(0,1) FP64 values, C = A*B"),
+    "uniform_1024": "N=1024, 16x16 blocks of 64, Bernoulli(0.5) shapes, U[-1,1] FP64 values",
+}
+
+
+def make_workload(name):
+    from paper_1504_05046_amd import gen
+    if name == "nonuniform_16384":
+        return gen.nonuniform_16384()
+    if name == "uniform_1024":
+        return gen.uniform_1024()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(p, got_c, c_off, target_s: float, seed: int = 12345):
+    """The oracle on the host cores, on a bounded random sample of present C blocks (the same
+    workload); also returns the sample's relative Frobenius error of the GPU result."""
+    import oracle
+    present = np.argwhere(c_off >= 0)
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(len(present))
+    a = p.a_mask.astype(np.float64) * p.inner[None, :]
+    sk = a @ p.b_mask.astype(np.float64)          # summed inner size of each C block's k-list
+    flops_of = lambda ij: 2.0 * p.rows[ij[0]] * p.cols[ij[1]] * sk[ij[0], ij[1]]
+    args = (p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    # calibrate on a small sample, then size the timed sample for ~target_s seconds
+    calib = [tuple(int(v) for v in present[q]) for q in order[:max(1, min(len(order), 2 * oracle.threads()))]]
+    t0 = time.perf_counter()
+    oracle.bsmm_blocks(*args, calib)
+    dt = max(1e-6, time.perf_counter() - t0)
+    rate = sum(flops_of(ij) for ij in calib) / dt
+    budget = rate * target_s
+    sel, fl = [], 0.0
+    for q in order:
+        ij = tuple(int(v) for v in present[q])
+        if fl >= budget and sel:
+            break
+        sel.append(ij)
+        fl += flops_of(ij)
+    t0 = time.perf_counter()
+    blocks, pres = oracle.bsmm_blocks(*args, sel)
+    dt = time.perf_counter() - t0
+    num = den = 0.0
+    for (i, j), blk in zip(sel, blocks):
+        o = int(c_off[i, j])
+        g = got_c[o:o + blk.size].reshape(blk.shape)
+        num += float(np.sum((g - blk) ** 2))
+        den += float(np.sum(blk ** 2))
+    return {
+        "value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+        "sample": f"{len(sel)} random present C blocks of {len(present)} ({fl / 1e9:.1f} GFLOP useful, "
+                  f"{dt:.1f} s), plain FP64 C oracle, OpenMP over C blocks",
+        "seconds": dt,
+    }, (num / den) ** 0.5 if den > 0 else 0.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="nonuniform_16384", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--tile", type=int, default=0, help="0 = library choice, else variant id + 1")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "layout is a design in DESIGN.md, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1504_05046_amd import bsm
+
+    dev = torch.device("cuda:0")
+    p = make_workload(args.workload)
+    t0 = time.perf_counter()
+    plan = bsm.Plan.from_problem(p, tile=args.tile)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+    A = torch.from_numpy(p.a_data).to(dev)
+    B = A if p.b_is_a else torch.from_numpy(p.b_data).to(dev)
+    C = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.execute(A, B, C, stream=stream)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        plan.execute(A, B, C, stream=stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    kern_avg = float(np.mean(kern_ms))
+    flops = info.useful_flops
+    value = flops / (ms_per_step * 1e-3) / 1e12
+    achieved = flops / (kern_avg * 1e-3) / 1e12
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+                   "precision": "fp64", "useful_gflop": round(flops / 1e9, 3),
+                   "c_blocks": info.c_blocks, "triples": info.triples, "tasks": info.tasks,
+                   "plan_ms": round(plan_ms, 1)},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                     "traffic": None, "kernel": "f64_tiles", "kernel_ms": round(kern_avg, 4),
+                     "kernel_ms_sd": round(float(np.std(kern_ms)), 4)},
+    }
+    if not args.no_cpu_baseline:
+        got = C.cpu().numpy()[:info.c_elems]
+        cb, err = cpu_baseline(p, got, plan.c_offsets(), args.cpu_seconds)
+        result["cpu_baseline"] = cb
+        result["sample_rel_err"] = err
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -40,6 +40,7 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             build_library()
         L = ctypes.CDLL(LIB_PATH)
+        L.oracle_threads.restype = ctypes.c_int
         L.oracle_words.restype = _i64
         L.oracle_words.argtypes = [_i64]
         L.oracle_shape_product.argtypes = [_i64, _i64, _i64, _p, _p, _p]
@@ -72,6 +73,11 @@ def _ptr(a: np.ndarray) -> int:
 
 def _c64(a, dtype) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
 
 
 # ---- block-sparse product ---------------------------------------------------------------------

@@ -30,6 +30,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 static int64_t words_of(int64_t ncols) { return (ncols + 63) / 64; }
 
@@ -38,6 +41,15 @@ static int bit_at(const uint64_t* bits, int64_t ncols, int64_t i, int64_t j) {
 }
 
 int64_t oracle_words(int64_t ncols) { return words_of(ncols); }
+
+/* Threads the OpenMP loops below use. */
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* Chat = boolean product of the two shapes, by the definition: a triple loop over (i, j, k). */
 int oracle_shape_product(int64_t M, int64_t K, int64_t N, const uint64_t* a_bits,

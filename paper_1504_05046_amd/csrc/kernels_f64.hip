@@ -15,9 +15,9 @@ namespace bsm {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int TM, int TN>
+template <int TM, int TN, int KC_>
 struct F64Cfg {
-  static constexpr int KC = 16;             // k-chunk staged per step
+  static constexpr int KC = KC_;            // k-chunk staged per step
   static constexpr int ASTR = KC + 1;       // LDS row stride of the A chunk (rows x KC)
   static constexpr int BSTR = TN + 16;      // LDS row stride of the B chunk (KC x cols)
   static constexpr int SLOTS = (TM / 16) * (TN / 16) / 4;  // 16x16 output blocks per wave
@@ -28,41 +28,32 @@ struct F64Cfg {
   static_assert(SLOTS >= 1, "tile too small for 4 waves");
 };
 
-template <int TM, int TN>
-__global__ __launch_bounds__(256) void f64_tiles(const Item* __restrict__ items,
-                                                 const Triple* __restrict__ tri, XcdMap map,
-                                                 const ProductArgs* __restrict__ prods,
-                                                 ProductArgs single, int accumulate) {
-  using C = F64Cfg<TM, TN>;
-  __shared__ double As[2][TM * C::ASTR];
-  __shared__ double Bs[2][C::KC * C::BSTR];
-
-  // XCD-aware task lookup: the hardware deals workgroups round-robin over the 8 XCDs, so
-  // workgroup 8q + x runs on XCD x and takes that XCD's q-th task.
-  const int x = blockIdx.x % kXcds, qx = blockIdx.x / kXcds;
-  const int idx = map.begin[x] + qx;
-  if (idx >= map.begin[x + 1]) return;
-  const Item it = items[idx];
-  const ProductArgs pa = prods ? prods[it.product] : single;
-
+// The part of a task one wave runs when it owns NS of the sub-tile's 16x16 output blocks.
+// Every wave of the workgroup walks the same k-chunks and meets the same barriers; NS is a
+// compile-time constant so that the MFMA stream has no per-block branches.
+template <int TM, int TN, int KC, int NS>
+__device__ __forceinline__ void run_task(const Item& it, const Triple* __restrict__ tri,
+                                         const ProductArgs& pa, int accumulate, int wave,
+                                         double (*As)[TM * F64Cfg<TM, TN, KC>::ASTR],
+                                         double (*Bs)[F64Cfg<TM, TN, KC>::KC * F64Cfg<TM, TN, KC>::BSTR]) {
+  using C = F64Cfg<TM, TN, KC>;
   const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, i16 = lane & 15;
   const int h = it.h, w = it.w, ldc = it.ldc;
-  const int bcn = (w + 15) >> 4, nb = ((h + 15) >> 4) * bcn;
+  const int bcn = (w + 15) >> 4;
 
   // this wave's output blocks q = wave, wave+4, ... (row-major over the sub-tile's 16x16 blocks)
-  int a_u[C::SLOTS], b_u[C::SLOTS];
+  int a_u[NS > 0 ? NS : 1], b_u[NS > 0 ? NS : 1];
 #pragma unroll
-  for (int j = 0; j < C::SLOTS; ++j) {
+  for (int j = 0; j < NS; ++j) {
     int q = wave + 4 * j;
     int rb = q / bcn, cb = q - rb * bcn;
     a_u[j] = 16 * rb * C::ASTR;
     b_u[j] = 16 * cb;
   }
-  d4 acc[C::SLOTS];
+  d4 acc[NS > 0 ? NS : 1];
 #pragma unroll
-  for (int j = 0; j < C::SLOTS; ++j) acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < NS; ++j) acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
 
   // staging assignment: A chunk row-major (16 consecutive threads read one row's 16 k),
   // B chunk row-major (TN consecutive threads read one k-row's columns)
@@ -119,19 +110,24 @@ __global__ __launch_bounds__(256) void f64_tiles(const Item* __restrict__ items,
     const bool more = tn < te;
     if (more) load(tnx, kn);
 
-    const double* as = As[buf] + i16 * C::ASTR + g;
-    const double* bs = Bs[buf] + g * C::BSTR + i16;
+    if (NS > 0) {
+      const double* as = As[buf] + i16 * C::ASTR + g;
+      const double* bs = Bs[buf] + g * C::BSTR + i16;
+      // one 4-deep MFMA step per iteration; steps past the block's end hold only zeros and are
+      // skipped (the condition is the same for the whole wave)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      if (s < nsteps) {
+      for (int s = 0; s < C::KC / 4; ++s) {
+        if (s < nsteps) {
+          double av[NS > 0 ? NS : 1], bv[NS > 0 ? NS : 1];
 #pragma unroll
-        for (int j = 0; j < C::SLOTS; ++j) {
-          if (wave + 4 * j < nb) {
-            double av = as[a_u[j] + 4 * s];
-            double bv = bs[b_u[j] + 4 * s * C::BSTR];
-            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
+          for (int j = 0; j < NS; ++j) {
+            av[j] = as[a_u[j] + 4 * s];
+            bv[j] = bs[b_u[j] + 4 * s * C::BSTR];
           }
+#pragma unroll
+          for (int j = 0; j < NS; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], acc[j], 0, 0, 0);
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     if (more) store(buf ^ 1);
@@ -142,27 +138,67 @@ __global__ __launch_bounds__(256) void f64_tiles(const Item* __restrict__ items,
     tc = tnx;
   }
 
-  // epilogue: lane holds rows g + 4r (r = 0..3) of column i16 of each of its 16x16 blocks
+  // epilogue: on gfx950 the FP64 16x16x4 result puts row g + 4r (r = 0..3), column i16 of a
+  // 16x16 block in register r of lane 16g + i16
   double* Cb = pa.C + it.c_off + int64_t(it.r0) * ldc + it.c0;
   const double alpha = pa.alpha;
 #pragma unroll
-  for (int j = 0; j < C::SLOTS; ++j) {
+  for (int j = 0; j < NS; ++j) {
     int q = wave + 4 * j;
-    if (q < nb) {
-      int rbk = q / bcn, cbk = q - rbk * bcn;
-      int col = 16 * cbk + i16;
+    int rbk = q / bcn, cbk = q - rbk * bcn;
+    int col = 16 * cbk + i16;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int row = 16 * rbk + g + 4 * r;
-        if (row < h && col < w) {
-          double* pc = Cb + int64_t(row) * ldc + col;
-          double v = alpha * acc[j][r];
-          *pc = accumulate ? v + *pc : v;
-        }
+    for (int r = 0; r < 4; ++r) {
+      int row = 16 * rbk + g + 4 * r;
+      if (row < h && col < w) {
+        double* pc = Cb + int64_t(row) * ldc + col;
+        double v = alpha * acc[j][r];
+        *pc = accumulate ? v + *pc : v;
       }
     }
   }
 }
+
+template <int TM, int TN, int KC, int NS>
+__device__ __forceinline__ void dispatch_ns(int ns, const Item& it, const Triple* __restrict__ tri,
+                                            const ProductArgs& pa, int accumulate, int wave,
+                                            double (*As)[TM * F64Cfg<TM, TN, KC>::ASTR],
+                                            double (*Bs)[F64Cfg<TM, TN, KC>::KC * F64Cfg<TM, TN, KC>::BSTR]) {
+  if constexpr (NS > F64Cfg<TM, TN, KC>::SLOTS) {
+    return;
+  } else {
+    if (ns == NS) run_task<TM, TN, KC, NS>(it, tri, pa, accumulate, wave, As, Bs);
+    else dispatch_ns<TM, TN, KC, NS + 1>(ns, it, tri, pa, accumulate, wave, As, Bs);
+  }
+}
+
+template <int TM, int TN, int KC, int OCC>
+__global__ __launch_bounds__(256, OCC) void f64_tiles(const Item* __restrict__ items,
+                                                 const Triple* __restrict__ tri, XcdMap map,
+                                                 const ProductArgs* __restrict__ prods,
+                                                 ProductArgs single, int accumulate) {
+  using C = F64Cfg<TM, TN, KC>;
+  __shared__ double As[2][TM * C::ASTR];
+  __shared__ double Bs[2][C::KC * C::BSTR];
+
+  // XCD-aware task lookup: the hardware deals workgroups round-robin over the 8 XCDs, so
+  // workgroup 8q + x runs on XCD x and takes that XCD's q-th task.
+  const int x = blockIdx.x % kXcds, qx = blockIdx.x / kXcds;
+  const int idx = map.begin[x] + qx;
+  if (idx >= map.begin[x + 1]) return;
+  const Item it = items[idx];
+  const ProductArgs pa = prods ? prods[it.product] : single;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = ((it.h + 15) >> 4) * ((it.w + 15) >> 4);
+  const int ns = nb > wave ? (nb - wave + 3) >> 2 : 0;  // output blocks of this wave
+  dispatch_ns<TM, TN, KC, 0>(ns, it, tri, pa, accumulate, wave, As, Bs);
+}
+
+#define BSM_F64_VARIANT(ID, TM, TN, KC, OCC)                                                 \
+  case ID:                                                                                   \
+    hipLaunchKernelGGL((f64_tiles<TM, TN, KC, OCC>), g, b, 0, stream, items, tri, map, prods, \
+                       single, accumulate);                                                  \
+    break;
 
 hipError_t launch_f64(int variant, int64_t grid, const Item* items, const Triple* tri,
                       const XcdMap& map, const ProductArgs* prods, const ProductArgs& single,
@@ -170,15 +206,14 @@ hipError_t launch_f64(int variant, int64_t grid, const Item* items, const Triple
   if (grid <= 0) return hipSuccess;
   dim3 g(static_cast<uint32_t>(grid)), b(256);
   switch (variant) {
-    case 0:
-      hipLaunchKernelGGL((f64_tiles<128, 128>), g, b, 0, stream, items, tri, map, prods, single, accumulate);
-      break;
-    case 1:
-      hipLaunchKernelGGL((f64_tiles<64, 64>), g, b, 0, stream, items, tri, map, prods, single, accumulate);
-      break;
-    case 2:
-      hipLaunchKernelGGL((f64_tiles<32, 32>), g, b, 0, stream, items, tri, map, prods, single, accumulate);
-      break;
+    BSM_F64_VARIANT(0, 128, 128, 16, 2)
+    BSM_F64_VARIANT(1, 64, 64, 16, 1)
+    BSM_F64_VARIANT(2, 32, 32, 16, 1)
+    BSM_F64_VARIANT(3, 128, 128, 32, 1)
+    BSM_F64_VARIANT(4, 128, 128, 16, 1)
+    BSM_F64_VARIANT(5, 64, 64, 32, 1)
+    BSM_F64_VARIANT(6, 128, 64, 16, 2)
+    BSM_F64_VARIANT(7, 64, 64, 16, 3)
     default:
       return hipErrorInvalidValue;
   }

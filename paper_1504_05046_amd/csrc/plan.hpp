@@ -14,8 +14,9 @@ namespace bsm {
 struct Variant {
   int tm, tn;
 };
-constexpr int kNumVariants = 3;
-constexpr Variant kVariants[kNumVariants] = {{128, 128}, {64, 64}, {32, 32}};
+constexpr int kNumVariants = 8;
+constexpr Variant kVariants[kNumVariants] = {{128, 128}, {64, 64}, {32, 32}, {128, 128},
+                                             {128, 128}, {64, 64},  {128, 64}, {64, 64}};
 
 enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1 };
 
