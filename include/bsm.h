@@ -124,6 +124,11 @@ bsm_status bsm_plan_destroy(bsm_plan* plan);
  * min(P_row, P_col). */
 int64_t bsm_concurrent_iterations(int64_t p_row, int64_t p_col, int64_t K);
 
+/* The tile variants this build provides: variant v (option tile = v + 1) computes C sub-tiles of
+ * at most tm[v] x tn[v] elements per workgroup.  Writes up to `cap` entries (either array may be
+ * NULL) and returns the number of variants. */
+int32_t bsm_tile_variants(int32_t* tm, int32_t* tn, int32_t cap);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* bsm_last_error(void);
 

@@ -61,6 +61,8 @@ def load() -> ctypes.CDLL:
     L.bsm_options_default.restype = None
     L.bsm_concurrent_iterations.restype = _i64
     L.bsm_concurrent_iterations.argtypes = [_i64, _i64, _i64]
+    L.bsm_tile_variants.restype = ctypes.c_int32
+    L.bsm_tile_variants.argtypes = [_p, _p, ctypes.c_int32]
     L.bsm_plan_create.argtypes = [ctypes.POINTER(_p), _i64, _p, _i64, _p, _i64, _p, _p, _p,
                                   ctypes.POINTER(Options)]
     L.bsm_plan_query.argtypes = [_p, ctypes.POINTER(PlanInfo)]
@@ -101,6 +103,16 @@ def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, til
 
 def concurrent_iterations(p_row: int, p_col: int, K: int) -> int:
     return int(load().bsm_concurrent_iterations(p_row, p_col, K))
+
+
+def tile_variants():
+    """[(tm, tn)] of every tile variant (option tile = index + 1)."""
+    L = load()
+    n = int(L.bsm_tile_variants(None, None, 0))
+    tm = np.zeros(n, np.int32)
+    tn = np.zeros(n, np.int32)
+    L.bsm_tile_variants(tm.ctypes.data, tn.ctypes.data, n)
+    return list(zip(tm.tolist(), tn.tolist()))
 
 
 def _stream_handle(stream) -> Optional[int]:

@@ -43,6 +43,14 @@ void bsm_options_default(bsm_options* opt) {
   opt->tile = 0;
 }
 
+int32_t bsm_tile_variants(int32_t* tm, int32_t* tn, int32_t cap) {
+  for (int v = 0; v < kNumVariants && v < cap; ++v) {
+    if (tm) tm[v] = kVariants[v].tm;
+    if (tn) tn[v] = kVariants[v].tn;
+  }
+  return kNumVariants;
+}
+
 int64_t bsm_concurrent_iterations(int64_t p_row, int64_t p_col, int64_t K) {
   if (p_row < 2 || p_col < 2) return 2;
   if (p_row >= K && p_col >= K) return K;

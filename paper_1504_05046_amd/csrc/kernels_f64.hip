@@ -15,28 +15,37 @@ namespace bsm {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int TM, int TN, int KC_>
+// Fourth word of a raw (stride 0) buffer descriptor on gfx9-family targets: 32-bit data format,
+// no swizzle; loads past num_records return 0.
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr uint32_t kOutOfRange = 0x7FFFFFF8u;
+
+template <int TM, int TN, int KC_, int NW_>
 struct F64Cfg {
   static constexpr int KC = KC_;            // k-chunk staged per step
-  static constexpr int ASTR = KC + 1;       // LDS row stride of the A chunk (rows x KC)
-  static constexpr int BSTR = TN + 16;      // LDS row stride of the B chunk (KC x cols)
-  static constexpr int SLOTS = (TM / 16) * (TN / 16) / 4;  // 16x16 output blocks per wave
-  static constexpr int ALD = TM / 16;       // A elements each thread stages per chunk
-  static constexpr int BK = 256 / TN;       // B rows covered by one pass of 256 threads
+  static constexpr int NW = NW_;            // waves per workgroup
+  static constexpr int NT = 64 * NW;        // threads per workgroup
+  // LDS row strides (doubles), padded so that a half-wave's fragment reads hit distinct banks
+  static constexpr int ASTR = KC == 16 ? KC + 1 : KC + 2;  // A chunk: TM rows x KC
+  static constexpr int BSTR = TN + 16;                     // B chunk: KC rows x TN
+  static constexpr int SLOTS = ((TM / 16) * (TN / 16) + NW - 1) / NW;  // 16x16 blocks per wave
+  static constexpr int ARP = NT / KC;       // A rows staged per pass (KC threads per row)
+  static constexpr int ALD = TM / ARP;      // A elements each thread stages per chunk
+  static constexpr int BK = NT / TN;        // B k-rows staged per pass (TN threads per row)
   static constexpr int BLD = KC / BK;       // B elements each thread stages per chunk
-  static_assert(TN <= 256 && 256 % TN == 0 && KC % BK == 0, "tile shape");
-  static_assert(SLOTS >= 1, "tile too small for 4 waves");
+  static_assert(KC % 16 == 0 && NT % KC == 0 && TM % ARP == 0, "A staging shape");
+  static_assert(TN <= NT && NT % TN == 0 && KC % BK == 0, "B staging shape");
 };
 
 // The part of a task one wave runs when it owns NS of the sub-tile's 16x16 output blocks.
 // Every wave of the workgroup walks the same k-chunks and meets the same barriers; NS is a
 // compile-time constant so that the MFMA stream has no per-block branches.
-template <int TM, int TN, int KC, int NS>
+template <int TM, int TN, int KC, int NW, int NS>
 __device__ __forceinline__ void run_task(const Item& it, const Triple* __restrict__ tri,
                                          const ProductArgs& pa, int accumulate, int wave,
-                                         double (*As)[TM * F64Cfg<TM, TN, KC>::ASTR],
-                                         double (*Bs)[F64Cfg<TM, TN, KC>::KC * F64Cfg<TM, TN, KC>::BSTR]) {
-  using C = F64Cfg<TM, TN, KC>;
+                                         double (*As)[TM * F64Cfg<TM, TN, KC, NW>::ASTR],
+                                         double (*Bs)[F64Cfg<TM, TN, KC, NW>::KC * F64Cfg<TM, TN, KC, NW>::BSTR]) {
+  using C = F64Cfg<TM, TN, KC, NW>;
   const int tid = threadIdx.x, lane = tid & 63;
   const int g = lane >> 4, i16 = lane & 15;
   const int h = it.h, w = it.w, ldc = it.ldc;
@@ -46,7 +55,7 @@ __device__ __forceinline__ void run_task(const Item& it, const Triple* __restric
   int a_u[NS > 0 ? NS : 1], b_u[NS > 0 ? NS : 1];
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    int q = wave + 4 * j;
+    int q = wave + NW * j;
     int rb = q / bcn, cb = q - rb * bcn;
     a_u[j] = 16 * rb * C::ASTR;
     b_u[j] = 16 * cb;
@@ -57,29 +66,37 @@ __device__ __forceinline__ void run_task(const Item& it, const Triple* __restric
 
   // staging assignment: A chunk row-major (16 consecutive threads read one row's 16 k),
   // B chunk row-major (TN consecutive threads read one k-row's columns)
-  const int ka = tid & 15, ra0 = tid >> 4;
+  const int ka = tid % KC, ra0 = tid / KC;
   const int cbl = tid % TN, kb0 = tid / TN;
   double ra[C::ALD], rb[C::BLD];
 
+  // Staging loads go through buffer descriptors: a load whose offset lies past num_records
+  // returns 0 instead of touching memory.  A's descriptor ends at row h of the sub-tile, so rows
+  // beyond it read 0; the k-tail (k >= s_k would wrap into the next row) is sent out of range
+  // explicitly.  B's descriptor ends at the last element of the sub-tile's columns, so k-rows
+  // beyond s_k read 0; columns beyond w read finite neighbours that only feed output columns the
+  // epilogue discards.
   auto load = [&](const Triple& t, int kk) {
     const int ks = tri_ks(t);
-    const double* Ab = pa.A + tri_a_off(t) + int64_t(it.r0) * ks + kk;
-    const double* Bb = pa.B + tri_b_off(t) + int64_t(kk) * ldc + it.c0;
+    const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(pa.A + tri_a_off(t) + int64_t(it.r0) * ks), (short)0, h * ks * 8, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t br = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(pa.B + tri_b_off(t) + it.c0), (short)0, ((ks - 1) * ldc + w) * 8, kRsrcWord3);
     const bool kin = kk + ka < ks;
 #pragma unroll
     for (int p = 0; p < C::ALD; ++p) {
-      int row = ra0 + 16 * p;
-      ra[p] = (kin && row < h) ? Ab[int64_t(row) * ks + ka] : 0.0;
+      const uint32_t off = kin ? uint32_t(((ra0 + C::ARP * p) * ks + kk + ka) * 8) : kOutOfRange;
+      ra[p] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ar, off, 0, 0));
     }
 #pragma unroll
     for (int p = 0; p < C::BLD; ++p) {
-      int kr = kb0 + C::BK * p;
-      rb[p] = (cbl < w && kk + kr < ks) ? Bb[int64_t(kr) * ldc + cbl] : 0.0;
+      const uint32_t off = uint32_t(((kk + kb0 + C::BK * p) * ldc + cbl) * 8);
+      rb[p] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(br, off, 0, 0));
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int p = 0; p < C::ALD; ++p) As[buf][(ra0 + 16 * p) * C::ASTR + ka] = ra[p];
+    for (int p = 0; p < C::ALD; ++p) As[buf][(ra0 + C::ARP * p) * C::ASTR + ka] = ra[p];
 #pragma unroll
     for (int p = 0; p < C::BLD; ++p) Bs[buf][(kb0 + C::BK * p) * C::BSTR + cbl] = rb[p];
   };
@@ -118,14 +135,24 @@ __device__ __forceinline__ void run_task(const Item& it, const Triple* __restric
 #pragma unroll
       for (int s = 0; s < C::KC / 4; ++s) {
         if (s < nsteps) {
-          double av[NS > 0 ? NS : 1], bv[NS > 0 ? NS : 1];
+          // fragments are read in groups of up to 8 blocks to bound register use
 #pragma unroll
-          for (int j = 0; j < NS; ++j) {
-            av[j] = as[a_u[j] + 4 * s];
-            bv[j] = bs[b_u[j] + 4 * s * C::BSTR];
+          for (int j0 = 0; j0 < NS; j0 += 8) {
+            constexpr int G = NS < 8 ? NS : 8;
+            double av[G > 0 ? G : 1], bv[G > 0 ? G : 1];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+              if (j0 + j < NS) {
+                av[j] = as[a_u[j0 + j] + 4 * s];
+                bv[j] = bs[b_u[j0 + j] + 4 * s * C::BSTR];
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+              if (j0 + j < NS)
+                acc[j0 + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], acc[j0 + j], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
           }
-#pragma unroll
-          for (int j = 0; j < NS; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], acc[j], 0, 0, 0);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -144,7 +171,7 @@ __device__ __forceinline__ void run_task(const Item& it, const Triple* __restric
   const double alpha = pa.alpha;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    int q = wave + 4 * j;
+    int q = wave + NW * j;
     int rbk = q / bcn, cbk = q - rbk * bcn;
     int col = 16 * cbk + i16;
 #pragma unroll
@@ -159,25 +186,25 @@ __device__ __forceinline__ void run_task(const Item& it, const Triple* __restric
   }
 }
 
-template <int TM, int TN, int KC, int NS>
+template <int TM, int TN, int KC, int NW, int NS>
 __device__ __forceinline__ void dispatch_ns(int ns, const Item& it, const Triple* __restrict__ tri,
                                             const ProductArgs& pa, int accumulate, int wave,
-                                            double (*As)[TM * F64Cfg<TM, TN, KC>::ASTR],
-                                            double (*Bs)[F64Cfg<TM, TN, KC>::KC * F64Cfg<TM, TN, KC>::BSTR]) {
-  if constexpr (NS > F64Cfg<TM, TN, KC>::SLOTS) {
+                                            double (*As)[TM * F64Cfg<TM, TN, KC, NW>::ASTR],
+                                            double (*Bs)[F64Cfg<TM, TN, KC, NW>::KC * F64Cfg<TM, TN, KC, NW>::BSTR]) {
+  if constexpr (NS > F64Cfg<TM, TN, KC, NW>::SLOTS) {
     return;
   } else {
-    if (ns == NS) run_task<TM, TN, KC, NS>(it, tri, pa, accumulate, wave, As, Bs);
-    else dispatch_ns<TM, TN, KC, NS + 1>(ns, it, tri, pa, accumulate, wave, As, Bs);
+    if (ns == NS) run_task<TM, TN, KC, NW, NS>(it, tri, pa, accumulate, wave, As, Bs);
+    else dispatch_ns<TM, TN, KC, NW, NS + 1>(ns, it, tri, pa, accumulate, wave, As, Bs);
   }
 }
 
-template <int TM, int TN, int KC, int OCC>
-__global__ __launch_bounds__(256, OCC) void f64_tiles(const Item* __restrict__ items,
+template <int TM, int TN, int KC, int NW, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC) void f64_tiles(const Item* __restrict__ items,
                                                  const Triple* __restrict__ tri, XcdMap map,
                                                  const ProductArgs* __restrict__ prods,
                                                  ProductArgs single, int accumulate) {
-  using C = F64Cfg<TM, TN, KC>;
+  using C = F64Cfg<TM, TN, KC, NW>;
   __shared__ double As[2][TM * C::ASTR];
   __shared__ double Bs[2][C::KC * C::BSTR];
 
@@ -190,30 +217,23 @@ __global__ __launch_bounds__(256, OCC) void f64_tiles(const Item* __restrict__ i
   const ProductArgs pa = prods ? prods[it.product] : single;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nb = ((it.h + 15) >> 4) * ((it.w + 15) >> 4);
-  const int ns = nb > wave ? (nb - wave + 3) >> 2 : 0;  // output blocks of this wave
-  dispatch_ns<TM, TN, KC, 0>(ns, it, tri, pa, accumulate, wave, As, Bs);
+  const int ns = nb > wave ? (nb - wave + NW - 1) / NW : 0;  // output blocks of this wave
+  dispatch_ns<TM, TN, KC, NW, 0>(ns, it, tri, pa, accumulate, wave, As, Bs);
 }
 
-#define BSM_F64_VARIANT(ID, TM, TN, KC, OCC)                                                 \
+#define BSM_F64_LAUNCH(ID, TM, TN, KC, NW, OCC)                                              \
   case ID:                                                                                   \
-    hipLaunchKernelGGL((f64_tiles<TM, TN, KC, OCC>), g, b, 0, stream, items, tri, map, prods, \
-                       single, accumulate);                                                  \
+    hipLaunchKernelGGL((f64_tiles<TM, TN, KC, NW, OCC>), dim3(grid32), dim3(64 * NW), 0, stream, \
+                       items, tri, map, prods, single, accumulate);                          \
     break;
 
 hipError_t launch_f64(int variant, int64_t grid, const Item* items, const Triple* tri,
                       const XcdMap& map, const ProductArgs* prods, const ProductArgs& single,
                       int accumulate, hipStream_t stream) {
   if (grid <= 0) return hipSuccess;
-  dim3 g(static_cast<uint32_t>(grid)), b(256);
+  const uint32_t grid32 = static_cast<uint32_t>(grid);
   switch (variant) {
-    BSM_F64_VARIANT(0, 128, 128, 16, 2)
-    BSM_F64_VARIANT(1, 64, 64, 16, 1)
-    BSM_F64_VARIANT(2, 32, 32, 16, 1)
-    BSM_F64_VARIANT(3, 128, 128, 32, 1)
-    BSM_F64_VARIANT(4, 128, 128, 16, 1)
-    BSM_F64_VARIANT(5, 64, 64, 32, 1)
-    BSM_F64_VARIANT(6, 128, 64, 16, 2)
-    BSM_F64_VARIANT(7, 64, 64, 16, 3)
+    BSM_F64_VARIANTS(BSM_F64_LAUNCH)
     default:
       return hipErrorInvalidValue;
   }

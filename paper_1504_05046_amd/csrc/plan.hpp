@@ -9,14 +9,14 @@
 
 namespace bsm {
 
-// Tile variants: the largest C sub-tile one workgroup computes.  Every variant runs 4 waves of
-// 64 lanes; sub-tiles are cut in multiples of 16 rows/columns.
+// Tile variants (see BSM_F64_VARIANTS): the largest C sub-tile one workgroup computes.
 struct Variant {
-  int tm, tn;
+  int tm, tn, nw;
 };
-constexpr int kNumVariants = 8;
-constexpr Variant kVariants[kNumVariants] = {{128, 128}, {64, 64}, {32, 32}, {128, 128},
-                                             {128, 128}, {64, 64},  {128, 64}, {64, 64}};
+#define BSM_VARIANT_ROW(ID, TM, TN, KC, NW, OCC) {TM, TN, NW},
+constexpr Variant kVariants[] = {BSM_F64_VARIANTS(BSM_VARIANT_ROW)};
+#undef BSM_VARIANT_ROW
+constexpr int kNumVariants = int(sizeof(kVariants) / sizeof(kVariants[0]));
 
 enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1 };
 

@@ -15,6 +15,21 @@ constexpr int64_t kMaxBlock = 65535;          // block sizes fit 16 bits
 constexpr int64_t kMaxElems = int64_t(1) << 48;  // tile offsets fit 48 bits
 constexpr int kXcds = 8;                       // MI355X: 8 accelerator dies, each with its own L2
 
+// FP64 tile variants: X(id, TM, TN, KC, NW, OCC) = largest C sub-tile TM x TN of one workgroup,
+// k-chunk KC staged through LDS per step, NW waves per workgroup, OCC waves per SIMD the register
+// allocator must leave room for (512 / OCC registers per lane).  Sub-tiles are cut in multiples of 16 rows/columns.
+#define BSM_F64_VARIANTS(X)     \
+  X(0, 128, 128, 16, 4, 2)      \
+  X(1, 64, 64, 16, 4, 1)        \
+  X(2, 32, 32, 16, 4, 1)        \
+  X(3, 128, 128, 32, 4, 1)      \
+  X(4, 128, 128, 16, 4, 1)      \
+  X(5, 64, 64, 32, 4, 1)        \
+  X(6, 128, 64, 16, 4, 2)       \
+  X(7, 64, 64, 16, 4, 3)        \
+  X(8, 128, 128, 16, 8, 4)      \
+  X(9, 128, 64, 16, 4, 3)
+
 // One (i,k,j) block triple of a C block's k-list: where A_ik and B_kj start and the inner block
 // size.  a = A offset | (s_k << 48);  b = B offset | (k << 48).
 struct Triple {

@@ -121,5 +121,16 @@ def test_eq1_matches_golden_table():
         assert bsm.concurrent_iterations(prow, pcol, K) == want
 
 
+def test_tile_variants_listed():
+    v = bsm.tile_variants()
+    assert len(v) >= 3
+    for tm, tn in v:
+        assert tm % 16 == 0 and tn % 16 == 0 and 16 <= tm <= 256 and 16 <= tn <= 256
+    p = gen.random_problem(9, 3, 3, 3, 1, 300, 1.0, 1.0)
+    for t in range(1, len(v) + 1):
+        bsm.Plan.from_problem(p, tile=t).close()
+    _expect(bsm.E_INVALID, lambda: bsm.Plan.from_problem(p, tile=len(v) + 1))
+
+
 def test_destroy_null_is_ok():
     assert bsm.load().bsm_plan_destroy(None) == bsm.OK

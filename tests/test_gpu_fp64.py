@@ -82,9 +82,13 @@ def test_random_nonuniform(seed):
     check(gen.random_problem(100 + seed, 9, 11, 8, 1, 200, 0.35, 0.4))
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", range(1, len(bsm.tile_variants()) + 1))
 def test_every_tile_variant(tile):
     check(gen.random_problem(200 + tile, 6, 7, 6, 1, 300, 0.5, 0.5), tile=tile)
+    p = gen.integer_problem(250 + tile, 5, 6, 5, 1, 200, 0.6, 0.6)
+    got, _ = run_gpu(p, tile=tile)
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    assert np.array_equal(got, ref)
 
 
 @pytest.mark.parametrize("order", ["0", "1"])
