@@ -80,6 +80,7 @@ typedef struct {
   int64_t tasks;           /* work items the GPU executes (C sub-tiles) */
   double useful_flops;     /* 2 * sum over triples of r_i s_k t_j */
   int64_t workspace_bytes; /* device memory the plan holds besides the caller's buffers */
+  int64_t k_windows;       /* launches per execute: ceil(K / k_window) */
 } bsm_plan_info;
 
 typedef struct bsm_plan bsm_plan;
@@ -115,6 +116,15 @@ bsm_status bsm_plan_c_offsets(const bsm_plan* plan, int64_t* c_offsets);
  * device; BSM_E_HIP if a launch fails. */
 bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
                        double* dC, int accumulate, void* stream);
+
+/* Per-task timings of the last execute of a plan created with record_timings = 1 (waits for
+ * `stream`).  n must equal the plan's task count.  features (n x 5 floats, host; may be NULL)
+ * receives each task's cost-model features: log h, log w, log (summed inner size of its k-list),
+ * log (number of k-list blocks), k-list density (summed inner size / total inner size);
+ * seconds (n floats, host; may be NULL) the task's duration on the device clock.
+ * Errors: BSM_E_STATE if no timed execute has run, BSM_E_MISMATCH for a wrong n. */
+bsm_status bsm_plan_timings(bsm_plan* plan, float* features, float* seconds, int64_t n,
+                            void* stream);
 
 /* Release the plan (waits for its device work first).  NULL is accepted. */
 bsm_status bsm_plan_destroy(bsm_plan* plan);

@@ -41,7 +41,8 @@ class PlanInfo(ctypes.Structure):
                 ("c_blocks", ctypes.c_int64), ("a_elems", ctypes.c_int64),
                 ("b_elems", ctypes.c_int64), ("c_elems", ctypes.c_int64),
                 ("triples", ctypes.c_int64), ("tasks", ctypes.c_int64),
-                ("useful_flops", ctypes.c_double), ("workspace_bytes", ctypes.c_int64)]
+                ("useful_flops", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
+                ("k_windows", ctypes.c_int64)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -70,8 +71,9 @@ def load() -> ctypes.CDLL:
     L.bsm_plan_c_offsets.argtypes = [_p, _p]
     L.bsm_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
     L.bsm_plan_destroy.argtypes = [_p]
+    L.bsm_plan_timings.argtypes = [_p, _p, _p, _i64, _p]
     for name in ("bsm_plan_create", "bsm_plan_query", "bsm_plan_c_shape", "bsm_plan_c_offsets",
-                 "bsm_execute", "bsm_plan_destroy"):
+                 "bsm_execute", "bsm_plan_destroy", "bsm_plan_timings"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -175,6 +177,14 @@ class Plan:
         """C = alpha*A*B (+C); A, B, C are FP64 device tensors holding the packed tiles."""
         _check(load().bsm_execute(self._h, float(alpha), _dev_ptr(A), _dev_ptr(B), _dev_ptr(C),
                                   int(bool(accumulate)), _stream_handle(stream)))
+
+    def timings(self, stream=None):
+        """(features[tasks, 5], seconds[tasks]) of the last timed execute."""
+        n = self.info().tasks
+        f = np.zeros((n, 5), dtype=np.float32)
+        t = np.zeros(n, dtype=np.float32)
+        _check(load().bsm_plan_timings(self._h, f.ctypes.data, t.ctypes.data, n, _stream_handle(stream)))
+        return f, t
 
     def close(self):
         if getattr(self, "_h", None):

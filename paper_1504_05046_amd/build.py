@@ -11,6 +11,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -39,19 +40,22 @@ def build(verbose: bool = False) -> str:
     if os.path.isdir(BUILD):
         shutil.rmtree(BUILD)
     os.makedirs(BUILD)
-    objs = []
+    jobs = []
     for src in sorted(glob.glob(os.path.join(CSRC, "*.cpp"))):
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-        out = _run(["g++"] + CXX_FLAGS + ["-c", src, "-o", obj])
-        if verbose and out:
-            print(out)
-        objs.append(obj)
+        jobs.append((["g++"] + CXX_FLAGS + ["-c", src, "-o", obj], obj))
     for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-        out = _run([HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj])
-        if verbose and out:
-            print(out)
-        objs.append(obj)
+        jobs.append(([HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj], obj))
+    # translation units compile independently (the tile kernels dominate; one per form)
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        outs = list(ex.map(lambda j: _run(j[0]), jobs))
+    if verbose:
+        for out in outs:
+            if out:
+                print(out)
+    objs = [j[1] for j in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs)
     os.replace(tmp, LIB)

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/bsm.h"
 #include "kernels.hpp"
@@ -26,8 +27,13 @@ struct bsm_plan {
   HostPlan hp;
   Item* d_items = nullptr;
   Triple* d_tri = nullptr;
+  void* d_opA = nullptr;         // converted operands of the reduced-precision forms
+  void* d_opB = nullptr;
+  double* d_partial = nullptr;   // raw sums between k-windows (laid out like C)
+  uint64_t* d_stamps = nullptr;  // per-task start/end clocks
   int device = -1;
   bool uploaded = false;
+  bool timed = false;            // an execute has recorded timings
 };
 
 extern "C" {
@@ -73,6 +79,7 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
   cfg.record_timings = o.record_timings;
   cfg.tile = o.tile;
   if (const char* s = getenv("BSM_ORDER")) cfg.order = atoi(s);
+  if (const char* s = getenv("BSM_CUT")) cfg.cut_search = atoi(s) != 0;
   bsm_plan* p = new (std::nothrow) bsm_plan;
   if (!p) return fail(BSM_E_NOMEM, "host allocation failed");
   int code = BSM_OK;
@@ -106,7 +113,12 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   info->triples = int64_t(h.tri.size());
   info->tasks = int64_t(h.items.size());
   info->useful_flops = h.useful_flops;
-  info->workspace_bytes = int64_t(h.items.size() * sizeof(Item) + h.tri.size() * sizeof(Triple));
+  int64_t ws = int64_t(h.items.size() * sizeof(Item) + h.tri.size() * sizeof(Triple));
+  if (h.cfg.precision == BSM_FP32) ws += (h.a_elems + h.b_elems) * 4;
+  if (h.windows > 1) ws += h.c_elems * 8;
+  if (h.cfg.record_timings) ws += int64_t(h.items.size()) * 16;
+  info->workspace_bytes = ws;
+  info->k_windows = h.windows;
   return BSM_OK;
 }
 
@@ -152,6 +164,17 @@ static bsm_status upload(bsm_plan* p) {
     if ((e = hipMemcpy(p->d_tri, h.tri.data(), h.tri.size() * sizeof(Triple), hipMemcpyHostToDevice)) != hipSuccess)
       return hip_fail(e, "hipMemcpy(triples)");
   }
+  const int64_t ne_a = h.a_elems, ne_b = h.b_elems;
+  if (h.cfg.precision == BSM_FP32) {
+    if (ne_a > 0 && (e = hipMalloc(&p->d_opA, size_t(ne_a) * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(A fp32)");
+    if (ne_b > 0 && (e = hipMalloc(&p->d_opB, size_t(ne_b) * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(B fp32)");
+  }
+  if (h.windows > 1 && h.c_elems > 0) {
+    if ((e = hipMalloc(&p->d_partial, size_t(h.c_elems) * 8)) != hipSuccess) return hip_fail(e, "hipMalloc(partial)");
+  }
+  if (h.cfg.record_timings && !h.items.empty()) {
+    if ((e = hipMalloc(&p->d_stamps, h.items.size() * 16)) != hipSuccess) return hip_fail(e, "hipMalloc(stamps)");
+  }
   p->device = dev;
   p->uploaded = true;
   return BSM_OK;
@@ -173,17 +196,71 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
   if (overlaps(dC, h.c_elems * 8, dA, h.a_elems * 8) || overlaps(dC, h.c_elems * 8, dB, h.b_elems * 8))
     return fail(BSM_E_INVALID, "C overlaps A or B");
   if (accumulate != 0 && accumulate != 1) return fail(BSM_E_INVALID, "accumulate must be 0 or 1");
-  if (h.cfg.precision != BSM_FP64) return fail(BSM_E_UNSUPPORTED, "precision form not built yet");
+  if (h.cfg.precision == BSM_BF16X3) return fail(BSM_E_UNSUPPORTED, "precision form not built yet");
   bsm_status st = upload(plan);
   if (st != BSM_OK) return st;
   if (h.items.empty()) return BSM_OK;
-  XcdMap map;
-  for (int x = 0; x <= kXcds; ++x) map.begin[x] = h.xcd_begin[x];
-  ProductArgs single{dA, dB, dC, alpha};
-  int variant = h.items[0].variant;
-  hipError_t e = launch_f64(variant, h.grid, plan->d_items, plan->d_tri, map, nullptr, single,
-                            accumulate, static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  int form = FORM_F64;
+  const void* opA = dA;
+  const void* opB = dB;
+  if (h.cfg.precision == BSM_FP32) {
+    // S6: operands rounded to FP32 once per execute (A == B is converted once)
+    form = FORM_F32;
+    if ((e = launch_to_f32(dA, static_cast<float*>(plan->d_opA), h.a_elems, s)) != hipSuccess)
+      return hip_fail(e, "convert A");
+    opA = plan->d_opA;
+    if (dB == dA && h.b_elems == h.a_elems) {
+      opB = plan->d_opA;
+    } else {
+      if ((e = launch_to_f32(dB, static_cast<float*>(plan->d_opB), h.b_elems, s)) != hipSuccess)
+        return hip_fail(e, "convert B");
+      opB = plan->d_opB;
+    }
+  }
+  TileArgs a{};
+  a.items = plan->d_items;
+  a.tri = plan->d_tri;
+  for (int x = 0; x <= kXcds; ++x) a.map.begin[x] = h.xcd_begin[x];
+  a.prods = nullptr;
+  a.single = ProductArgs{opA, opB, dC, plan->d_partial, alpha};
+  a.accumulate = accumulate;
+  a.stamps = plan->d_stamps;
+  // S5: k-windows of I consecutive inner blocks, issued in order on the stream; each window
+  // resumes from the raw FP64 sums of the previous one, so C does not depend on I
+  const int64_t I = h.k_window_eff;
+  for (int64_t wdx = 0; wdx < h.windows; ++wdx) {
+    a.k_lo = int(wdx * I);
+    a.k_hi = wdx + 1 == h.windows ? kNoKLimit : int((wdx + 1) * I);
+    a.win_first = wdx == 0;
+    a.win_last = wdx + 1 == h.windows;
+    e = form == FORM_F64 ? launch_tiles_f64(h.items[0].variant, h.grid, a, s)
+                         : launch_tiles_f32(h.items[0].variant, h.grid, a, s);
+    if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+  }
+  plan->timed = plan->d_stamps != nullptr;
+  return BSM_OK;
+}
+
+bsm_status bsm_plan_timings(bsm_plan* plan, float* features, float* seconds, int64_t n,
+                            void* stream) {
+  if (!plan) return fail(BSM_E_INVALID, "plan is null");
+  const HostPlan& h = plan->hp;
+  if (n != int64_t(h.items.size())) return fail(BSM_E_MISMATCH, "n must equal the task count");
+  if (!plan->timed) return fail(BSM_E_STATE, "no execute with record_timings has run");
+  if (n == 0) return BSM_OK;
+  if ((!features && !seconds)) return fail(BSM_E_INVALID, "null output");
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  std::vector<uint64_t> st(size_t(n) * 2);
+  e = hipMemcpy(st.data(), plan->d_stamps, st.size() * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(stamps)");
+  for (int64_t q = 0; q < n; ++q) {
+    if (seconds) seconds[q] = float(double(st[size_t(2 * q + 1)] - st[size_t(2 * q)]) * 1e-8);
+    if (features)
+      for (int f = 0; f < 5; ++f) features[q * 5 + f] = h.features[size_t(q * 5 + f)];
+  }
   return BSM_OK;
 }
 
@@ -193,8 +270,9 @@ bsm_status bsm_plan_destroy(bsm_plan* plan) {
   if (plan->uploaded) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize");
-    if (plan->d_items) (void)hipFree(plan->d_items);
-    if (plan->d_tri) (void)hipFree(plan->d_tri);
+    for (void* ptr : {static_cast<void*>(plan->d_items), static_cast<void*>(plan->d_tri), plan->d_opA,
+                      plan->d_opB, static_cast<void*>(plan->d_partial), static_cast<void*>(plan->d_stamps)})
+      if (ptr) (void)hipFree(ptr);
   }
   delete plan;
   return st;

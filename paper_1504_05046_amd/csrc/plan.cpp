@@ -6,6 +6,8 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <numeric>
 
@@ -59,27 +61,84 @@ static int64_t pack_offsets(int64_t R, int64_t C, const std::vector<int64_t>& rs
   return pos;
 }
 
-// Cut a block dimension of `m` rows into near-equal pieces of at most `t` rows, each a
-// multiple of 16 rows except where the block ends.
-static void split_dim(int m, int t, std::vector<std::pair<int, int>>& out) {
-  out.clear();
-  int nb16 = (m + 15) / 16, per = t / 16;
-  int pieces = (nb16 + per - 1) / per;
-  int base = nb16 / pieces, extra = nb16 % pieces, off = 0;
-  for (int p = 0; p < pieces; ++p) {
-    int nbl = base + (p < extra ? 1 : 0);
-    int size = std::min(nbl * 16, m - off);
-    out.emplace_back(off, size);
-    off += nbl * 16;
+// Sub-tile cuts of one C block.  A dimension of nb16 16-row blocks is cut into the fewest
+// pieces of at most `per` blocks; among all such cuts of both dimensions the planner takes the
+// one whose slowest wave issues the fewest MFMAs (a workgroup's NW waves share a sub-tile's
+// 16x16 output blocks round-robin, so a sub-tile of b blocks costs ceil(b / NW) per k-step).
+static void compositions(int total, int parts, int per, std::vector<int>& cur,
+                         std::vector<std::vector<int>>& out) {
+  if (parts == 1) {
+    if (total >= 1 && total <= per) {
+      cur.push_back(total);
+      out.push_back(cur);
+      cur.pop_back();
+    }
+    return;
+  }
+  for (int a = 1; a <= per && a <= total - (parts - 1); ++a) {
+    cur.push_back(a);
+    compositions(total - a, parts - 1, per, cur, out);
+    cur.pop_back();
   }
 }
 
-// Library-chosen tile variant for a C block (largest tile for large blocks).
+static std::vector<std::vector<int>> cuts_of(int nb16, int per, bool search) {
+  int parts = (nb16 + per - 1) / per;
+  std::vector<std::vector<int>> out;
+  if (search && parts <= 3) {
+    std::vector<int> cur;
+    compositions(nb16, parts, per, cur, out);
+  } else {  // large blocks: near-equal pieces
+    std::vector<int> c;
+    int base = nb16 / parts, extra = nb16 % parts;
+    for (int p = 0; p < parts; ++p) c.push_back(base + (p < extra ? 1 : 0));
+    out.push_back(c);
+  }
+  return out;
+}
+
+struct CutChoice {
+  std::vector<int> rows, cols;  // piece sizes in 16-blocks
+};
+
+static const CutChoice& best_cut(int br, int bc, int per_r, int per_c, int nw, bool search,
+                                 std::map<std::array<int, 5>, CutChoice>& memo) {
+  std::array<int, 5> key{br, bc, per_r, per_c, nw};
+  auto f = memo.find(key);
+  if (f != memo.end()) return f->second;
+  auto rc = cuts_of(br, per_r, search), cc = cuts_of(bc, per_c, search);
+  int64_t best = -1;
+  CutChoice choice;
+  for (auto& r : rc)
+    for (auto& c : cc) {
+      int64_t cost = 0;
+      for (int a : r)
+        for (int b : c) cost += (a * b + nw - 1) / nw;
+      if (best < 0 || cost < best) {
+        best = cost;
+        choice.rows = r;
+        choice.cols = c;
+      }
+    }
+  return memo.emplace(key, choice).first->second;
+}
+
+static void pieces_to_ranges(const std::vector<int>& blocks, int m,
+                             std::vector<std::pair<int, int>>& out) {
+  out.clear();
+  int off = 0;
+  for (int nb : blocks) {
+    out.emplace_back(off, std::min(nb * 16, m - off));
+    off += nb * 16;
+  }
+}
+
+// Library-chosen tile variant for a C block.
 static int pick_variant(int m, int n, int forced) {
   if (forced > 0) return forced - 1;
-  int d = std::max(m, n);
-  (void)d;
-  return 0;
+  (void)m;
+  (void)n;
+  return kDefaultVariant;
 }
 
 std::vector<double> flop_costs(const HostPlan& p) {
@@ -203,6 +262,7 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   p.features.clear();
   p.useful_flops = 0;
   std::vector<std::pair<int, int>> rs, cs;
+  std::map<std::array<int, 5>, CutChoice> cut_memo;
   double ktot = 0;
   for (int64_t k = 0; k < K; ++k) ktot += double(p.inner[size_t(k)]);
   for (int64_t i = 0; i < M; ++i) {
@@ -231,8 +291,11 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
       int m = int(p.rows[size_t(i)]), n = int(p.cols[size_t(j)]);
       p.useful_flops += 2.0 * m * n * sk;
       int v = pick_variant(m, n, cfg.tile);
-      split_dim(m, kVariants[v].tm, rs);
-      split_dim(n, kVariants[v].tn, cs);
+      const CutChoice& cut = best_cut((m + 15) / 16, (n + 15) / 16, kVariants[v].tm / 16,
+                                      kVariants[v].tn / 16, kVariants[v].nw, cfg.cut_search,
+                                      cut_memo);
+      pieces_to_ranges(cut.rows, m, rs);
+      pieces_to_ranges(cut.cols, n, cs);
       for (auto& r : rs)
         for (auto& c : cs) {
           Item it;
@@ -255,6 +318,9 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
         }
     }
   }
+  // S5: k-windows (0 = all K inner blocks in flight at once)
+  p.k_window_eff = (cfg.k_window == 0 || cfg.k_window >= K) ? std::max<int64_t>(K, 1) : cfg.k_window;
+  p.windows = K > 0 ? (K + p.k_window_eff - 1) / p.k_window_eff : 1;
   // S4: cost and order
   schedule(p, flop_costs(p));
   *code = BSM_OK;

@@ -9,14 +9,15 @@
 
 namespace bsm {
 
-// Tile variants (see BSM_F64_VARIANTS): the largest C sub-tile one workgroup computes.
+// Tile variants (see BSM_TILE_VARIANTS): the largest C sub-tile one workgroup computes.
 struct Variant {
   int tm, tn, nw;
 };
 #define BSM_VARIANT_ROW(ID, TM, TN, KC, NW, OCC) {TM, TN, NW},
-constexpr Variant kVariants[] = {BSM_F64_VARIANTS(BSM_VARIANT_ROW)};
+constexpr Variant kVariants[] = {BSM_TILE_VARIANTS(BSM_VARIANT_ROW)};
 #undef BSM_VARIANT_ROW
 constexpr int kNumVariants = int(sizeof(kVariants) / sizeof(kVariants[0]));
+constexpr int kDefaultVariant = 0;  // 128 x 128, 8 waves
 
 enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1 };
 
@@ -27,6 +28,7 @@ struct PlanConfig {
   int record_timings = 0;
   int tile = 0;       // 0 = auto, else variant id + 1
   int order = ORDER_LOCALITY;
+  bool cut_search = false;  // choose sub-tile cuts by slowest-wave cost (else near-equal pieces)
 };
 
 struct HostPlan {
@@ -44,6 +46,8 @@ struct HostPlan {
   std::vector<double> cost;      // scheduler cost of items[q]
   std::vector<float> features;   // 5 per item: log h, log w, log sum_k, log #k, density
   int32_t xcd_begin[kXcds + 1] = {0};
+  int64_t k_window_eff = 0;      // inner blocks per k-window
+  int64_t windows = 1;           // number of k-windows
   int64_t grid = 0;              // workgroups of the launch
 };
 

@@ -1,0 +1,368 @@
+// Tile contraction on gfx950 MFMA, FP64 and FP32 forms.
+//
+// One workgroup (NW waves) executes one task: a C sub-tile of h x w (h <= TM, w <= TN) and the
+// k-list of its C block (the triples whose k lies in the current k-window).  For every triple, in
+// ascending k, the workgroup streams KC-wide k-chunks of A_ik (rows r0..r0+h) and B_kj (cols
+// c0..c0+w) from HBM into LDS (double-buffered, one barrier per chunk), and the waves share the
+// sub-tile's 16x16 output blocks round-robin.  FP64 form: v_mfma_f64_16x16x4 into FP64
+// registers across the whole k-list.  FP32 form: v_mfma_f32_16x16x4 into FP32 registers within
+// one block product A_ik B_kj, folded into FP64 registers when the triple ends.  The epilogue
+// writes alpha*acc (+C) once per element: the paper's multiply task and reduction task fused,
+// with no temporaries (Sec. 3.2, Fig. 3).
+#include <hip/hip_runtime.h>
+
+#pragma once
+#include "kernels.hpp"
+
+namespace bsm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+// Fourth word of a raw (stride 0) buffer descriptor on gfx9-family targets: 32-bit data format,
+// no swizzle; loads past num_records return 0.
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr uint32_t kOutOfRange = 0x7FFFFFF0u;
+
+template <int FORM>
+struct FormT;
+
+template <>
+struct FormT<FORM_F64> {
+  using T = double;
+  static constexpr bool kFold = false;
+  __device__ static inline T load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  // v_mfma_f64_16x16x4: register r of lane 16g + i holds row g + 4r, column i (gfx950)
+  __device__ static inline int out_row(int g, int r) { return g + 4 * r; }
+};
+
+template <>
+struct FormT<FORM_F32> {
+  using T = float;
+  static constexpr bool kFold = true;
+  __device__ static inline T load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+  // v_mfma_f32_16x16x4: register r of lane 16g + i holds row 4g + r, column i
+  __device__ static inline int out_row(int g, int r) { return 4 * g + r; }
+};
+
+template <int TM, int TN, int KC_, int NW_, int FORM>
+struct TileCfg {
+  using T = typename FormT<FORM>::T;
+  static constexpr int ES = int(sizeof(T));
+  static constexpr int KC = KC_;            // k-chunk staged per step
+  static constexpr int NW = NW_;            // waves per workgroup
+  static constexpr int NT = 64 * NW;        // threads per workgroup
+  // A chunk: TM rows x KC.  With KC = 16 the rows are unpadded and the k index is XOR-swizzled
+  // with bits 1..3 of the row, which keeps both the staging stores (two rows per half-wave) and
+  // the fragment reads (16 rows per half-wave) free of bank conflicts; otherwise rows are padded.
+  static constexpr bool SWZ = false;
+  static constexpr int ASTR = SWZ ? KC : (KC == 16 ? KC + 1 : KC + 2);
+  // B chunk: KC rows x TN, padded so that a half-wave's fragment reads hit distinct banks
+  static constexpr int BSTR = TN + 16;
+  __device__ static inline int apos(int row, int k) {
+    return row * ASTR + (SWZ ? (k ^ (row & 14)) : k);
+  }
+  static constexpr int SLOTS = ((TM / 16) * (TN / 16) + NW - 1) / NW;  // 16x16 blocks per wave
+  static constexpr int ARP = NT / KC;       // A rows staged per pass (KC threads per row)
+  static constexpr int ALD = TM / ARP;      // A elements each thread stages per chunk
+  static constexpr int BK = NT / TN;        // B k-rows staged per pass (TN threads per row)
+  static constexpr int BLD = KC / BK;       // B elements each thread stages per chunk
+  static constexpr int ASZ = TM * ASTR;     // elements of one A stage
+  static constexpr int BSZ = KC * BSTR;     // elements of one B stage
+  static_assert(KC % 16 == 0 && NT % KC == 0 && TM % ARP == 0, "A staging shape");
+  static_assert(TN <= NT && NT % TN == 0 && KC % BK == 0, "B staging shape");
+};
+
+// Values the whole wave agrees on, made explicit so that buffer descriptors built from them stay
+// in scalar registers.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint32_t uni(uint32_t v) { return uint32_t(__builtin_amdgcn_readfirstlane(int(v))); }
+template <typename P>
+__device__ inline P* uni_ptr(P* p) {
+  uint64_t v = reinterpret_cast<uint64_t>(p);
+  uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+  uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
+  return reinterpret_cast<P*>((uint64_t(hi) << 32) | lo);
+}
+
+// First triple of [tb, te) whose inner block index is >= k (the k-lists are sorted by k).
+__device__ inline uint32_t lower_bound_k(const Triple* __restrict__ tri, uint32_t tb, uint32_t te,
+                                         int k) {
+  while (tb < te) {
+    uint32_t mid = tb + ((te - tb) >> 1);
+    if (tri_k(tri[mid]) < k) tb = mid + 1;
+    else te = mid;
+  }
+  return tb;
+}
+
+// The part of a task one wave runs when it owns NS of the sub-tile's 16x16 output blocks.
+// Every wave of the workgroup walks the same k-chunks and meets the same barriers; NS is a
+// compile-time constant so that the MFMA stream has no per-block branches.
+template <int TM, int TN, int KC, int NW, int FORM, bool RESUME, int NS>
+__device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, const ProductArgs& pa,
+                                         int wave, typename FormT<FORM>::T* As,
+                                         typename FormT<FORM>::T* Bs) {
+  using C = TileCfg<TM, TN, KC, NW, FORM>;
+  using F = FormT<FORM>;
+  using T = typename C::T;
+  constexpr int NSA = NS > 0 ? NS : 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = lane >> 4, i16 = lane & 15;
+  const int h = it.h, w = it.w, ldc = it.ldc;
+  const int bcn = (w + 15) >> 4;
+
+  // this wave's output blocks q = wave, wave+NW, ... (row-major over the sub-tile's blocks)
+  int a_u[NSA], b_u[NSA];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    int q = wave + NW * j;
+    int rb = q / bcn, cb = q - rb * bcn;
+    a_u[j] = 16 * rb * C::ASTR;
+    b_u[j] = 16 * cb;
+  }
+  const int64_t c_base = it.c_off + int64_t(it.r0) * ldc + it.c0;
+
+  // FP64 accumulators; with a k-window after the first they resume from the raw partial sums
+  // (a separate instantiation, so that the common single-window case carries none of it)
+  d4 acc[NSA];
+  const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+      uni_ptr(pa.P + c_base), (short)0, uni(RESUME ? ((h - 1) * ldc + w) * 8 : 0), kRsrcWord3);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
+    if constexpr (RESUME) {
+      int q = wave + NW * j;
+      int rbk = q / bcn, cbk = q - rbk * bcn;
+      int col = 16 * cbk + i16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = 16 * rbk + F::out_row(g, r);
+        uint32_t off = (row < h && col < w) ? uint32_t((row * ldc + col) * 8) : kOutOfRange;
+        acc[j][r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(prs, off, 0, 0));
+      }
+    }
+  }
+  f4 acc32[FORM == FORM_F32 ? NSA : 1];
+  if constexpr (FORM == FORM_F32) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) acc32[j] = (f4){0.f, 0.f, 0.f, 0.f};
+  }
+
+  // staging assignment: A chunk row-major (KC consecutive threads read one row's k-chunk),
+  // B chunk row-major (TN consecutive threads read one k-row's columns)
+  const int ka = tid % KC, ra0 = tid / KC;
+  const int cbl = tid % TN, kb0 = tid / TN;
+  T ra[C::ALD], rb[C::BLD];
+  const T* Ag = static_cast<const T*>(pa.A);
+  const T* Bg = static_cast<const T*>(pa.B);
+
+  // Staging loads go through buffer descriptors: a load whose offset lies past num_records
+  // returns 0 instead of touching memory.  A's descriptor ends at row h of the sub-tile, so rows
+  // beyond it read 0; the k-tail (k >= s_k would wrap into the next row) is sent out of range
+  // explicitly.  B's descriptor ends at the last element of the sub-tile's columns, so k-rows
+  // beyond s_k read 0; columns beyond w read finite neighbours that only feed output columns the
+  // epilogue discards.
+  auto load = [&](const Triple& t, int kk) {
+    const int ks = tri_ks(t);
+    const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
+        uni_ptr(const_cast<T*>(Ag + tri_a_off(t) + int64_t(it.r0) * ks)), (short)0,
+        uni(h * ks * C::ES), kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t br = __builtin_amdgcn_make_buffer_rsrc(
+        uni_ptr(const_cast<T*>(Bg + tri_b_off(t) + it.c0)), (short)0,
+        uni(((ks - 1) * ldc + w) * C::ES), kRsrcWord3);
+    const bool kin = kk + ka < ks;
+#pragma unroll
+    for (int p = 0; p < C::ALD; ++p) {
+      const uint32_t off = kin ? uint32_t(((ra0 + C::ARP * p) * ks + kk + ka) * C::ES) : kOutOfRange;
+      ra[p] = F::load(ar, off);
+    }
+#pragma unroll
+    for (int p = 0; p < C::BLD; ++p) {
+      const uint32_t off = uint32_t(((kk + kb0 + C::BK * p) * ldc + cbl) * C::ES);
+      rb[p] = F::load(br, off);
+    }
+  };
+  auto store = [&](int buf) {
+    T* as = As + buf * C::ASZ;
+    T* bs = Bs + buf * C::BSZ;
+#pragma unroll
+    for (int p = 0; p < C::ALD; ++p) as[C::apos(ra0 + C::ARP * p, ka)] = ra[p];
+#pragma unroll
+    for (int p = 0; p < C::BLD; ++p) bs[(kb0 + C::BK * p) * C::BSTR + cbl] = rb[p];
+  };
+
+  uint32_t te = it.tri_begin + it.tri_count;
+  uint32_t t = it.tri_begin;
+  if (a.k_lo > 0) t = uni(lower_bound_k(a.tri, t, te, a.k_lo));
+  if (a.k_hi < kNoKLimit) te = uni(lower_bound_k(a.tri, t, te, a.k_hi));
+  int kk = 0;
+  Triple tc;
+  if (t < te) {
+    tc = a.tri[t];
+    load(tc, 0);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  while (t < te) {
+    const int ks = tri_ks(tc);
+    const int nsteps = (min(C::KC, ks - kk) + 3) >> 2;  // 4-deep MFMA steps holding data
+    // next chunk: the rest of this block, else the next triple
+    uint32_t tn = t;
+    int kn = kk + C::KC;
+    Triple tnx = tc;
+    const bool triple_ends = kn >= ks;
+    if (triple_ends) {
+      tn = t + 1;
+      kn = 0;
+      if (tn < te) tnx = a.tri[tn];
+    }
+    const bool more = tn < te;
+    if (more) load(tnx, kn);
+
+    if (NS > 0) {
+      const T* as = As + buf * C::ASZ;
+      const T* bs = Bs + buf * C::BSZ + g * C::BSTR + i16;
+      // one 4-deep MFMA step per iteration; steps past the block's end hold only zeros and are
+      // skipped (the condition is the same for the whole wave)
+#pragma unroll
+      for (int s = 0; s < C::KC / 4; ++s) {
+        if (s < nsteps) {
+          // fragments are read in groups of up to GM blocks to bound register use
+          constexpr int GM = NW >= 8 ? 4 : 8;
+#pragma unroll
+          for (int j0 = 0; j0 < NS; j0 += GM) {
+            constexpr int G = NS < GM ? NS : GM;
+            T av[G > 0 ? G : 1], bv[G > 0 ? G : 1];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+              if (j0 + j < NS) {
+                av[j] = as[a_u[j0 + j] + C::apos(i16, 4 * s + g)];
+                bv[j] = bs[b_u[j0 + j] + 4 * s * C::BSTR];
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+              if (j0 + j < NS) {
+                if constexpr (FORM == FORM_F64)
+                  acc[j0 + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], acc[j0 + j], 0, 0, 0);
+                else
+                  acc32[j0 + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[j], acc32[j0 + j], 0, 0, 0);
+              }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if constexpr (F::kFold) {
+        // the block product A_ik B_kj is complete: add it to the FP64 sum across k
+        if (triple_ends) {
+#pragma unroll
+          for (int j = 0; j < NS; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[j][r] += double(acc32[j][r]);
+            acc32[j] = (f4){0.f, 0.f, 0.f, 0.f};
+          }
+        }
+      }
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    t = tn;
+    kk = kn;
+    tc = tnx;
+  }
+
+  // epilogue: the raw sum goes to the partial buffer until the last k-window, which writes
+  // alpha*sum (+C)
+  const double alpha = pa.alpha;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    int q = wave + NW * j;
+    int rbk = q / bcn, cbk = q - rbk * bcn;
+    int col = 16 * cbk + i16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int row = 16 * rbk + F::out_row(g, r);
+      if (row < h && col < w) {
+        const int64_t e = c_base + int64_t(row) * ldc + col;
+        if (a.win_last) {
+          double v = alpha * acc[j][r];
+          pa.C[e] = a.accumulate ? v + pa.C[e] : v;
+        } else {
+          pa.P[e] = acc[j][r];
+        }
+      }
+    }
+  }
+}
+
+template <int TM, int TN, int KC, int NW, int FORM, bool RESUME, int NS>
+__device__ __forceinline__ void dispatch_ns(int ns, const TileArgs& a, const Item& it,
+                                            const ProductArgs& pa, int wave,
+                                            typename FormT<FORM>::T* As,
+                                            typename FormT<FORM>::T* Bs) {
+  if constexpr (NS > TileCfg<TM, TN, KC, NW, FORM>::SLOTS) {
+    return;
+  } else {
+    if (ns == NS) run_task<TM, TN, KC, NW, FORM, RESUME, NS>(a, it, pa, wave, As, Bs);
+    else dispatch_ns<TM, TN, KC, NW, FORM, RESUME, NS + 1>(ns, a, it, pa, wave, As, Bs);
+  }
+}
+
+template <int TM, int TN, int KC, int NW, int OCC, int FORM, bool RESUME>
+__global__ __launch_bounds__(64 * NW, OCC) void tiles(TileArgs a) {
+  using C = TileCfg<TM, TN, KC, NW, FORM>;
+  using T = typename C::T;
+  __shared__ T As[2 * C::ASZ];
+  __shared__ T Bs[2 * C::BSZ];
+
+  // XCD-aware task lookup: the hardware deals workgroups round-robin over the 8 XCDs, so
+  // workgroup 8q + x runs on XCD x and takes that XCD's q-th task.
+  const int x = blockIdx.x % kXcds, qx = blockIdx.x / kXcds;
+  const int idx = a.map.begin[x] + qx;
+  if (idx >= a.map.begin[x + 1]) return;
+  if (a.stamps && threadIdx.x == 0) a.stamps[2 * idx] = wall_clock64();
+  const Item it = a.items[idx];
+  const ProductArgs pa = a.prods ? a.prods[it.product] : a.single;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nb = ((it.h + 15) >> 4) * ((it.w + 15) >> 4);
+  const int ns = nb > wave ? (nb - wave + NW - 1) / NW : 0;  // output blocks of this wave
+  dispatch_ns<TM, TN, KC, NW, FORM, RESUME, 0>(ns, a, it, pa, wave, As, Bs);
+  if (a.stamps) {
+    __syncthreads();
+    if (threadIdx.x == 0) a.stamps[2 * idx + 1] = wall_clock64();
+  }
+}
+
+// Launches of one precision form (instantiated once per form, in its own translation unit).
+template <int FORM>
+hipError_t launch_tiles_form(int variant, int64_t grid, const TileArgs& args, hipStream_t stream) {
+  const uint32_t grid32 = static_cast<uint32_t>(grid);
+#define BSM_TILE_LAUNCH(ID, TM, TN, KC, NW, OCC)                                                  \
+  case ID:                                                                                        \
+    if (args.win_first)                                                                           \
+      hipLaunchKernelGGL((tiles<TM, TN, KC, NW, OCC, FORM, false>), dim3(grid32), dim3(64 * NW), 0, \
+                         stream, args);                                                           \
+    else                                                                                          \
+      hipLaunchKernelGGL((tiles<TM, TN, KC, NW, OCC, FORM, true>), dim3(grid32), dim3(64 * NW), 0,  \
+                         stream, args);                                                           \
+    break;
+  switch (variant) {
+    BSM_TILE_VARIANTS(BSM_TILE_LAUNCH)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef BSM_TILE_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace bsm

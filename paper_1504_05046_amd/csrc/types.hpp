@@ -15,20 +15,15 @@ constexpr int64_t kMaxBlock = 65535;          // block sizes fit 16 bits
 constexpr int64_t kMaxElems = int64_t(1) << 48;  // tile offsets fit 48 bits
 constexpr int kXcds = 8;                       // MI355X: 8 accelerator dies, each with its own L2
 
-// FP64 tile variants: X(id, TM, TN, KC, NW, OCC) = largest C sub-tile TM x TN of one workgroup,
+// Tile variants: X(id, TM, TN, KC, NW, OCC) = largest C sub-tile TM x TN of one workgroup,
 // k-chunk KC staged through LDS per step, NW waves per workgroup, OCC waves per SIMD the register
-// allocator must leave room for (512 / OCC registers per lane).  Sub-tiles are cut in multiples of 16 rows/columns.
-#define BSM_F64_VARIANTS(X)     \
-  X(0, 128, 128, 16, 4, 2)      \
-  X(1, 64, 64, 16, 4, 1)        \
-  X(2, 32, 32, 16, 4, 1)        \
-  X(3, 128, 128, 32, 4, 1)      \
-  X(4, 128, 128, 16, 4, 1)      \
-  X(5, 64, 64, 32, 4, 1)        \
-  X(6, 128, 64, 16, 4, 2)       \
-  X(7, 64, 64, 16, 4, 3)        \
-  X(8, 128, 128, 16, 8, 4)      \
-  X(9, 128, 64, 16, 4, 3)
+// allocator must leave room for (512 / OCC registers per lane).  Sub-tiles are cut in multiples
+// of 16 rows/columns.
+#define BSM_TILE_VARIANTS(X)    \
+  X(0, 128, 128, 16, 8, 4)      \
+  X(1, 128, 128, 16, 4, 2)      \
+  X(2, 64, 64, 16, 4, 3)        \
+  X(3, 32, 32, 16, 4, 4)
 
 // One (i,k,j) block triple of a C block's k-list: where A_ik and B_kj start and the inner block
 // size.  a = A offset | (s_k << 48);  b = B offset | (k << 48).
@@ -55,11 +50,13 @@ struct Item {
 };
 static_assert(sizeof(Item) == 32, "Item layout");
 
-// Operands of one product in a batch.
+// Operands of one product: A and B in the element type of the precision form (FP64 tiles, or
+// their FP32 / bf16-slice copies), C and the k-window partial sums P in FP64.
 struct ProductArgs {
-  const double* A;
-  const double* B;
+  const void* A;
+  const void* B;
   double* C;
+  double* P;
   double alpha;
 };
 
