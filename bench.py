@@ -24,12 +24,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "useful TFLOP/s, block-sparse MM: FP64 vs split-BF16 at ≤1e-6 rel err, 1 GPU"
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 MFMA (datasheet)
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA (datasheet)
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     "nonuniform_16384": ("N=16384, block sizes U{32..256} (last = remainder), Bernoulli(0.3) "
                          "A and B block shapes, N(0,1) FP64 values, C = A*B"),
     "uniform_1024": "N=1024, 16x16 blocks of 64, Bernoulli(0.5) shapes, U[-1,1] FP64 values",
+    "precision_32768": ("N=32768, block sizes U{64..256}, Bernoulli(0.4) shapes, N(0,1) values "
+                        "scaled per block by 10^U(-4,0), C = A*B"),
 }
 
 
@@ -39,7 +42,45 @@ def make_workload(name):
         return gen.nonuniform_16384()
     if name == "uniform_1024":
         return gen.uniform_1024()
+    if name == "precision_32768":
+        return gen.precision_32768()
     raise SystemExit(f"unknown workload {name}")
+
+
+def time_plan(plan, A, B, C, steps, warmup, stream, torch):
+    """(wall ms per step, mean and sd of the per-launch event time in ms)."""
+    for _ in range(warmup):
+        plan.execute(A, B, C, stream=stream)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        plan.execute(A, B, C, stream=stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    ev = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return wall, float(np.mean(ev)), float(np.std(ev))
+
+
+def sampled_error(p, got_c, c_off, nsample=48, seed=7):
+    """Relative Frobenius error of a random sample of C blocks against the oracle."""
+    import oracle
+    present = np.argwhere(c_off >= 0)
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(present), min(nsample, len(present)), replace=False)
+    sel = [tuple(int(v) for v in present[q]) for q in pick]
+    blocks, _ = oracle.bsmm_blocks(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data,
+                                   p.b_data, sel)
+    num = den = 0.0
+    for (i, j), blk in zip(sel, blocks):
+        o = int(c_off[i, j])
+        g = got_c[o:o + blk.size].reshape(blk.shape)
+        num += float(np.sum((g - blk) ** 2))
+        den += float(np.sum(blk ** 2))
+    return (num / den) ** 0.5 if den > 0 else 0.0
 
 
 def cpu_baseline(p, got_c, c_off, target_s: float, seed: int = 12345):
@@ -91,6 +132,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nonuniform_16384", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-split-bf16", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--tile", type=int, default=0, help="0 = library choice, else variant id + 1")
     args = ap.parse_args()
@@ -113,25 +155,9 @@ def main():
     C = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        plan.execute(A, B, C, stream=stream)
-    torch.cuda.synchronize()
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        plan.execute(A, B, C, stream=stream)
-        ends[k].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall / args.steps * 1e3
-    kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    kern_avg = float(np.mean(kern_ms))
+    wall_ms, kern_avg, kern_sd = time_plan(plan, A, B, C, args.steps, args.warmup, stream, torch)
     flops = info.useful_flops
-    value = flops / (ms_per_step * 1e-3) / 1e12
+    value = flops / (wall_ms * 1e-3) / 1e12
     achieved = flops / (kern_avg * 1e-3) / 1e12
 
     result = {
@@ -141,7 +167,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(wall_ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -153,14 +179,31 @@ def main():
                    "plan_ms": round(plan_ms, 1)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": None, "kernel": "f64_tiles", "kernel_ms": round(kern_avg, 4),
-                     "kernel_ms_sd": round(float(np.std(kern_ms)), 4)},
+                     "traffic": None, "kernel": "tiles (FP64 form)", "kernel_ms": round(kern_avg, 4),
+                     "kernel_ms_sd": round(kern_sd, 4)},
     }
+    C3 = None
+    if not args.no_split_bf16:
+        # the split-bf16 form on the same inputs: split pass + bf16 MFMA tile kernel per step
+        plan3 = bsm.Plan.from_problem(p, precision=bsm.BF16X3)
+        C3 = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
+        w3, e3, sd3 = time_plan(plan3, A, B, C3, args.steps, args.warmup, stream, torch)
+        result["split_bf16"] = {
+            "value": round(flops / (w3 * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+            "ms_per_step": round(w3, 4), "launch_ms": round(e3, 4),
+            "vs_fp64": round(wall_ms / w3, 3),
+            "mfma_frac": round(6 * flops / (e3 * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
+            "note": "useful flops only; the six slice products per block product are 6x the MFMA work",
+        }
     if not args.no_cpu_baseline:
         got = C.cpu().numpy()[:info.c_elems]
-        cb, err = cpu_baseline(p, got, plan.c_offsets(), args.cpu_seconds)
+        c_off = plan.c_offsets()
+        cb, err = cpu_baseline(p, got, c_off, args.cpu_seconds)
         result["cpu_baseline"] = cb
         result["sample_rel_err"] = err
+        if C3 is not None:
+            got3 = C3.cpu().numpy()[:info.c_elems]
+            result["split_bf16"]["sample_rel_err"] = sampled_error(p, got3, c_off)
     print(json.dumps(result), flush=True)
 
 

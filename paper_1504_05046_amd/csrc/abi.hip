@@ -29,6 +29,8 @@ struct bsm_plan {
   Triple* d_tri = nullptr;
   void* d_opA = nullptr;         // converted operands of the reduced-precision forms
   void* d_opB = nullptr;
+  SplitBlock* d_split_a = nullptr;  // split-bf16 form: block tables of the split pass
+  SplitBlock* d_split_b = nullptr;
   double* d_partial = nullptr;   // raw sums between k-windows (laid out like C)
   uint64_t* d_stamps = nullptr;  // per-task start/end clocks
   int device = -1;
@@ -115,6 +117,8 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   info->useful_flops = h.useful_flops;
   int64_t ws = int64_t(h.items.size() * sizeof(Item) + h.tri.size() * sizeof(Triple));
   if (h.cfg.precision == BSM_FP32) ws += (h.a_elems + h.b_elems) * 4;
+  if (h.cfg.precision == BSM_BF16X3)
+    ws += (h.a_elems32 + h.b_elems32) * 6 + int64_t((h.split_a.size() + h.split_b.size()) * sizeof(SplitBlock));
   if (h.windows > 1) ws += h.c_elems * 8;
   if (h.cfg.record_timings) ws += int64_t(h.items.size()) * 16;
   info->workspace_bytes = ws;
@@ -169,6 +173,15 @@ static bsm_status upload(bsm_plan* p) {
     if (ne_a > 0 && (e = hipMalloc(&p->d_opA, size_t(ne_a) * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(A fp32)");
     if (ne_b > 0 && (e = hipMalloc(&p->d_opB, size_t(ne_b) * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(B fp32)");
   }
+  if (h.cfg.precision == BSM_BF16X3) {
+    if (h.a_elems32 > 0 && (e = hipMalloc(&p->d_opA, size_t(h.a_elems32) * 6)) != hipSuccess) return hip_fail(e, "hipMalloc(A slices)");
+    if (h.b_elems32 > 0 && (e = hipMalloc(&p->d_opB, size_t(h.b_elems32) * 6)) != hipSuccess) return hip_fail(e, "hipMalloc(B slices)");
+    const size_t na = h.split_a.size() * sizeof(SplitBlock), nb = h.split_b.size() * sizeof(SplitBlock);
+    if (na && (e = hipMalloc(&p->d_split_a, na)) != hipSuccess) return hip_fail(e, "hipMalloc(split table)");
+    if (nb && (e = hipMalloc(&p->d_split_b, nb)) != hipSuccess) return hip_fail(e, "hipMalloc(split table)");
+    if (na && (e = hipMemcpy(p->d_split_a, h.split_a.data(), na, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy(split table)");
+    if (nb && (e = hipMemcpy(p->d_split_b, h.split_b.data(), nb, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy(split table)");
+  }
   if (h.windows > 1 && h.c_elems > 0) {
     if ((e = hipMalloc(&p->d_partial, size_t(h.c_elems) * 8)) != hipSuccess) return hip_fail(e, "hipMalloc(partial)");
   }
@@ -196,7 +209,6 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
   if (overlaps(dC, h.c_elems * 8, dA, h.a_elems * 8) || overlaps(dC, h.c_elems * 8, dB, h.b_elems * 8))
     return fail(BSM_E_INVALID, "C overlaps A or B");
   if (accumulate != 0 && accumulate != 1) return fail(BSM_E_INVALID, "accumulate must be 0 or 1");
-  if (h.cfg.precision == BSM_BF16X3) return fail(BSM_E_UNSUPPORTED, "precision form not built yet");
   bsm_status st = upload(plan);
   if (st != BSM_OK) return st;
   if (h.items.empty()) return BSM_OK;
@@ -219,12 +231,27 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
       opB = plan->d_opB;
     }
   }
+  int64_t a_plane = 0, b_plane = 0;
+  if (h.cfg.precision == BSM_BF16X3) {
+    // S6: three bf16 slices of every operand element, inner size padded to 32, B transposed
+    form = FORM_BF16X3;
+    a_plane = h.a_elems32;
+    b_plane = h.b_elems32;
+    if ((e = launch_split_bf16x3(plan->d_split_a, int64_t(h.split_a.size()), dA,
+                                 static_cast<uint16_t*>(plan->d_opA), a_plane, s)) != hipSuccess)
+      return hip_fail(e, "split A");
+    if ((e = launch_split_bf16x3(plan->d_split_b, int64_t(h.split_b.size()), dB,
+                                 static_cast<uint16_t*>(plan->d_opB), b_plane, s)) != hipSuccess)
+      return hip_fail(e, "split B");
+    opA = plan->d_opA;
+    opB = plan->d_opB;
+  }
   TileArgs a{};
   a.items = plan->d_items;
   a.tri = plan->d_tri;
   for (int x = 0; x <= kXcds; ++x) a.map.begin[x] = h.xcd_begin[x];
   a.prods = nullptr;
-  a.single = ProductArgs{opA, opB, dC, plan->d_partial, alpha};
+  a.single = ProductArgs{opA, opB, dC, plan->d_partial, alpha, a_plane, b_plane};
   a.accumulate = accumulate;
   a.stamps = plan->d_stamps;
   // S5: k-windows of I consecutive inner blocks, issued in order on the stream; each window
@@ -235,8 +262,10 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
     a.k_hi = wdx + 1 == h.windows ? kNoKLimit : int((wdx + 1) * I);
     a.win_first = wdx == 0;
     a.win_last = wdx + 1 == h.windows;
-    e = form == FORM_F64 ? launch_tiles_f64(h.items[0].variant, h.grid, a, s)
-                         : launch_tiles_f32(h.items[0].variant, h.grid, a, s);
+    const int v = h.items[0].variant;
+    e = form == FORM_F64   ? launch_tiles_f64(v, h.grid, a, s)
+        : form == FORM_F32 ? launch_tiles_f32(v, h.grid, a, s)
+                           : launch_tiles_bf16x3(v, h.grid, a, s);
     if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
   }
   plan->timed = plan->d_stamps != nullptr;
@@ -271,7 +300,8 @@ bsm_status bsm_plan_destroy(bsm_plan* plan) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize");
     for (void* ptr : {static_cast<void*>(plan->d_items), static_cast<void*>(plan->d_tri), plan->d_opA,
-                      plan->d_opB, static_cast<void*>(plan->d_partial), static_cast<void*>(plan->d_stamps)})
+                      plan->d_opB, static_cast<void*>(plan->d_split_a), static_cast<void*>(plan->d_split_b),
+                      static_cast<void*>(plan->d_partial), static_cast<void*>(plan->d_stamps)})
       if (ptr) (void)hipFree(ptr);
   }
   delete plan;

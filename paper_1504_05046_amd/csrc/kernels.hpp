@@ -34,4 +34,10 @@ hipError_t launch_tiles_f32(int variant, int64_t grid, const TileArgs& args, hip
 // dst[i] = src[i] rounded to FP32 for i < n.
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t stream);
 
+// Three bf16 slices of every block of one operand (see SplitBlock), planes `plane` elements apart.
+hipError_t launch_split_bf16x3(const SplitBlock* blocks, int64_t nblocks, const double* src,
+                               uint16_t* dst, int64_t plane, hipStream_t stream);
+
+hipError_t launch_tiles_bf16x3(int variant, int64_t grid, const TileArgs& args, hipStream_t stream);
+
 }  // namespace bsm

@@ -1,0 +1,292 @@
+// Split-bf16 tile contraction on gfx950 (v_mfma_f32_16x16x32_bf16).
+//
+// Each FP64 operand element is held as three bf16 slices a = a0 + a1 + a2 (written by the split
+// pass).  A block product is formed from the six slice products of order <= 2,
+//   a2 b0 + a1 b1 + a0 b2 + a1 b0 + a0 b1 + a0 b0,
+// accumulated in FP32 inside one block product A_ik B_kj and added into FP64 registers when the
+// triple ends; the epilogue writes alpha*sum (+C) in FP64 once per element.
+//
+// One workgroup of 8 waves runs one task (a C sub-tile of up to 128 x 128 and its k-list).  The
+// k-list is streamed in 32-deep chunks (one MFMA step): the three slices of A (rows) and of B
+// (columns, stored k-contiguous) go through double-buffered LDS with 16-byte loads and stores.
+// The waves form a 4 x 2 grid; each owns 2 x 4 of the sub-tile's 16x16 output blocks and reuses
+// every fragment it reads from LDS across a row or column of its blocks.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace bsm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kRsrcWord3b = 0x00020000;
+
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename P>
+__device__ inline P* uni_ptr(P* p) {
+  uint64_t v = reinterpret_cast<uint64_t>(p);
+  uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+  uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
+  return reinterpret_cast<P*>((uint64_t(hi) << 32) | lo);
+}
+
+__device__ inline uint32_t lower_bound_k3(const Triple* __restrict__ tri, uint32_t tb, uint32_t te,
+                                          int k) {
+  while (tb < te) {
+    uint32_t mid = tb + ((te - tb) >> 1);
+    if (tri_k(tri[mid]) < k) tb = mid + 1;
+    else te = mid;
+  }
+  return tb;
+}
+
+template <int TM, int TN, int NW>
+struct B3Cfg {
+  static constexpr int KC = kSliceK;           // one MFMA step per chunk
+  static constexpr int NT = 64 * NW;
+  static constexpr int RS = KC + 8;            // LDS row stride (bf16): 80 bytes, conflict-free
+  static constexpr int ASZ = 3 * TM * RS;      // bf16 elements of one A stage (3 slices)
+  static constexpr int BSZ = 3 * TN * RS;
+  static constexpr int WR = TM / 32;           // wave grid rows; each wave covers 32 rows
+  static constexpr int WC = NW / WR;           // wave grid cols
+  static constexpr int MC = TN / WC / 16;      // 16-col blocks per wave
+  static constexpr int AG = 3 * TM * (KC / 8); // 16-byte granules of one A stage
+  static constexpr int BG = 3 * TN * (KC / 8);
+  static constexpr int ALD = AG / NT, BLD = BG / NT;
+  static_assert(WR * WC == NW && AG % NT == 0 && BG % NT == 0, "bf16 tile shape");
+};
+
+template <int TM, int TN, int NW, bool RESUME, int NR, int NC>
+__device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const ProductArgs& pa,
+                                       int wr, int wc, uint16_t* As, uint16_t* Bs) {
+  using C = B3Cfg<TM, TN, NW>;
+  constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = lane >> 4, i16 = lane & 15;
+  const int h = it.h, w = it.w, ldc = it.ldc;
+  const int64_t c_base = it.c_off + int64_t(it.r0) * ldc + it.c0;
+  const int rb0 = 2 * wr, cb0 = C::MC * wc;
+
+  d4 acc[NRA][NCA];
+  f4 acc32[NRA][NCA];
+  const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+      uni_ptr(pa.P + c_base), (short)0, uni(RESUME ? ((h - 1) * ldc + w) * 8 : 0), kRsrcWord3b);
+#pragma unroll
+  for (int x = 0; x < NR; ++x)
+#pragma unroll
+    for (int y = 0; y < NC; ++y) {
+      acc[x][y] = (d4){0.0, 0.0, 0.0, 0.0};
+      acc32[x][y] = (f4){0.f, 0.f, 0.f, 0.f};
+      if constexpr (RESUME) {
+        const int col = 16 * (cb0 + y) + i16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (rb0 + x) + 4 * g + r;
+          const uint32_t off = (row < h && col < w) ? uint32_t((row * ldc + col) * 8) : 0x7FFFFFF0u;
+          acc[x][y][r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(prs, off, 0, 0));
+        }
+      }
+    }
+
+  const uint16_t* Ag = static_cast<const uint16_t*>(pa.A);
+  const uint16_t* Bg = static_cast<const uint16_t*>(pa.B);
+  u4 ra[C::ALD], rb[C::BLD];
+  // granule q of a stage: slice q / (rows*4), row (q % (rows*4)) / 4, k-octet q % 4
+  auto load = [&](const Triple& t, int kk) {
+    const int ks32 = int(pad_k(tri_ks(t)));
+    const uint16_t* ab = Ag + tri_a_off(t) + int64_t(it.r0) * ks32 + kk;
+    const uint16_t* bb = Bg + tri_b_off(t) + int64_t(it.c0) * ks32 + kk;
+    // rows past h (columns past w) fall outside the descriptor and read 0
+    const int na = uni(h * ks32 * 2), nb = uni(w * ks32 * 2);
+#pragma unroll
+    for (int p = 0; p < C::ALD; ++p) {
+      const int q = tid + C::NT * p;
+      const int s = q / (TM * 4), rem = q - s * (TM * 4);
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+          uni_ptr(const_cast<uint16_t*>(ab + s * pa.a_plane)), (short)0, na, kRsrcWord3b);
+      ra[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * ks32 + 8 * (rem & 3)) * 2), 0, 0);
+    }
+#pragma unroll
+    for (int p = 0; p < C::BLD; ++p) {
+      const int q = tid + C::NT * p;
+      const int s = q / (TN * 4), rem = q - s * (TN * 4);
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+          uni_ptr(const_cast<uint16_t*>(bb + s * pa.b_plane)), (short)0, nb, kRsrcWord3b);
+      rb[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * ks32 + 8 * (rem & 3)) * 2), 0, 0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < C::ALD; ++p) {
+      const int q = tid + C::NT * p;
+      const int s = q / (TM * 4), rem = q - s * (TM * 4);
+      *reinterpret_cast<u4*>(As + buf * C::ASZ + s * TM * C::RS + (rem >> 2) * C::RS + 8 * (rem & 3)) = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < C::BLD; ++p) {
+      const int q = tid + C::NT * p;
+      const int s = q / (TN * 4), rem = q - s * (TN * 4);
+      *reinterpret_cast<u4*>(Bs + buf * C::BSZ + s * TN * C::RS + (rem >> 2) * C::RS + 8 * (rem & 3)) = rb[p];
+    }
+  };
+
+  uint32_t te = it.tri_begin + it.tri_count;
+  uint32_t t = it.tri_begin;
+  if (a.k_lo > 0) t = uint32_t(uni(int(lower_bound_k3(a.tri, t, te, a.k_lo))));
+  if (a.k_hi < kNoKLimit) te = uint32_t(uni(int(lower_bound_k3(a.tri, t, te, a.k_hi))));
+  int kk = 0;
+  Triple tc;
+  if (t < te) {
+    tc = a.tri[t];
+    load(tc, 0);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  while (t < te) {
+    const int ks32 = int(pad_k(tri_ks(tc)));
+    uint32_t tn = t;
+    int kn = kk + C::KC;
+    Triple tnx = tc;
+    const bool triple_ends = kn >= ks32;
+    if (triple_ends) {
+      tn = t + 1;
+      kn = 0;
+      if (tn < te) tnx = a.tri[tn];
+    }
+    const bool more = tn < te;
+    if (more) load(tnx, kn);
+
+    if constexpr (NR > 0 && NC > 0) {
+      const uint16_t* as = As + buf * C::ASZ + (16 * rb0 + i16) * C::RS + 8 * g;
+      const uint16_t* bs = Bs + buf * C::BSZ + (16 * cb0 + i16) * C::RS + 8 * g;
+      bf8 af[3][NRA], bfr[3][NCA];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+#pragma unroll
+        for (int x = 0; x < NR; ++x)
+          af[s][x] = *reinterpret_cast<const bf8*>(as + s * TM * C::RS + 16 * x * C::RS);
+#pragma unroll
+        for (int y = 0; y < NC; ++y)
+          bfr[s][y] = *reinterpret_cast<const bf8*>(bs + s * TN * C::RS + 16 * y * C::RS);
+      }
+      // the six slice products, smallest first; consecutive MFMAs hit different accumulators
+      constexpr int PA[6] = {2, 1, 0, 1, 0, 0};
+      constexpr int PB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+      for (int m = 0; m < 6; ++m)
+#pragma unroll
+        for (int x = 0; x < NR; ++x)
+#pragma unroll
+          for (int y = 0; y < NC; ++y)
+            acc32[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[PA[m]][x], bfr[PB[m]][y], acc32[x][y], 0, 0, 0);
+      if (triple_ends) {
+#pragma unroll
+        for (int x = 0; x < NR; ++x)
+#pragma unroll
+          for (int y = 0; y < NC; ++y) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[x][y][r] += double(acc32[x][y][r]);
+            acc32[x][y] = (f4){0.f, 0.f, 0.f, 0.f};
+          }
+      }
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    t = tn;
+    kk = kn;
+    tc = tnx;
+  }
+
+  // epilogue (v_mfma_f32_16x16x32_bf16: register r of lane 16g + i holds row 4g + r, column i)
+  const double alpha = pa.alpha;
+#pragma unroll
+  for (int x = 0; x < NR; ++x)
+#pragma unroll
+    for (int y = 0; y < NC; ++y) {
+      const int col = 16 * (cb0 + y) + i16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (rb0 + x) + 4 * g + r;
+        if (row < h && col < w) {
+          const int64_t e = c_base + int64_t(row) * ldc + col;
+          if (a.win_last) {
+            const double v = alpha * acc[x][y][r];
+            pa.C[e] = a.accumulate ? v + pa.C[e] : v;
+          } else {
+            pa.P[e] = acc[x][y][r];
+          }
+        }
+      }
+    }
+}
+
+template <int TM, int TN, int NW, bool RESUME, int NR>
+__device__ __forceinline__ void dispatch_nc(int nc, const TileArgs& a, const Item& it,
+                                            const ProductArgs& pa, int wr, int wc, uint16_t* As,
+                                            uint16_t* Bs) {
+  constexpr int MC = B3Cfg<TM, TN, NW>::MC;
+  switch (nc) {
+    case 0: run_b3<TM, TN, NW, RESUME, NR, 0>(a, it, pa, wr, wc, As, Bs); break;
+    case 1: run_b3<TM, TN, NW, RESUME, NR, (1 <= MC ? 1 : MC)>(a, it, pa, wr, wc, As, Bs); break;
+    case 2: run_b3<TM, TN, NW, RESUME, NR, (2 <= MC ? 2 : MC)>(a, it, pa, wr, wc, As, Bs); break;
+    case 3: run_b3<TM, TN, NW, RESUME, NR, (3 <= MC ? 3 : MC)>(a, it, pa, wr, wc, As, Bs); break;
+    default: run_b3<TM, TN, NW, RESUME, NR, (4 <= MC ? 4 : MC)>(a, it, pa, wr, wc, As, Bs); break;
+  }
+}
+
+template <int TM, int TN, int KC, int NW, int OCC, bool RESUME>
+__global__ __launch_bounds__(64 * NW, OCC) void tiles_bf16x3(TileArgs a) {
+  using C = B3Cfg<TM, TN, NW>;
+  static_assert(KC == kSliceK && C::MC <= 4, "bf16 variant");
+  __shared__ __attribute__((aligned(16))) uint16_t As[2 * C::ASZ];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2 * C::BSZ];
+  const int x = blockIdx.x % kXcds, qx = blockIdx.x / kXcds;
+  const int idx = a.map.begin[x] + qx;
+  if (idx >= a.map.begin[x + 1]) return;
+  if (a.stamps && threadIdx.x == 0) a.stamps[2 * idx] = wall_clock64();
+  const Item it = a.items[idx];
+  const ProductArgs pa = a.prods ? a.prods[it.product] : a.single;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave / C::WC, wc = wave % C::WC;
+  const int nr = min(max(((it.h + 15) >> 4) - 2 * wr, 0), 2);
+  const int nc = min(max(((it.w + 15) >> 4) - C::MC * wc, 0), C::MC);
+  if (nr == 0) dispatch_nc<TM, TN, NW, RESUME, 0>(nc, a, it, pa, wr, wc, As, Bs);
+  else if (nr == 1) dispatch_nc<TM, TN, NW, RESUME, 1>(nc, a, it, pa, wr, wc, As, Bs);
+  else dispatch_nc<TM, TN, NW, RESUME, 2>(nc, a, it, pa, wr, wc, As, Bs);
+  if (a.stamps) {
+    __syncthreads();
+    if (threadIdx.x == 0) a.stamps[2 * idx + 1] = wall_clock64();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tiles_bf16x3(int variant, int64_t grid, const TileArgs& args, hipStream_t stream) {
+  if (grid <= 0) return hipSuccess;
+  const uint32_t grid32 = static_cast<uint32_t>(grid);
+#define BSM_B3_LAUNCH(ID, TM, TN, KC, NW, OCC)                                                    \
+  case ID:                                                                                        \
+    if (args.win_first)                                                                           \
+      hipLaunchKernelGGL((tiles_bf16x3<TM, TN, KC, NW, OCC, false>), dim3(grid32), dim3(64 * NW), \
+                         0, stream, args);                                                        \
+    else                                                                                          \
+      hipLaunchKernelGGL((tiles_bf16x3<TM, TN, KC, NW, OCC, true>), dim3(grid32), dim3(64 * NW),  \
+                         0, stream, args);                                                        \
+    break;
+  switch (variant) {
+    BSM_BF16_VARIANTS(BSM_B3_LAUNCH)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef BSM_B3_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace bsm

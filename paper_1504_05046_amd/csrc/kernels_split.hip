@@ -14,6 +14,94 @@ __global__ __launch_bounds__(256) void to_f32(const double* __restrict__ src,
     dst[i] = float(src[i]);
 }
 
+// Round to the nearest value with 8 significant bits (bf16 precision), ties to even, by adding
+// half an ulp of the 8-bit grid to the bit pattern.  Exact for finite values in FP32's normal
+// range; non-finite values are passed through.
+__device__ inline double round8(double a) {
+  uint64_t b = uint64_t(__double_as_longlong(a));
+  if (((b >> 52) & 0x7FF) == 0x7FF) return a;
+  b += ((uint64_t(1) << 44) - 1) + ((b >> 45) & 1);
+  b &= ~((uint64_t(1) << 45) - 1);
+  return __longlong_as_double(int64_t(b));
+}
+
+// Bits of a value that already has at most 8 significant bits, as bf16.
+__device__ inline uint16_t bf16_bits(double x) {
+  return uint16_t(__float_as_uint(float(x)) >> 16);
+}
+
+// a = a0 + a1 + a2 + (error below 2^-24 |a|): each slice is the residual rounded to 8 bits;
+// the residuals a - a0 and (a - a0) - a1 are exact in FP64.
+__device__ inline void split3(double a, uint16_t& s0, uint16_t& s1, uint16_t& s2) {
+  const double a0 = round8(a);
+  const double r1 = a - a0;
+  const double a1 = round8(r1);
+  const double a2 = round8(r1 - a1);
+  s0 = bf16_bits(a0);
+  s1 = bf16_bits(a1);
+  s2 = bf16_bits(a2);
+}
+
+// One workgroup per operand block: writes the block's three slices into the planes (plane p at
+// dst + p * plane), inner size padded with zeros to a multiple of 32; B blocks are transposed
+// through LDS in 32 x 64 tiles so that both the reads and the writes are coalesced.
+__global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict__ blocks,
+                                                    const double* __restrict__ src,
+                                                    uint16_t* __restrict__ dst, int64_t plane) {
+  __shared__ double tile[32][65];
+  const SplitBlock b = blocks[blockIdx.x];
+  const int ks32 = int(pad_k(b.ks));
+  const double* sb = src + b.src_off;
+  uint16_t* d0 = dst + b.dst_off;
+  uint16_t* d1 = d0 + plane;
+  uint16_t* d2 = d1 + plane;
+  if (!b.transpose) {
+    const int64_t n = int64_t(b.rows) * ks32;
+    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+      const int r = int(e / ks32), k = int(e - int64_t(r) * ks32);
+      const double v = k < b.ks ? sb[int64_t(r) * b.ld_src + k] : 0.0;
+      uint16_t x0, x1, x2;
+      split3(v, x0, x1, x2);
+      d0[e] = x0;
+      d1[e] = x1;
+      d2[e] = x2;
+    }
+    return;
+  }
+  // source: ks rows x `rows` columns (ld = ld_src); destination: `rows` x ks32
+  for (int c0 = 0; c0 < b.rows; c0 += 64) {
+    for (int k0 = 0; k0 < ks32; k0 += 32) {
+      for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
+        const int kk = e >> 6, cc = e & 63;
+        const int k = k0 + kk, c = c0 + cc;
+        tile[kk][cc] = (k < b.ks && c < b.rows) ? sb[int64_t(k) * b.ld_src + c] : 0.0;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
+        const int cc = e >> 5, kk = e & 31;
+        const int c = c0 + cc;
+        if (c < b.rows) {
+          uint16_t x0, x1, x2;
+          split3(tile[kk][cc], x0, x1, x2);
+          const int64_t o = int64_t(c) * ks32 + k0 + kk;
+          d0[o] = x0;
+          d1[o] = x1;
+          d2[o] = x2;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_split_bf16x3(const SplitBlock* blocks, int64_t nblocks, const double* src,
+                               uint16_t* dst, int64_t plane, hipStream_t stream) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_bf16x3, dim3(uint32_t(nblocks)), dim3(256), 0, stream, blocks, src, dst,
+                     plane);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;

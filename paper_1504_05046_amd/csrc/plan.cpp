@@ -217,7 +217,8 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   if (cfg.precision < 0 || cfg.precision > 2) return "unknown precision";
   if (cfg.sched < 0 || cfg.sched > 1) return "unknown scheduler";
   if (cfg.k_window < 0) return "negative k_window";
-  if (cfg.tile < 0 || cfg.tile > kNumVariants) return "unknown tile variant";
+  if (cfg.tile < 0 || cfg.tile > (cfg.precision == 2 ? kNumBf16Variants : kNumVariants))
+    return "unknown tile variant";
 
   p.cfg = cfg;
   p.M = M; p.K = K; p.N = N;
@@ -252,6 +253,40 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
     return "a tile buffer exceeds 2^48 elements";
   }
 
+  // split-bf16 form: operand blocks in the slice planes (inner size padded to 32; B transposed)
+  std::vector<int64_t> a_off32, b_off32;
+  const bool bf16 = cfg.precision == 2;
+  if (bf16) {
+    a_off32.assign(p.a_off.size(), -1);
+    b_off32.assign(p.b_off.size(), -1);
+    int64_t pos = 0;
+    for (int64_t i = 0; i < M; ++i)
+      for (int64_t k = 0; k < K; ++k) {
+        int64_t o = p.a_off[size_t(i * K + k)];
+        if (o < 0) continue;
+        a_off32[size_t(i * K + k)] = pos;
+        p.split_a.push_back(SplitBlock{o, pos, int32_t(p.rows[size_t(i)]), int32_t(p.inner[size_t(k)]),
+                                       int32_t(p.inner[size_t(k)]), 0});
+        pos += p.rows[size_t(i)] * pad_k(p.inner[size_t(k)]);
+      }
+    p.a_elems32 = pos;
+    pos = 0;
+    for (int64_t k = 0; k < K; ++k)
+      for (int64_t j = 0; j < N; ++j) {
+        int64_t o = p.b_off[size_t(k * N + j)];
+        if (o < 0) continue;
+        b_off32[size_t(k * N + j)] = pos;
+        p.split_b.push_back(SplitBlock{o, pos, int32_t(p.cols[size_t(j)]), int32_t(p.inner[size_t(k)]),
+                                       int32_t(p.cols[size_t(j)]), 1});
+        pos += p.cols[size_t(j)] * pad_k(p.inner[size_t(k)]);
+      }
+    p.b_elems32 = pos;
+    if (p.a_elems32 >= kMaxElems / 4 || p.b_elems32 >= kMaxElems / 4) {
+      *code = BSM_E_NOMEM;
+      return "slice planes exceed the descriptor range";
+    }
+  }
+
   // S3: k-lists (A row AND B column) and tasks
   std::vector<uint64_t> bt(size_t(N * wk), 0);  // B's shape transposed: column j's k bits
   for (int64_t k = 0; k < K; ++k)
@@ -277,8 +312,10 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
           int64_t k = w * 64 + __builtin_ctzll(x);
           x &= x - 1;
           Triple t;
-          t.a = uint64_t(p.a_off[size_t(i * K + k)]) | (uint64_t(p.inner[size_t(k)]) << 48);
-          t.b = uint64_t(p.b_off[size_t(k * N + j)]) | (uint64_t(k) << 48);
+          const int64_t ao = bf16 ? a_off32[size_t(i * K + k)] : p.a_off[size_t(i * K + k)];
+          const int64_t bo = bf16 ? b_off32[size_t(k * N + j)] : p.b_off[size_t(k * N + j)];
+          t.a = uint64_t(ao) | (uint64_t(p.inner[size_t(k)]) << 48);
+          t.b = uint64_t(bo) | (uint64_t(k) << 48);
           p.tri.push_back(t);
           sk += double(p.inner[size_t(k)]);
         }
@@ -290,10 +327,10 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
       }
       int m = int(p.rows[size_t(i)]), n = int(p.cols[size_t(j)]);
       p.useful_flops += 2.0 * m * n * sk;
-      int v = pick_variant(m, n, cfg.tile);
-      const CutChoice& cut = best_cut((m + 15) / 16, (n + 15) / 16, kVariants[v].tm / 16,
-                                      kVariants[v].tn / 16, kVariants[v].nw, cfg.cut_search,
-                                      cut_memo);
+      const int v = bf16 ? 0 : pick_variant(m, n, cfg.tile);
+      const Variant& var = bf16 ? kBf16Variants[v] : kVariants[v];
+      const CutChoice& cut = best_cut((m + 15) / 16, (n + 15) / 16, var.tm / 16, var.tn / 16,
+                                      var.nw, cfg.cut_search, cut_memo);
       pieces_to_ranges(cut.rows, m, rs);
       pieces_to_ranges(cut.cols, n, cs);
       for (auto& r : rs)

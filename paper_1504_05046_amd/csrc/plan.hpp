@@ -15,9 +15,11 @@ struct Variant {
 };
 #define BSM_VARIANT_ROW(ID, TM, TN, KC, NW, OCC) {TM, TN, NW},
 constexpr Variant kVariants[] = {BSM_TILE_VARIANTS(BSM_VARIANT_ROW)};
-#undef BSM_VARIANT_ROW
 constexpr int kNumVariants = int(sizeof(kVariants) / sizeof(kVariants[0]));
 constexpr int kDefaultVariant = 0;  // 128 x 128, 8 waves
+constexpr Variant kBf16Variants[] = {BSM_BF16_VARIANTS(BSM_VARIANT_ROW)};
+constexpr int kNumBf16Variants = int(sizeof(kBf16Variants) / sizeof(kBf16Variants[0]));
+#undef BSM_VARIANT_ROW
 
 enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1 };
 
@@ -45,6 +47,9 @@ struct HostPlan {
   std::vector<Item> items;       // tasks in execution order, grouped by XCD
   std::vector<double> cost;      // scheduler cost of items[q]
   std::vector<float> features;   // 5 per item: log h, log w, log sum_k, log #k, density
+  // split-bf16 form: slice-plane layout of A and B and the split pass's block table
+  int64_t a_elems32 = 0, b_elems32 = 0;
+  std::vector<SplitBlock> split_a, split_b;
   int32_t xcd_begin[kXcds + 1] = {0};
   int64_t k_window_eff = 0;      // inner blocks per k-window
   int64_t windows = 1;           // number of k-windows

@@ -25,6 +25,27 @@ constexpr int kXcds = 8;                       // MI355X: 8 accelerator dies, ea
   X(2, 64, 64, 16, 4, 3)        \
   X(3, 32, 32, 16, 4, 4)
 
+// Split-bf16 tile variants (same fields; the k-chunk is one 32-deep bf16 MFMA step).
+#define BSM_BF16_VARIANTS(X) \
+  X(0, 128, 128, 32, 8, 2)
+
+// Slice planes of the split-bf16 form: each block with its inner size padded to a multiple of 32
+// (zeros), A blocks row-major (rows x s32), B blocks transposed (cols x s32), so that both MFMA
+// operands read 8 consecutive k per lane.
+constexpr int kSliceK = 32;
+BSM_HD inline int64_t pad_k(int64_t ks) { return (ks + kSliceK - 1) / kSliceK * kSliceK; }
+
+// One block of an operand as the split pass sees it: src_off in the packed FP64 tiles, dst_off in
+// a slice plane, `rows` output rows (A rows, or B columns when transposed), inner size ks.
+struct SplitBlock {
+  int64_t src_off;
+  int64_t dst_off;
+  int32_t rows;
+  int32_t ks;
+  int32_t ld_src;     // leading dimension of the source block (ks for A, the B block's width)
+  int32_t transpose;  // 1: the source is ks x rows (B) and is written transposed
+};
+
 // One (i,k,j) block triple of a C block's k-list: where A_ik and B_kj start and the inner block
 // size.  a = A offset | (s_k << 48);  b = B offset | (k << 48).
 struct Triple {
@@ -58,6 +79,7 @@ struct ProductArgs {
   double* C;
   double* P;
   double alpha;
+  int64_t a_plane, b_plane;  // split-bf16 form: elements between consecutive slice planes
 };
 
 }  // namespace bsm

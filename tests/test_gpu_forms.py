@@ -71,7 +71,58 @@ def test_fp32_alpha_accumulate_and_alias():
     assert rel_fro(got, ref(q)) <= 1e-5
 
 
-@pytest.mark.parametrize("precision", [bsm.FP64, bsm.FP32])
+@pytest.mark.parametrize("seed", range(3))
+def test_bf16x3_form_error_gate(seed):
+    p = gen.random_problem(1700 + seed, 8, 9, 7, 1, 200, 0.4, 0.5)
+    _say(f"[bf16x3] {p.name} seed={seed}")
+    got, _ = run(p, precision=bsm.BF16X3)
+    assert np.all(np.isfinite(got))
+    err = rel_fro(got, ref(p))
+    assert err <= 1e-6, err
+
+
+def test_bf16x3_form_scaled_blocks():
+    """Block values scaled by 10^U(-4,0) as in the precision workload, at a small size."""
+    p = gen.nonuniform(4101, 1500, 64, 256, 0.4, draw=gen._scaled_normal(4101), name="prec_small")
+    got, _ = run(p, precision=bsm.BF16X3)
+    err = rel_fro(got, ref(p))
+    _say(f"[bf16x3] scaled rel err {err:.3e}")
+    assert err <= 1e-6, err
+
+
+def test_bf16x3_ragged_sizes():
+    sizes = [1, 3, 15, 16, 17, 31, 33, 63, 64, 65, 127, 129, 255, 256]
+    rng = np.random.default_rng(17)
+    rows, inner, cols = rng.permutation(sizes), rng.permutation(sizes), rng.permutation(sizes)
+    a_mask = rng.random((len(rows), len(inner))) < 0.4
+    b_mask = rng.random((len(inner), len(cols))) < 0.4
+    p = gen.make_problem("ragged_b3", 17, rows, inner, cols, a_mask, b_mask)
+    got, _ = run(p, precision=bsm.BF16X3)
+    assert rel_fro(got, ref(p)) <= 1e-6
+
+
+def test_bf16x3_integer_inputs_bit_exact():
+    """Integers in [-8, 8] are exact in bf16 (the second and third slices are 0) and their block
+    sums stay below 2^24, so the split form reproduces the FP64 result bit for bit."""
+    p = gen.integer_problem(1750, 6, 7, 5, 1, 200, 0.6, 0.6)
+    got, _ = run(p, precision=bsm.BF16X3)
+    assert np.array_equal(got, ref(p))
+
+
+def test_bf16x3_alpha_accumulate_and_alias():
+    p = gen.random_problem(1760, 5, 6, 5, 10, 140, 0.6, 0.6)
+    C0 = np.random.default_rng(2).standard_normal(ref(p).size)
+    got, _ = run(p, precision=bsm.BF16X3, alpha=-0.5, C0=C0)
+    assert rel_fro(got, ref(p, -0.5, C0)) <= 1e-6
+    rows = np.array([10, 25, 40, 60, 25])
+    mask = np.random.default_rng(3).random((5, 5)) < 0.6
+    np.fill_diagonal(mask, True)
+    q = gen.make_problem("alias", 9, rows, rows, rows, mask, mask, b_is_a=True)
+    got, _ = run(q, precision=bsm.BF16X3)
+    assert rel_fro(got, ref(q)) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", [bsm.FP64, bsm.FP32, bsm.BF16X3])
 def test_k_window_bitwise_invariant(precision):
     """Issuing the k-iterations I at a time (I = 1, 2, 3, K) gives the same bits."""
     p = gen.random_problem(800 + precision, 7, 9, 6, 8, 150, 0.6, 0.6)
