@@ -70,6 +70,8 @@ typedef struct {
   int64_t k_window;       /* k-iterations in flight at once (multiple issue, Sec. 3.2): 0 = all K */
   int32_t record_timings; /* 1 = record each task's start/end clock for bsm_plan_timings */
   int32_t tile;           /* 0 = chosen by the library; otherwise a tile variant id (bsm_tile_*) */
+  int32_t use_graph;      /* 1 = bsm_execute captures its launches into a hipGraph and replays it
+                             while the operands, alpha and accumulate stay the same */
 } bsm_options;
 
 typedef struct {
@@ -81,7 +83,10 @@ typedef struct {
   double useful_flops;     /* 2 * sum over triples of r_i s_k t_j */
   int64_t workspace_bytes; /* device memory the plan holds besides the caller's buffers */
   int64_t k_windows;       /* launches per execute: ceil(K / k_window) */
+  int32_t tile;            /* tile variant in use (variant id + 1) */
 } bsm_plan_info;
+
+typedef struct bsm_batch bsm_batch;
 
 typedef struct bsm_plan bsm_plan;
 
@@ -126,8 +131,58 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
 bsm_status bsm_plan_timings(bsm_plan* plan, float* features, float* seconds, int64_t n,
                             void* stream);
 
+/* The cost-model features of every task in the current task order (n x 5 floats, host; n = task
+ * count): log h, log w, log (summed inner size of the k-list), log (number of k-list blocks),
+ * k-list density.  Host-only. */
+bsm_status bsm_plan_features(const bsm_plan* plan, float* features, int64_t n);
+
+/* Re-order and re-bin the tasks by the given per-task costs (n floats, host, >= 0, in the current
+ * task order; e.g. a cost model's predictions).  Only the schedule changes: every task still runs
+ * once and C is bitwise the same.  The new order is uploaded at the next execute. */
+bsm_status bsm_plan_set_costs(bsm_plan* plan, const float* costs, int64_t n);
+
+/* Autotuner: time every tile variant of the plan's precision form on the given operands (C is
+ * overwritten with A B) and keep the fastest; *chosen (may be NULL) receives its id + 1.  When the
+ * environment variable BSM_TUNE_CACHE names a file, choices are looked up there by a workload
+ * signature first and appended after tuning.  Synchronises `stream`. */
+bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, double* dC,
+                        void* stream, int32_t* chosen);
+
 /* Release the plan (waits for its device work first).  NULL is accepted. */
 bsm_status bsm_plan_destroy(bsm_plan* plan);
+
+/* ---- batches: many independent products in one launch ---------------------------------------
+ * A batch concatenates the tasks of n plans (same precision and tile variant, k_window 0) into one
+ * task list and one schedule; bsm_batch_execute captures every member's operand conversion plus one
+ * tile-kernel launch over all tasks into a hipGraph and replays it while the operand pointers,
+ * alphas and accumulate stay the same.  The plans must outlive the batch and must not run
+ * elsewhere while the batch executes. */
+bsm_status bsm_batch_create(bsm_batch** out, bsm_plan* const* plans, int64_t n);
+
+/* Task count, total useful flops and tile variant (id + 1) of a batch (any pointer may be NULL). */
+bsm_status bsm_batch_query(const bsm_batch* batch, int64_t* tasks, double* useful_flops,
+                           int32_t* tile);
+
+/* C_q = alphas[q] A_q B_q (+ C_q) for every member q.  alphas, dA, dB, dC: host arrays of n
+ * entries (alphas may be NULL = all 1); the pointers they hold are device buffers as for
+ * bsm_execute. */
+bsm_status bsm_batch_execute(bsm_batch* batch, const double* alphas, const double* const* dA,
+                             const double* const* dB, double* const* dC, int accumulate,
+                             void* stream);
+
+/* Per-task features and durations of the last batch execute (members created with
+ * record_timings = 1), as bsm_plan_timings; n = the batch's task count. */
+bsm_status bsm_batch_timings(bsm_batch* batch, float* features, float* seconds, int64_t n,
+                             void* stream);
+
+/* Re-order and re-bin the batch's tasks by per-task costs, as bsm_plan_set_costs. */
+bsm_status bsm_batch_set_costs(bsm_batch* batch, const float* costs, int64_t n);
+
+/* Autotuner over the whole batch (every member is re-cut for the chosen variant). */
+bsm_status bsm_batch_autotune(bsm_batch* batch, const double* const* dA, const double* const* dB,
+                              double* const* dC, void* stream, int32_t* chosen);
+
+bsm_status bsm_batch_destroy(bsm_batch* batch);
 
 /* Eq. 1: how many SUMMA iterations are issued at once on a P_row x P_col process grid with K
  * inner blocks: 2 if either grid dimension is below 2, K if both are at least K, else

@@ -32,7 +32,7 @@ class BsmError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sched", ctypes.c_int32),
                 ("k_window", ctypes.c_int64), ("record_timings", ctypes.c_int32),
-                ("tile", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -42,7 +42,7 @@ class PlanInfo(ctypes.Structure):
                 ("b_elems", ctypes.c_int64), ("c_elems", ctypes.c_int64),
                 ("triples", ctypes.c_int64), ("tasks", ctypes.c_int64),
                 ("useful_flops", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
-                ("k_windows", ctypes.c_int64)]
+                ("k_windows", ctypes.c_int64), ("tile", ctypes.c_int32)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -72,8 +72,21 @@ def load() -> ctypes.CDLL:
     L.bsm_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
     L.bsm_plan_destroy.argtypes = [_p]
     L.bsm_plan_timings.argtypes = [_p, _p, _p, _i64, _p]
+    L.bsm_plan_features.argtypes = [_p, _p, _i64]
+    L.bsm_plan_set_costs.argtypes = [_p, _p, _i64]
+    L.bsm_autotune.argtypes = [_p, _p, _p, _p, _p, _p]
+    L.bsm_batch_create.argtypes = [ctypes.POINTER(_p), _p, _i64]
+    L.bsm_batch_query.argtypes = [_p, _p, _p, _p]
+    L.bsm_batch_execute.argtypes = [_p, _p, _p, _p, _p, ctypes.c_int, _p]
+    L.bsm_batch_timings.argtypes = [_p, _p, _p, _i64, _p]
+    L.bsm_batch_set_costs.argtypes = [_p, _p, _i64]
+    L.bsm_batch_autotune.argtypes = [_p, _p, _p, _p, _p, _p]
+    L.bsm_batch_destroy.argtypes = [_p]
     for name in ("bsm_plan_create", "bsm_plan_query", "bsm_plan_c_shape", "bsm_plan_c_offsets",
-                 "bsm_execute", "bsm_plan_destroy", "bsm_plan_timings"):
+                 "bsm_execute", "bsm_plan_destroy", "bsm_plan_timings", "bsm_plan_features",
+                 "bsm_plan_set_costs", "bsm_autotune", "bsm_batch_create", "bsm_batch_query",
+                 "bsm_batch_execute", "bsm_batch_timings", "bsm_batch_set_costs",
+                 "bsm_batch_autotune", "bsm_batch_destroy"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -96,10 +109,12 @@ def _arr(a, dtype):
     return np.ascontiguousarray(np.asarray(a, dtype=dtype))
 
 
-def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, tile=0) -> Options:
+def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, tile=0,
+            use_graph=0) -> Options:
     o = Options()
     load().bsm_options_default(ctypes.byref(o))
     o.precision, o.sched, o.k_window, o.record_timings, o.tile = precision, sched, k_window, record_timings, tile
+    o.use_graph = use_graph
     return o
 
 
@@ -130,6 +145,26 @@ def _dev_ptr(t) -> int:
     if t is None:
         return 0
     return t.data_ptr()
+
+
+def _check_operands(info, A, B, C):
+    """Device buffers handed to the library must hold the plan's element counts and be FP64,
+    contiguous device tensors (the C ABI only sees the pointers)."""
+    bufs = (("A", A, info.a_elems), ("B", B, info.b_elems), ("C", C, info.c_elems))
+    for name, t, need in bufs:
+        if need > 0 and t is None:
+            raise ValueError(f"{name} is required ({need} elements)")
+        if need > 0 and t.numel() < need:
+            raise ValueError(f"{name} holds {t.numel()} elements, the plan needs {need}")
+    for name, t, need in bufs:
+        if need <= 0 or t is None:
+            continue
+        if getattr(t, "dtype", None) is not None and str(t.dtype) != "torch.float64":
+            raise ValueError(f"{name} must be float64, got {t.dtype}")
+        if hasattr(t, "is_contiguous") and not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if hasattr(t, "is_cuda") and not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
 
 
 class Plan:
@@ -175,6 +210,7 @@ class Plan:
 
     def execute(self, A, B, C, alpha: float = 1.0, accumulate: bool = False, stream=None):
         """C = alpha*A*B (+C); A, B, C are FP64 device tensors holding the packed tiles."""
+        _check_operands(self.info(), A, B, C)
         _check(load().bsm_execute(self._h, float(alpha), _dev_ptr(A), _dev_ptr(B), _dev_ptr(C),
                                   int(bool(accumulate)), _stream_handle(stream)))
 
@@ -186,9 +222,94 @@ class Plan:
         _check(load().bsm_plan_timings(self._h, f.ctypes.data, t.ctypes.data, n, _stream_handle(stream)))
         return f, t
 
+    def features(self) -> np.ndarray:
+        n = self.info().tasks
+        f = np.zeros((n, 5), dtype=np.float32)
+        _check(load().bsm_plan_features(self._h, f.ctypes.data, n))
+        return f
+
+    def set_costs(self, costs):
+        c = _arr(costs, np.float32)
+        _check(load().bsm_plan_set_costs(self._h, c.ctypes.data, c.size))
+
+    def autotune(self, A, B, C, stream=None) -> int:
+        _check_operands(self.info(), A, B, C)
+        chosen = ctypes.c_int32(0)
+        _check(load().bsm_autotune(self._h, _dev_ptr(A), _dev_ptr(B), _dev_ptr(C),
+                                   _stream_handle(stream), ctypes.byref(chosen)))
+        return int(chosen.value)
+
     def close(self):
         if getattr(self, "_h", None):
             _check(load().bsm_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(xs):
+    arr = (ctypes.c_void_p * len(xs))()
+    for q, x in enumerate(xs):
+        arr[q] = _dev_ptr(x) if x is not None else 0
+    return arr
+
+
+class Batch:
+    """Many independent products executed as one graph-captured launch."""
+
+    def __init__(self, plans):
+        self._plans = list(plans)  # keep the member plans alive
+        hs = (ctypes.c_void_p * len(self._plans))(*[p.handle.value for p in self._plans])
+        h = _p()
+        _check(load().bsm_batch_create(ctypes.byref(h), hs, len(self._plans)))
+        self._h = h
+
+    def query(self):
+        t = ctypes.c_int64(0)
+        f = ctypes.c_double(0)
+        v = ctypes.c_int32(0)
+        _check(load().bsm_batch_query(self._h, ctypes.byref(t), ctypes.byref(f), ctypes.byref(v)))
+        return int(t.value), float(f.value), int(v.value)
+
+    def execute(self, As, Bs, Cs, alphas=None, accumulate=False, stream=None):
+        n = len(self._plans)
+        if not (len(As) == len(Bs) == len(Cs) == n):
+            raise ValueError("one A, B and C per member plan")
+        for p, A, B, C in zip(self._plans, As, Bs, Cs):
+            _check_operands(p.info(), A, B, C)
+        al = None
+        if alphas is not None:
+            al = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64))
+        _check(load().bsm_batch_execute(self._h, al.ctypes.data if al is not None else None,
+                                        _ptr_array(As), _ptr_array(Bs), _ptr_array(Cs),
+                                        int(bool(accumulate)), _stream_handle(stream)))
+
+    def timings(self, stream=None):
+        n = self.query()[0]
+        f = np.zeros((n, 5), dtype=np.float32)
+        t = np.zeros(n, dtype=np.float32)
+        _check(load().bsm_batch_timings(self._h, f.ctypes.data, t.ctypes.data, n, _stream_handle(stream)))
+        return f, t
+
+    def set_costs(self, costs):
+        c = _arr(costs, np.float32)
+        _check(load().bsm_batch_set_costs(self._h, c.ctypes.data, c.size))
+
+    def autotune(self, As, Bs, Cs, stream=None) -> int:
+        for p, A, B, C in zip(self._plans, As, Bs, Cs):
+            _check_operands(p.info(), A, B, C)
+        chosen = ctypes.c_int32(0)
+        _check(load().bsm_batch_autotune(self._h, _ptr_array(As), _ptr_array(Bs), _ptr_array(Cs),
+                                         _stream_handle(stream), ctypes.byref(chosen)))
+        return int(chosen.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().bsm_batch_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -1,7 +1,12 @@
 // C ABI of the library (declared in include/bsm.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,20 +28,359 @@ static bsm_status hip_fail(hipError_t e, const char* what) {
   return fail(BSM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+#define BSM_HIP(call, what)                          \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------------
+// Device copies of a task list: tasks, triples, optional per-task clocks.
+struct TaskSet {
+  Item* items = nullptr;
+  Triple* tri = nullptr;
+  uint64_t* stamps = nullptr;
+  size_t n_items = 0, n_tri = 0;
+  bool timed = false;  // a launch has recorded clocks since the tasks last changed
+
+  void release() {
+    if (items) (void)hipFree(items);
+    if (tri) (void)hipFree(tri);
+    if (stamps) (void)hipFree(stamps);
+    items = nullptr;
+    tri = nullptr;
+    stamps = nullptr;
+    n_items = n_tri = 0;
+  }
+
+  // (Re-)upload tasks (always) and triples (when their count changed); clocks if asked for.
+  bsm_status upload(const HostPlan& h, bool with_stamps) {
+    if (h.items.size() != n_items) {
+      if (items) (void)hipFree(items);
+      if (stamps) (void)hipFree(stamps);
+      items = nullptr;
+      stamps = nullptr;
+      n_items = h.items.size();
+      if (n_items) BSM_HIP(hipMalloc(&items, n_items * sizeof(Item)), "hipMalloc(tasks)");
+    }
+    if (n_items)
+      BSM_HIP(hipMemcpy(items, h.items.data(), n_items * sizeof(Item), hipMemcpyHostToDevice),
+              "hipMemcpy(tasks)");
+    if (h.tri.size() != n_tri) {
+      if (tri) (void)hipFree(tri);
+      tri = nullptr;
+      n_tri = h.tri.size();
+      if (n_tri) BSM_HIP(hipMalloc(&tri, n_tri * sizeof(Triple)), "hipMalloc(triples)");
+    }
+    if (n_tri)
+      BSM_HIP(hipMemcpy(tri, h.tri.data(), n_tri * sizeof(Triple), hipMemcpyHostToDevice),
+              "hipMemcpy(triples)");
+    if (with_stamps && !stamps && n_items)
+      BSM_HIP(hipMalloc(&stamps, n_items * 16), "hipMalloc(clocks)");
+    timed = false;
+    return BSM_OK;
+  }
+};
+
+// A captured launch sequence, replayed while its arguments stay the same.  Capture happens on a
+// private stream; the instantiated graph is launched on the caller's stream.
+struct GraphCache {
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uint64_t> key;
+  bool valid = false;
+
+  void invalidate() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    valid = false;
+  }
+  void release() {
+    invalidate();
+    if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
+  }
+  bsm_status run(const std::vector<uint64_t>& k, const std::function<bsm_status(hipStream_t)>& body,
+                 hipStream_t stream) {
+    if (!valid || k != key) {
+      invalidate();
+      if (!cap) BSM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
+      BSM_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      bsm_status st = body(cap);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(cap, &g);
+      if (st != BSM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      graph = g;
+      BSM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+      key = k;
+      valid = true;
+    }
+    BSM_HIP(hipGraphLaunch(exec, stream), "hipGraphLaunch");
+    return BSM_OK;
+  }
+};
+
+static uint64_t bits_of(double d) {
+  uint64_t u;
+  std::memcpy(&u, &d, 8);
+  return u;
+}
+
+// ------------------------------------------------------------------------------------------------
 struct bsm_plan {
   HostPlan hp;
-  Item* d_items = nullptr;
-  Triple* d_tri = nullptr;
-  void* d_opA = nullptr;         // converted operands of the reduced-precision forms
+  TaskSet ts;
+  void* d_opA = nullptr;            // converted operands of the reduced-precision forms
   void* d_opB = nullptr;
   SplitBlock* d_split_a = nullptr;  // split-bf16 form: block tables of the split pass
   SplitBlock* d_split_b = nullptr;
-  double* d_partial = nullptr;   // raw sums between k-windows (laid out like C)
-  uint64_t* d_stamps = nullptr;  // per-task start/end clocks
+  double* d_partial = nullptr;      // raw sums between k-windows (laid out like C)
+  GraphCache gc;
   int device = -1;
-  bool uploaded = false;
-  bool timed = false;            // an execute has recorded timings
+  bool ready = false;               // device buffers allocated
+  bool tasks_dirty = true;          // host tasks changed since the last upload
+  int use_graph = 0;
 };
+
+struct bsm_batch {
+  std::vector<bsm_plan*> members;
+  HostPlan hp;                      // merged tasks
+  TaskSet ts;
+  ProductArgs* d_prods = nullptr;
+  std::vector<ProductArgs> h_prods;
+  GraphCache gc;
+  bool tasks_dirty = true;
+};
+
+static bsm_status check_device(int* dev) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return fail(BSM_E_UNSUPPORTED, std::string("no HIP device: ") + hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, *dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(BSM_E_UNSUPPORTED, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+  return BSM_OK;
+}
+
+// Device buffers of a plan other than its task list.
+static bsm_status prepare(bsm_plan* p) {
+  if (p->ready) return BSM_OK;
+  int dev;
+  bsm_status st = check_device(&dev);
+  if (st != BSM_OK) return st;
+  const HostPlan& h = p->hp;
+  if (h.cfg.precision == BSM_FP32) {
+    if (h.a_elems > 0) BSM_HIP(hipMalloc(&p->d_opA, size_t(h.a_elems) * 4), "hipMalloc(A fp32)");
+    if (h.b_elems > 0) BSM_HIP(hipMalloc(&p->d_opB, size_t(h.b_elems) * 4), "hipMalloc(B fp32)");
+  }
+  if (h.cfg.precision == BSM_BF16X3) {
+    if (h.a_elems32 > 0) BSM_HIP(hipMalloc(&p->d_opA, size_t(h.a_elems32) * 6), "hipMalloc(A slices)");
+    if (h.b_elems32 > 0) BSM_HIP(hipMalloc(&p->d_opB, size_t(h.b_elems32) * 6), "hipMalloc(B slices)");
+    const size_t na = h.split_a.size() * sizeof(SplitBlock), nb = h.split_b.size() * sizeof(SplitBlock);
+    if (na) {
+      BSM_HIP(hipMalloc(&p->d_split_a, na), "hipMalloc(split table)");
+      BSM_HIP(hipMemcpy(p->d_split_a, h.split_a.data(), na, hipMemcpyHostToDevice), "hipMemcpy(split table)");
+    }
+    if (nb) {
+      BSM_HIP(hipMalloc(&p->d_split_b, nb), "hipMalloc(split table)");
+      BSM_HIP(hipMemcpy(p->d_split_b, h.split_b.data(), nb, hipMemcpyHostToDevice), "hipMemcpy(split table)");
+    }
+  }
+  if (h.windows > 1 && h.c_elems > 0)
+    BSM_HIP(hipMalloc(&p->d_partial, size_t(h.c_elems) * 8), "hipMalloc(partial)");
+  p->device = dev;
+  p->ready = true;
+  return BSM_OK;
+}
+
+static bsm_status sync_tasks(bsm_plan* p) {
+  if (!p->tasks_dirty) return BSM_OK;
+  bsm_status st = p->ts.upload(p->hp, p->hp.cfg.record_timings != 0);
+  if (st != BSM_OK) return st;
+  p->tasks_dirty = false;
+  p->gc.invalidate();
+  return BSM_OK;
+}
+
+// S6: operands in the precision form's element type and layout (queued on s).
+static bsm_status enqueue_convert(bsm_plan* p, const double* dA, const double* dB, hipStream_t s,
+                                  ProductArgs& pa) {
+  const HostPlan& h = p->hp;
+  pa.A = dA;
+  pa.B = dB;
+  pa.a_plane = pa.b_plane = 0;
+  if (h.cfg.precision == BSM_FP32) {
+    BSM_HIP(launch_to_f32(dA, static_cast<float*>(p->d_opA), h.a_elems, s), "convert A");
+    pa.A = p->d_opA;
+    if (dB == dA && h.b_elems == h.a_elems) {
+      pa.B = p->d_opA;  // C = A A: one conversion
+    } else {
+      BSM_HIP(launch_to_f32(dB, static_cast<float*>(p->d_opB), h.b_elems, s), "convert B");
+      pa.B = p->d_opB;
+    }
+  } else if (h.cfg.precision == BSM_BF16X3) {
+    pa.a_plane = h.a_elems32;
+    pa.b_plane = h.b_elems32;
+    BSM_HIP(launch_split_bf16x3(p->d_split_a, int64_t(h.split_a.size()), dA,
+                                static_cast<uint16_t*>(p->d_opA), pa.a_plane, s), "split A");
+    BSM_HIP(launch_split_bf16x3(p->d_split_b, int64_t(h.split_b.size()), dB,
+                                static_cast<uint16_t*>(p->d_opB), pa.b_plane, s), "split B");
+    pa.A = p->d_opA;
+    pa.B = p->d_opB;
+  }
+  return BSM_OK;
+}
+
+static hipError_t launch_form(int precision, int variant, int64_t grid, const TileArgs& a,
+                              hipStream_t s) {
+  if (precision == BSM_FP64) return launch_tiles_f64(variant, grid, a, s);
+  if (precision == BSM_FP32) return launch_tiles_f32(variant, grid, a, s);
+  return launch_tiles_bf16x3(variant, grid, a, s);
+}
+
+// S7/S8 (and S5): the tile kernel over a task list, once per k-window.
+static bsm_status enqueue_tiles(const HostPlan& h, TaskSet& ts, const ProductArgs* prods,
+                                const ProductArgs& single, int accumulate, hipStream_t s) {
+  if (h.items.empty()) return BSM_OK;
+  TileArgs a{};
+  a.items = ts.items;
+  a.tri = ts.tri;
+  for (int x = 0; x <= kXcds; ++x) a.map.begin[x] = h.xcd_begin[x];
+  a.prods = prods;
+  a.single = single;
+  a.accumulate = accumulate;
+  a.stamps = ts.stamps;
+  // k-windows of I consecutive inner blocks, issued in order on the stream; each window resumes
+  // from the raw FP64 sums of the previous one, so C does not depend on I
+  const int64_t I = h.k_window_eff;
+  for (int64_t wdx = 0; wdx < h.windows; ++wdx) {
+    a.k_lo = int(wdx * I);
+    a.k_hi = wdx + 1 == h.windows ? kNoKLimit : int((wdx + 1) * I);
+    a.win_first = wdx == 0;
+    a.win_last = wdx + 1 == h.windows;
+    BSM_HIP(launch_form(h.cfg.precision, h.variant, h.grid, a, s), "tile kernel launch");
+  }
+  if (ts.stamps) ts.timed = true;
+  return BSM_OK;
+}
+
+static bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {
+  if (na <= 0 || nb <= 0) return false;
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+static bsm_status check_operands(const HostPlan& h, const double* dA, const double* dB,
+                                 const double* dC, int accumulate) {
+  if ((h.a_elems > 0 && !dA) || (h.b_elems > 0 && !dB) || (h.c_elems > 0 && !dC))
+    return fail(BSM_E_INVALID, "null tile buffer");
+  if (overlaps(dC, h.c_elems * 8, dA, h.a_elems * 8) || overlaps(dC, h.c_elems * 8, dB, h.b_elems * 8))
+    return fail(BSM_E_INVALID, "C overlaps A or B");
+  if (accumulate != 0 && accumulate != 1) return fail(BSM_E_INVALID, "accumulate must be 0 or 1");
+  return BSM_OK;
+}
+
+static bsm_status timings_of(const HostPlan& h, TaskSet& ts, float* features, float* seconds,
+                             int64_t n, void* stream) {
+  if (n != int64_t(h.items.size())) return fail(BSM_E_MISMATCH, "n must equal the task count");
+  if (!ts.timed) return fail(BSM_E_STATE, "no execute with record_timings has run since the tasks last changed");
+  if (n == 0) return BSM_OK;
+  if (!features && !seconds) return fail(BSM_E_INVALID, "null output");
+  BSM_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "hipStreamSynchronize");
+  std::vector<uint64_t> st(size_t(n) * 2);
+  BSM_HIP(hipMemcpy(st.data(), ts.stamps, st.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy(clocks)");
+  for (int64_t q = 0; q < n; ++q) {
+    // the constant clock runs at 100 MHz
+    if (seconds) seconds[q] = float(double(st[size_t(2 * q + 1)] - st[size_t(2 * q)]) * 1e-8);
+    if (features)
+      for (int f = 0; f < 5; ++f) features[q * 5 + f] = h.features[size_t(q * 5 + f)];
+  }
+  return BSM_OK;
+}
+
+static bsm_status set_costs(HostPlan& h, const float* costs, int64_t n) {
+  if (n != int64_t(h.items.size())) return fail(BSM_E_MISMATCH, "n must equal the task count");
+  if (n > 0 && !costs) return fail(BSM_E_INVALID, "null costs");
+  std::vector<double> c(static_cast<size_t>(n));
+  for (int64_t q = 0; q < n; ++q) {
+    if (!(costs[q] >= 0.f) || !std::isfinite(costs[q])) return fail(BSM_E_INVALID, "costs must be finite and >= 0");
+    c[size_t(q)] = costs[q];
+  }
+  schedule(h, c);
+  return BSM_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Autotuning: time each tile variant on the caller's operands and keep the fastest.  Choices are
+// remembered per workload signature in the file named by BSM_TUNE_CACHE (lines "key variant").
+static std::string tune_key(const std::vector<const HostPlan*>& parts) {
+  double nb = 0, sm = 0, sn = 0, sk = 0;
+  for (const HostPlan* p : parts)
+    for (const CBlock& c : p->cblocks) {
+      nb += 1;
+      sm += c.m;
+      sn += c.n;
+      sk += c.sk;
+    }
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "gfx950/p%d/b%zu/c%.0f/m%.0f/n%.0f/k%.0f", parts[0]->cfg.precision,
+                parts.size(), nb, nb > 0 ? sm / nb : 0, nb > 0 ? sn / nb : 0, nb > 0 ? sk / nb : 0);
+  return buf;
+}
+
+static int tune_cache_lookup(const std::string& key) {
+  const char* path = std::getenv("BSM_TUNE_CACHE");
+  if (!path) return -1;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return -1;
+  char k[256];
+  int v, found = -1;
+  while (std::fscanf(f, "%255s %d", k, &v) == 2)
+    if (key == k) found = v;
+  std::fclose(f);
+  return found;
+}
+
+static void tune_cache_store(const std::string& key, int v) {
+  const char* path = std::getenv("BSM_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d\n", key.c_str(), v);
+  std::fclose(f);
+}
+
+static bsm_status time_body(const std::function<bsm_status(hipStream_t)>& body, hipStream_t s,
+                            int reps, float* ms) {
+  hipEvent_t e0, e1;
+  BSM_HIP(hipEventCreate(&e0), "hipEventCreate");
+  BSM_HIP(hipEventCreate(&e1), "hipEventCreate");
+  bsm_status st = body(s);  // warm-up
+  if (st == BSM_OK) {
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == BSM_OK; ++r) st = body(s);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(ms, e0, e1);
+    *ms /= float(reps);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+static int num_variants(int precision) {
+  return precision == BSM_BF16X3 ? kNumBf16Variants : kNumVariants;
+}
 
 extern "C" {
 
@@ -49,6 +393,7 @@ void bsm_options_default(bsm_options* opt) {
   opt->k_window = 0;
   opt->record_timings = 0;
   opt->tile = 0;
+  opt->use_graph = 0;
 }
 
 int32_t bsm_tile_variants(int32_t* tm, int32_t* tn, int32_t cap) {
@@ -74,6 +419,7 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
   bsm_options o;
   bsm_options_default(&o);
   if (opt) o = *opt;
+  if (o.use_graph != 0 && o.use_graph != 1) return fail(BSM_E_INVALID, "use_graph must be 0 or 1");
   PlanConfig cfg;
   cfg.precision = o.precision;
   cfg.sched = o.sched;
@@ -96,6 +442,7 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
     delete p;
     return fail(bsm_status(code), err);
   }
+  p->use_graph = o.use_graph;
   *out = p;
   return BSM_OK;
 }
@@ -123,6 +470,7 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   if (h.cfg.record_timings) ws += int64_t(h.items.size()) * 16;
   info->workspace_bytes = ws;
   info->k_windows = h.windows;
+  info->tile = h.variant + 1;
   return BSM_OK;
 }
 
@@ -140,171 +488,306 @@ bsm_status bsm_plan_c_offsets(const bsm_plan* plan, int64_t* c_offsets) {
   return BSM_OK;
 }
 
-static bsm_status check_device(int* dev) {
-  hipError_t e = hipGetDevice(dev);
-  if (e != hipSuccess) return fail(BSM_E_UNSUPPORTED, std::string("no HIP device: ") + hipGetErrorString(e));
-  hipDeviceProp_t prop;
-  e = hipGetDeviceProperties(&prop, *dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(BSM_E_UNSUPPORTED, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
-  return BSM_OK;
-}
-
-static bsm_status upload(bsm_plan* p) {
-  if (p->uploaded) return BSM_OK;
-  int dev;
-  bsm_status st = check_device(&dev);
-  if (st != BSM_OK) return st;
-  const HostPlan& h = p->hp;
-  hipError_t e;
-  if (!h.items.empty()) {
-    if ((e = hipMalloc(&p->d_items, h.items.size() * sizeof(Item))) != hipSuccess) return hip_fail(e, "hipMalloc(tasks)");
-    if ((e = hipMemcpy(p->d_items, h.items.data(), h.items.size() * sizeof(Item), hipMemcpyHostToDevice)) != hipSuccess)
-      return hip_fail(e, "hipMemcpy(tasks)");
-  }
-  if (!h.tri.empty()) {
-    if ((e = hipMalloc(&p->d_tri, h.tri.size() * sizeof(Triple))) != hipSuccess) return hip_fail(e, "hipMalloc(triples)");
-    if ((e = hipMemcpy(p->d_tri, h.tri.data(), h.tri.size() * sizeof(Triple), hipMemcpyHostToDevice)) != hipSuccess)
-      return hip_fail(e, "hipMemcpy(triples)");
-  }
-  const int64_t ne_a = h.a_elems, ne_b = h.b_elems;
-  if (h.cfg.precision == BSM_FP32) {
-    if (ne_a > 0 && (e = hipMalloc(&p->d_opA, size_t(ne_a) * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(A fp32)");
-    if (ne_b > 0 && (e = hipMalloc(&p->d_opB, size_t(ne_b) * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(B fp32)");
-  }
-  if (h.cfg.precision == BSM_BF16X3) {
-    if (h.a_elems32 > 0 && (e = hipMalloc(&p->d_opA, size_t(h.a_elems32) * 6)) != hipSuccess) return hip_fail(e, "hipMalloc(A slices)");
-    if (h.b_elems32 > 0 && (e = hipMalloc(&p->d_opB, size_t(h.b_elems32) * 6)) != hipSuccess) return hip_fail(e, "hipMalloc(B slices)");
-    const size_t na = h.split_a.size() * sizeof(SplitBlock), nb = h.split_b.size() * sizeof(SplitBlock);
-    if (na && (e = hipMalloc(&p->d_split_a, na)) != hipSuccess) return hip_fail(e, "hipMalloc(split table)");
-    if (nb && (e = hipMalloc(&p->d_split_b, nb)) != hipSuccess) return hip_fail(e, "hipMalloc(split table)");
-    if (na && (e = hipMemcpy(p->d_split_a, h.split_a.data(), na, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy(split table)");
-    if (nb && (e = hipMemcpy(p->d_split_b, h.split_b.data(), nb, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy(split table)");
-  }
-  if (h.windows > 1 && h.c_elems > 0) {
-    if ((e = hipMalloc(&p->d_partial, size_t(h.c_elems) * 8)) != hipSuccess) return hip_fail(e, "hipMalloc(partial)");
-  }
-  if (h.cfg.record_timings && !h.items.empty()) {
-    if ((e = hipMalloc(&p->d_stamps, h.items.size() * 16)) != hipSuccess) return hip_fail(e, "hipMalloc(stamps)");
-  }
-  p->device = dev;
-  p->uploaded = true;
-  return BSM_OK;
-}
-
-static bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {
-  if (na <= 0 || nb <= 0) return false;
-  const char* pa = static_cast<const char*>(a);
-  const char* pb = static_cast<const char*>(b);
-  return pa < pb + nb && pb < pa + na;
-}
-
 bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
                        double* dC, int accumulate, void* stream) {
   if (!plan) return fail(BSM_E_INVALID, "plan is null");
   const HostPlan& h = plan->hp;
-  if ((h.a_elems > 0 && !dA) || (h.b_elems > 0 && !dB) || (h.c_elems > 0 && !dC))
-    return fail(BSM_E_INVALID, "null tile buffer");
-  if (overlaps(dC, h.c_elems * 8, dA, h.a_elems * 8) || overlaps(dC, h.c_elems * 8, dB, h.b_elems * 8))
-    return fail(BSM_E_INVALID, "C overlaps A or B");
-  if (accumulate != 0 && accumulate != 1) return fail(BSM_E_INVALID, "accumulate must be 0 or 1");
-  bsm_status st = upload(plan);
+  bsm_status st = check_operands(h, dA, dB, dC, accumulate);
   if (st != BSM_OK) return st;
+  if ((st = prepare(plan)) != BSM_OK) return st;
+  if ((st = sync_tasks(plan)) != BSM_OK) return st;
   if (h.items.empty()) return BSM_OK;
+  auto body = [&](hipStream_t s) -> bsm_status {
+    ProductArgs pa{};
+    bsm_status r = enqueue_convert(plan, dA, dB, s, pa);
+    if (r != BSM_OK) return r;
+    pa.C = dC;
+    pa.P = plan->d_partial;
+    pa.alpha = alpha;
+    return enqueue_tiles(h, plan->ts, nullptr, pa, accumulate, s);
+  };
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e;
-  int form = FORM_F64;
-  const void* opA = dA;
-  const void* opB = dB;
-  if (h.cfg.precision == BSM_FP32) {
-    // S6: operands rounded to FP32 once per execute (A == B is converted once)
-    form = FORM_F32;
-    if ((e = launch_to_f32(dA, static_cast<float*>(plan->d_opA), h.a_elems, s)) != hipSuccess)
-      return hip_fail(e, "convert A");
-    opA = plan->d_opA;
-    if (dB == dA && h.b_elems == h.a_elems) {
-      opB = plan->d_opA;
-    } else {
-      if ((e = launch_to_f32(dB, static_cast<float*>(plan->d_opB), h.b_elems, s)) != hipSuccess)
-        return hip_fail(e, "convert B");
-      opB = plan->d_opB;
-    }
-  }
-  int64_t a_plane = 0, b_plane = 0;
-  if (h.cfg.precision == BSM_BF16X3) {
-    // S6: three bf16 slices of every operand element, inner size padded to 32, B transposed
-    form = FORM_BF16X3;
-    a_plane = h.a_elems32;
-    b_plane = h.b_elems32;
-    if ((e = launch_split_bf16x3(plan->d_split_a, int64_t(h.split_a.size()), dA,
-                                 static_cast<uint16_t*>(plan->d_opA), a_plane, s)) != hipSuccess)
-      return hip_fail(e, "split A");
-    if ((e = launch_split_bf16x3(plan->d_split_b, int64_t(h.split_b.size()), dB,
-                                 static_cast<uint16_t*>(plan->d_opB), b_plane, s)) != hipSuccess)
-      return hip_fail(e, "split B");
-    opA = plan->d_opA;
-    opB = plan->d_opB;
-  }
-  TileArgs a{};
-  a.items = plan->d_items;
-  a.tri = plan->d_tri;
-  for (int x = 0; x <= kXcds; ++x) a.map.begin[x] = h.xcd_begin[x];
-  a.prods = nullptr;
-  a.single = ProductArgs{opA, opB, dC, plan->d_partial, alpha, a_plane, b_plane};
-  a.accumulate = accumulate;
-  a.stamps = plan->d_stamps;
-  // S5: k-windows of I consecutive inner blocks, issued in order on the stream; each window
-  // resumes from the raw FP64 sums of the previous one, so C does not depend on I
-  const int64_t I = h.k_window_eff;
-  for (int64_t wdx = 0; wdx < h.windows; ++wdx) {
-    a.k_lo = int(wdx * I);
-    a.k_hi = wdx + 1 == h.windows ? kNoKLimit : int((wdx + 1) * I);
-    a.win_first = wdx == 0;
-    a.win_last = wdx + 1 == h.windows;
-    const int v = h.items[0].variant;
-    e = form == FORM_F64   ? launch_tiles_f64(v, h.grid, a, s)
-        : form == FORM_F32 ? launch_tiles_f32(v, h.grid, a, s)
-                           : launch_tiles_bf16x3(v, h.grid, a, s);
-    if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
-  }
-  plan->timed = plan->d_stamps != nullptr;
-  return BSM_OK;
+  if (!plan->use_graph) return body(s);
+  std::vector<uint64_t> key{uint64_t(uintptr_t(dA)), uint64_t(uintptr_t(dB)), uint64_t(uintptr_t(dC)),
+                            bits_of(alpha), uint64_t(accumulate)};
+  st = plan->gc.run(key, body, s);
+  if (st == BSM_OK && plan->ts.stamps) plan->ts.timed = true;
+  return st;
 }
 
 bsm_status bsm_plan_timings(bsm_plan* plan, float* features, float* seconds, int64_t n,
                             void* stream) {
   if (!plan) return fail(BSM_E_INVALID, "plan is null");
-  const HostPlan& h = plan->hp;
-  if (n != int64_t(h.items.size())) return fail(BSM_E_MISMATCH, "n must equal the task count");
-  if (!plan->timed) return fail(BSM_E_STATE, "no execute with record_timings has run");
-  if (n == 0) return BSM_OK;
-  if ((!features && !seconds)) return fail(BSM_E_INVALID, "null output");
-  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-  std::vector<uint64_t> st(size_t(n) * 2);
-  e = hipMemcpy(st.data(), plan->d_stamps, st.size() * 8, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(stamps)");
-  for (int64_t q = 0; q < n; ++q) {
-    if (seconds) seconds[q] = float(double(st[size_t(2 * q + 1)] - st[size_t(2 * q)]) * 1e-8);
-    if (features)
-      for (int f = 0; f < 5; ++f) features[q * 5 + f] = h.features[size_t(q * 5 + f)];
+  return timings_of(plan->hp, plan->ts, features, seconds, n, stream);
+}
+
+bsm_status bsm_plan_features(const bsm_plan* plan, float* features, int64_t n) {
+  if (!plan) return fail(BSM_E_INVALID, "plan is null");
+  if (n != int64_t(plan->hp.items.size())) return fail(BSM_E_MISMATCH, "n must equal the task count");
+  if (n > 0 && !features) return fail(BSM_E_INVALID, "null output");
+  if (n > 0) std::memcpy(features, plan->hp.features.data(), size_t(n) * 5 * sizeof(float));
+  return BSM_OK;
+}
+
+bsm_status bsm_plan_set_costs(bsm_plan* plan, const float* costs, int64_t n) {
+  if (!plan) return fail(BSM_E_INVALID, "plan is null");
+  bsm_status st = set_costs(plan->hp, costs, n);
+  if (st == BSM_OK) plan->tasks_dirty = true;
+  return st;
+}
+
+bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, double* dC,
+                        void* stream, int32_t* chosen) {
+  if (!plan) return fail(BSM_E_INVALID, "plan is null");
+  HostPlan& h = plan->hp;
+  bsm_status st = check_operands(h, dA, dB, dC, 0);
+  if (st != BSM_OK) return st;
+  if ((st = prepare(plan)) != BSM_OK) return st;
+  const std::string key = tune_key({&h});
+  int best = tune_cache_lookup(key);
+  if (best < 0 || best >= num_variants(h.cfg.precision)) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float best_ms = 0.f;
+    best = h.variant;
+    for (int v = 0; v < num_variants(h.cfg.precision); ++v) {
+      cut_items(h, v);
+      schedule(h, flop_costs(h));
+      plan->tasks_dirty = true;
+      if ((st = sync_tasks(plan)) != BSM_OK) return st;
+      auto body = [&](hipStream_t q) -> bsm_status {
+        ProductArgs pa{};
+        bsm_status r = enqueue_convert(plan, dA, dB, q, pa);
+        if (r != BSM_OK) return r;
+        pa.C = dC;
+        pa.P = plan->d_partial;
+        pa.alpha = 1.0;
+        return enqueue_tiles(h, plan->ts, nullptr, pa, 0, q);
+      };
+      float ms = 0.f;
+      if ((st = time_body(body, s, 2, &ms)) != BSM_OK) return st;
+      if (v == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    tune_cache_store(key, best);
   }
+  cut_items(h, best);
+  schedule(h, flop_costs(h));
+  plan->tasks_dirty = true;
+  if ((st = sync_tasks(plan)) != BSM_OK) return st;
+  if (chosen) *chosen = best + 1;
   return BSM_OK;
 }
 
 bsm_status bsm_plan_destroy(bsm_plan* plan) {
   if (!plan) return BSM_OK;
   bsm_status st = BSM_OK;
-  if (plan->uploaded) {
+  if (plan->ready || plan->ts.items) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize");
-    for (void* ptr : {static_cast<void*>(plan->d_items), static_cast<void*>(plan->d_tri), plan->d_opA,
-                      plan->d_opB, static_cast<void*>(plan->d_split_a), static_cast<void*>(plan->d_split_b),
-                      static_cast<void*>(plan->d_partial), static_cast<void*>(plan->d_stamps)})
+    plan->gc.release();
+    plan->ts.release();
+    for (void* ptr : {plan->d_opA, plan->d_opB, static_cast<void*>(plan->d_split_a),
+                      static_cast<void*>(plan->d_split_b), static_cast<void*>(plan->d_partial)})
       if (ptr) (void)hipFree(ptr);
   }
   delete plan;
+  return st;
+}
+
+// ---- batches -------------------------------------------------------------------------------------
+bsm_status bsm_batch_create(bsm_batch** out, bsm_plan* const* plans, int64_t n) {
+  if (!out) return fail(BSM_E_INVALID, "out is null");
+  *out = nullptr;
+  if (n <= 0 || !plans) return fail(BSM_E_INVALID, "a batch needs at least one plan");
+  std::vector<const HostPlan*> parts;
+  for (int64_t q = 0; q < n; ++q) {
+    if (!plans[q]) return fail(BSM_E_INVALID, "null plan in batch");
+    parts.push_back(&plans[q]->hp);
+  }
+  bsm_batch* b = new (std::nothrow) bsm_batch;
+  if (!b) return fail(BSM_E_NOMEM, "host allocation failed");
+  int code = BSM_OK;
+  std::string err;
+  try {
+    err = merge_plans(b->hp, parts, &code);
+  } catch (const std::bad_alloc&) {
+    code = BSM_E_NOMEM;
+    err = "host allocation failed while merging";
+  }
+  if (code != BSM_OK) {
+    delete b;
+    return fail(bsm_status(code), err);
+  }
+  b->members.assign(plans, plans + n);
+  *out = b;
+  return BSM_OK;
+}
+
+bsm_status bsm_batch_query(const bsm_batch* batch, int64_t* tasks, double* useful_flops,
+                           int32_t* tile) {
+  if (!batch) return fail(BSM_E_INVALID, "batch is null");
+  if (tasks) *tasks = int64_t(batch->hp.items.size());
+  if (useful_flops) *useful_flops = batch->hp.useful_flops;
+  if (tile) *tile = batch->hp.variant + 1;
+  return BSM_OK;
+}
+
+static bsm_status batch_sync(bsm_batch* b) {
+  if (!b->tasks_dirty) return BSM_OK;
+  bsm_status st = b->ts.upload(b->hp, b->members[0]->hp.cfg.record_timings != 0);
+  if (st != BSM_OK) return st;
+  b->tasks_dirty = false;
+  b->gc.invalidate();
+  return BSM_OK;
+}
+
+static bsm_status batch_body(bsm_batch* b, const double* const* dA, const double* const* dB,
+                             int accumulate, hipStream_t s) {
+  for (size_t q = 0; q < b->members.size(); ++q) {
+    ProductArgs pa{};
+    bsm_status st = enqueue_convert(b->members[q], dA[q], dB[q], s, pa);
+    if (st != BSM_OK) return st;
+  }
+  return enqueue_tiles(b->hp, b->ts, b->d_prods, ProductArgs{}, accumulate, s);
+}
+
+// Operand table of the batch (device copy refreshed only when a pointer or alpha changed).
+static bsm_status batch_table(bsm_batch* b, const double* alphas, const double* const* dA,
+                              const double* const* dB, double* const* dC) {
+  const size_t n = b->members.size();
+  std::vector<ProductArgs> t(n);
+  for (size_t q = 0; q < n; ++q) {
+    bsm_plan* p = b->members[q];
+    const HostPlan& h = p->hp;
+    ProductArgs& pa = t[q];
+    std::memset(&pa, 0, sizeof pa);
+    pa.A = dA[q];
+    pa.B = dB[q];
+    if (h.cfg.precision == BSM_FP32) {
+      pa.A = p->d_opA;
+      pa.B = (dB[q] == dA[q] && h.b_elems == h.a_elems) ? p->d_opA : p->d_opB;
+    } else if (h.cfg.precision == BSM_BF16X3) {
+      pa.A = p->d_opA;
+      pa.B = p->d_opB;
+      pa.a_plane = h.a_elems32;
+      pa.b_plane = h.b_elems32;
+    }
+    pa.C = dC[q];
+    pa.P = nullptr;
+    pa.alpha = alphas ? alphas[q] : 1.0;
+  }
+  bool same = t.size() == b->h_prods.size() && b->d_prods &&
+              std::memcmp(t.data(), b->h_prods.data(), n * sizeof(ProductArgs)) == 0;
+  if (!same) {
+    if (!b->d_prods) BSM_HIP(hipMalloc(&b->d_prods, n * sizeof(ProductArgs)), "hipMalloc(operand table)");
+    BSM_HIP(hipMemcpy(b->d_prods, t.data(), n * sizeof(ProductArgs), hipMemcpyHostToDevice),
+            "hipMemcpy(operand table)");
+    b->h_prods = t;
+  }
+  return BSM_OK;
+}
+
+bsm_status bsm_batch_execute(bsm_batch* batch, const double* alphas, const double* const* dA,
+                             const double* const* dB, double* const* dC, int accumulate,
+                             void* stream) {
+  if (!batch) return fail(BSM_E_INVALID, "batch is null");
+  if (!dA || !dB || !dC) return fail(BSM_E_INVALID, "null operand array");
+  bsm_status st;
+  for (size_t q = 0; q < batch->members.size(); ++q) {
+    if ((st = check_operands(batch->members[q]->hp, dA[q], dB[q], dC[q], accumulate)) != BSM_OK) return st;
+    if ((st = prepare(batch->members[q])) != BSM_OK) return st;
+  }
+  if ((st = batch_sync(batch)) != BSM_OK) return st;
+  if ((st = batch_table(batch, alphas, dA, dB, dC)) != BSM_OK) return st;
+  if (batch->hp.items.empty()) return BSM_OK;
+  // one graph: every member's operand conversion, then one tile launch over all tasks
+  std::vector<uint64_t> key{uint64_t(accumulate)};
+  for (size_t q = 0; q < batch->members.size(); ++q) {
+    key.push_back(uint64_t(uintptr_t(dA[q])));
+    key.push_back(uint64_t(uintptr_t(dB[q])));
+    key.push_back(uint64_t(uintptr_t(dC[q])));
+    key.push_back(bits_of(alphas ? alphas[q] : 1.0));
+  }
+  auto body = [&](hipStream_t s) { return batch_body(batch, dA, dB, accumulate, s); };
+  st = batch->gc.run(key, body, static_cast<hipStream_t>(stream));
+  if (st == BSM_OK && batch->ts.stamps) batch->ts.timed = true;
+  return st;
+}
+
+bsm_status bsm_batch_timings(bsm_batch* batch, float* features, float* seconds, int64_t n,
+                             void* stream) {
+  if (!batch) return fail(BSM_E_INVALID, "batch is null");
+  return timings_of(batch->hp, batch->ts, features, seconds, n, stream);
+}
+
+bsm_status bsm_batch_set_costs(bsm_batch* batch, const float* costs, int64_t n) {
+  if (!batch) return fail(BSM_E_INVALID, "batch is null");
+  bsm_status st = set_costs(batch->hp, costs, n);
+  if (st == BSM_OK) batch->tasks_dirty = true;
+  return st;
+}
+
+bsm_status bsm_batch_autotune(bsm_batch* batch, const double* const* dA, const double* const* dB,
+                              double* const* dC, void* stream, int32_t* chosen) {
+  if (!batch) return fail(BSM_E_INVALID, "batch is null");
+  if (!dA || !dB || !dC) return fail(BSM_E_INVALID, "null operand array");
+  bsm_status st;
+  std::vector<const HostPlan*> parts;
+  for (size_t q = 0; q < batch->members.size(); ++q) {
+    if ((st = check_operands(batch->members[q]->hp, dA[q], dB[q], dC[q], 0)) != BSM_OK) return st;
+    if ((st = prepare(batch->members[q])) != BSM_OK) return st;
+    parts.push_back(&batch->members[q]->hp);
+  }
+  const int prec = parts[0]->cfg.precision;
+  const std::string key = tune_key(parts);
+  auto recut = [&](int v) -> bsm_status {
+    for (bsm_plan* p : batch->members) {
+      cut_items(p->hp, v);
+      schedule(p->hp, flop_costs(p->hp));
+      p->tasks_dirty = true;
+    }
+    int code = BSM_OK;
+    std::string err = merge_plans(batch->hp, parts, &code);
+    if (code != BSM_OK) return fail(bsm_status(code), err);
+    batch->tasks_dirty = true;
+    return batch_sync(batch);
+  };
+  int best = tune_cache_lookup(key);
+  if (best < 0 || best >= num_variants(prec)) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = batch_table(batch, nullptr, dA, dB, dC)) != BSM_OK) return st;
+    float best_ms = 0.f;
+    best = 0;
+    for (int v = 0; v < num_variants(prec); ++v) {
+      if ((st = recut(v)) != BSM_OK) return st;
+      auto body = [&](hipStream_t q) { return batch_body(batch, dA, dB, 0, q); };
+      float ms = 0.f;
+      if ((st = time_body(body, s, 2, &ms)) != BSM_OK) return st;
+      if (v == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    tune_cache_store(key, best);
+  }
+  if ((st = recut(best)) != BSM_OK) return st;
+  if (chosen) *chosen = best + 1;
+  return BSM_OK;
+}
+
+bsm_status bsm_batch_destroy(bsm_batch* batch) {
+  if (!batch) return BSM_OK;
+  bsm_status st = BSM_OK;
+  if (batch->ts.items || batch->d_prods) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize");
+  }
+  batch->gc.release();
+  batch->ts.release();
+  if (batch->d_prods) (void)hipFree(batch->d_prods);
+  delete batch;
   return st;
 }
 

@@ -133,14 +133,6 @@ static void pieces_to_ranges(const std::vector<int>& blocks, int m,
   }
 }
 
-// Library-chosen tile variant for a C block.
-static int pick_variant(int m, int n, int forced) {
-  if (forced > 0) return forced - 1;
-  (void)m;
-  (void)n;
-  return kDefaultVariant;
-}
-
 std::vector<double> flop_costs(const HostPlan& p) {
   std::vector<double> c(p.items.size());
   for (size_t q = 0; q < p.items.size(); ++q) {
@@ -201,6 +193,42 @@ void schedule(HostPlan& p, const std::vector<double>& cost) {
   p.cost.swap(c2);
   p.features.swap(f2);
   p.grid = maxc * kXcds;
+}
+
+void cut_items(HostPlan& p, int variant) {
+  const bool bf16 = p.cfg.precision == 2;
+  const Variant& var = bf16 ? kBf16Variants[variant] : kVariants[variant];
+  std::vector<std::pair<int, int>> rs, cs;
+  std::map<std::array<int, 5>, CutChoice> cut_memo;
+  p.items.clear();
+  p.features.clear();
+  p.variant = variant;
+  for (const CBlock& cb : p.cblocks) {
+    const CutChoice& cut = best_cut((cb.m + 15) / 16, (cb.n + 15) / 16, var.tm / 16, var.tn / 16,
+                                    var.nw, p.cfg.cut_search, cut_memo);
+    pieces_to_ranges(cut.rows, cb.m, rs);
+    pieces_to_ranges(cut.cols, cb.n, cs);
+    for (auto& r : rs)
+      for (auto& c : cs) {
+        Item it;
+        it.c_off = cb.c_off;
+        it.tri_begin = cb.tri_begin;
+        it.tri_count = cb.tri_count;
+        it.r0 = uint16_t(r.first);
+        it.h = uint16_t(r.second);
+        it.c0 = uint16_t(c.first);
+        it.w = uint16_t(c.second);
+        it.ldc = uint16_t(cb.n);
+        it.variant = uint16_t(variant);
+        it.product = 0;
+        p.items.push_back(it);
+        p.features.push_back(std::log(float(it.h)));
+        p.features.push_back(std::log(float(it.w)));
+        p.features.push_back(std::log(float(std::max(1.0, cb.sk))));
+        p.features.push_back(std::log(float(std::max<uint32_t>(1, cb.tri_count))));
+        p.features.push_back(float(p.k_total > 0 ? cb.sk / p.k_total : 0.0));
+      }
+  }
 }
 
 std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
@@ -296,10 +324,7 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   p.items.clear();
   p.features.clear();
   p.useful_flops = 0;
-  std::vector<std::pair<int, int>> rs, cs;
-  std::map<std::array<int, 5>, CutChoice> cut_memo;
-  double ktot = 0;
-  for (int64_t k = 0; k < K; ++k) ktot += double(p.inner[size_t(k)]);
+  p.cblocks.clear();
   for (int64_t i = 0; i < M; ++i) {
     for (int64_t j = 0; j < N; ++j) {
       int64_t co = p.c_off[size_t(i * N + j)];
@@ -327,39 +352,55 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
       }
       int m = int(p.rows[size_t(i)]), n = int(p.cols[size_t(j)]);
       p.useful_flops += 2.0 * m * n * sk;
-      const int v = bf16 ? 0 : pick_variant(m, n, cfg.tile);
-      const Variant& var = bf16 ? kBf16Variants[v] : kVariants[v];
-      const CutChoice& cut = best_cut((m + 15) / 16, (n + 15) / 16, var.tm / 16, var.tn / 16,
-                                      var.nw, cfg.cut_search, cut_memo);
-      pieces_to_ranges(cut.rows, m, rs);
-      pieces_to_ranges(cut.cols, n, cs);
-      for (auto& r : rs)
-        for (auto& c : cs) {
-          Item it;
-          it.c_off = co;
-          it.tri_begin = uint32_t(tb);
-          it.tri_count = uint32_t(tc);
-          it.r0 = uint16_t(r.first);
-          it.h = uint16_t(r.second);
-          it.c0 = uint16_t(c.first);
-          it.w = uint16_t(c.second);
-          it.ldc = uint16_t(n);
-          it.variant = uint16_t(v);
-          it.product = 0;
-          p.items.push_back(it);
-          p.features.push_back(std::log(float(it.h)));
-          p.features.push_back(std::log(float(it.w)));
-          p.features.push_back(std::log(float(std::max(1.0, sk))));
-          p.features.push_back(std::log(float(std::max<size_t>(1, tc))));
-          p.features.push_back(float(ktot > 0 ? sk / ktot : 0.0));
-        }
+      p.cblocks.push_back(CBlock{co, uint32_t(tb), uint32_t(tc), m, n, sk});
     }
   }
+  p.k_total = 0;
+  for (int64_t k = 0; k < K; ++k) p.k_total += double(p.inner[size_t(k)]);
+  cut_items(p, bf16 ? 0 : (cfg.tile > 0 ? cfg.tile - 1 : kDefaultVariant));
   // S5: k-windows (0 = all K inner blocks in flight at once)
   p.k_window_eff = (cfg.k_window == 0 || cfg.k_window >= K) ? std::max<int64_t>(K, 1) : cfg.k_window;
   p.windows = K > 0 ? (K + p.k_window_eff - 1) / p.k_window_eff : 1;
   // S4: cost and order
   schedule(p, flop_costs(p));
+  *code = BSM_OK;
+  return "";
+}
+
+std::string merge_plans(HostPlan& out, const std::vector<const HostPlan*>& parts, int* code) {
+  *code = BSM_E_MISMATCH;
+  if (parts.empty()) {
+    *code = BSM_E_INVALID;
+    return "empty batch";
+  }
+  const HostPlan& p0 = *parts[0];
+  out = HostPlan();
+  out.cfg = p0.cfg;
+  out.variant = p0.variant;
+  out.windows = 1;
+  out.k_window_eff = 1;
+  for (size_t q = 0; q < parts.size(); ++q) {
+    const HostPlan& p = *parts[q];
+    if (p.cfg.precision != p0.cfg.precision) return "batch members differ in precision";
+    if (p.variant != p0.variant) return "batch members differ in tile variant";
+    if (p.windows != 1) return "batch members must issue all k-iterations at once (k_window 0)";
+    const uint64_t tb = out.tri.size();
+    if (tb + p.tri.size() >= (uint64_t(1) << 32)) {
+      *code = BSM_E_NOMEM;
+      return "more than 2^32 block triples in the batch";
+    }
+    out.tri.insert(out.tri.end(), p.tri.begin(), p.tri.end());
+    for (const Item& it0 : p.items) {
+      Item it = it0;
+      it.tri_begin = uint32_t(it.tri_begin + tb);
+      it.product = uint32_t(q);
+      out.items.push_back(it);
+    }
+    out.features.insert(out.features.end(), p.features.begin(), p.features.end());
+    out.useful_flops += p.useful_flops;
+    out.c_blocks += p.c_blocks;
+  }
+  schedule(out, flop_costs(out));
   *code = BSM_OK;
   return "";
 }

@@ -33,6 +33,14 @@ struct PlanConfig {
   bool cut_search = false;  // choose sub-tile cuts by slowest-wave cost (else near-equal pieces)
 };
 
+// A present C block and its k-list (the unit tasks are cut from).
+struct CBlock {
+  int64_t c_off;
+  uint32_t tri_begin, tri_count;
+  int32_t m, n;
+  double sk;  // summed inner size of the k-list
+};
+
 struct HostPlan {
   PlanConfig cfg;
   int64_t M = 0, K = 0, N = 0;
@@ -44,6 +52,9 @@ struct HostPlan {
   double useful_flops = 0.0;
 
   std::vector<Triple> tri;       // k-lists of all C blocks, C blocks in row-major order
+  std::vector<CBlock> cblocks;   // present C blocks, row-major
+  double k_total = 0;            // summed inner size of all K blocks
+  int variant = 0;               // tile variant the tasks are cut for
   std::vector<Item> items;       // tasks in execution order, grouped by XCD
   std::vector<double> cost;      // scheduler cost of items[q]
   std::vector<float> features;   // 5 per item: log h, log w, log sum_k, log #k, density
@@ -64,8 +75,15 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
                        const uint64_t* a_bits, const uint64_t* b_bits, const PlanConfig& cfg,
                        int* code);
 
+// Cut every C block into tasks for the given tile variant (replaces items and features).
+void cut_items(HostPlan& p, int variant);
+
 // Re-order and re-partition the tasks from per-item costs (never changes the task set).
 void schedule(HostPlan& p, const std::vector<double>& cost);
+
+// Concatenate the tasks of several plans (same precision, tile variant, one k-window) into one
+// schedule; task q of part p keeps its triples and is tagged with product p.
+std::string merge_plans(HostPlan& out, const std::vector<const HostPlan*>& parts, int* code);
 
 // Flop-count cost of every item.
 std::vector<double> flop_costs(const HostPlan& p);

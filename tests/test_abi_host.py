@@ -134,3 +134,58 @@ def test_tile_variants_listed():
 
 def test_destroy_null_is_ok():
     assert bsm.load().bsm_plan_destroy(None) == bsm.OK
+
+
+def test_batch_rules_checked_on_host():
+    p = gen.random_problem(40, 3, 3, 3, 1, 50, 0.8, 0.8)
+    q = gen.random_problem(41, 4, 2, 3, 1, 50, 0.8, 0.8)
+    a = bsm.Plan.from_problem(p)
+    b = bsm.Plan.from_problem(q)
+    batch = bsm.Batch([a, b])
+    tasks, flops, tile = batch.query()
+    assert tasks == a.info().tasks + b.info().tasks
+    assert flops == a.info().useful_flops + b.info().useful_flops
+    assert tile == a.info().tile
+    _expect(bsm.E_MISMATCH, lambda: bsm.Batch([a, bsm.Plan.from_problem(q, precision=bsm.FP32)]))
+    _expect(bsm.E_MISMATCH, lambda: bsm.Batch([a, bsm.Plan.from_problem(q, tile=2)]))
+    _expect(bsm.E_MISMATCH, lambda: bsm.Batch([a, bsm.Plan.from_problem(q, k_window=1)]))
+    L = bsm.load()
+    assert L.bsm_batch_create(None, None, 0) == bsm.E_INVALID
+
+
+def test_set_costs_validation_and_features():
+    p = gen.random_problem(42, 4, 4, 4, 1, 200, 0.7, 0.7)
+    plan = bsm.Plan.from_problem(p)
+    n = plan.info().tasks
+    f = plan.features()
+    assert f.shape == (n, 5) and np.all(np.isfinite(f))
+    # features: log h, log w in [0, log 128]; density in (0, 1]
+    assert np.all(f[:, :2] >= 0) and np.all(f[:, :2] <= np.log(128) + 1e-6)
+    assert np.all((f[:, 4] > 0) & (f[:, 4] <= 1))
+    _expect(bsm.E_MISMATCH, lambda: plan.set_costs(np.ones(n + 1)))
+    bad = np.ones(n)
+    bad[0] = np.nan
+    _expect(bsm.E_INVALID, lambda: plan.set_costs(bad))
+    bad[0] = -1
+    _expect(bsm.E_INVALID, lambda: plan.set_costs(bad))
+    plan.set_costs(np.arange(n, dtype=np.float32))
+    assert plan.info().tasks == n
+
+
+def test_binding_rejects_short_buffers():
+    """The binding checks buffer sizes before a pointer reaches the library (no device needed:
+    the check happens before any device call)."""
+    torch = pytest.importorskip("torch")
+    p = gen.random_problem(43, 3, 3, 3, 4, 40, 1.0, 1.0)
+    plan = bsm.Plan.from_problem(p)
+    info = plan.info()
+    A = torch.zeros(info.a_elems, dtype=torch.float64)
+    B = torch.zeros(info.b_elems, dtype=torch.float64)
+    with pytest.raises(ValueError, match="C holds"):
+        plan.execute(A, B, torch.zeros(info.c_elems - 1, dtype=torch.float64))
+    with pytest.raises(ValueError, match="float64"):
+        plan.execute(A, B, torch.zeros(info.c_elems, dtype=torch.float32))
+    with pytest.raises(ValueError, match="A holds"):
+        plan.execute(A[:-1], B, torch.zeros(info.c_elems, dtype=torch.float64))
+    with pytest.raises(ValueError, match="device"):
+        plan.execute(A, B, torch.zeros(info.c_elems, dtype=torch.float64))
