@@ -156,13 +156,14 @@ def _check_operands(info, A, B, C):
             raise ValueError(f"{name} is required ({need} elements)")
         if need > 0 and t.numel() < need:
             raise ValueError(f"{name} holds {t.numel()} elements, the plan needs {need}")
-    for name, t, need in bufs:
-        if need <= 0 or t is None:
-            continue
+    used = [(name, t) for name, t, need in bufs if need > 0 and t is not None]
+    for name, t in used:
         if getattr(t, "dtype", None) is not None and str(t.dtype) != "torch.float64":
             raise ValueError(f"{name} must be float64, got {t.dtype}")
+    for name, t in used:
         if hasattr(t, "is_contiguous") and not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
+    for name, t in used:
         if hasattr(t, "is_cuda") and not t.is_cuda:
             raise ValueError(f"{name} must be a device tensor")
 
