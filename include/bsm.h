@@ -184,6 +184,54 @@ bsm_status bsm_batch_autotune(bsm_batch* batch, const double* const* dA, const d
 
 bsm_status bsm_batch_destroy(bsm_batch* batch);
 
+/* ---- learned task cost model ---------------------------------------------------------------------
+ * A small fully connected network (5 -> 32 -> 32 -> 1, ReLU, FP32) predicts a task's log run time
+ * from its features (bsm_plan_features).  It is trained on the device (forward, backward, Adam)
+ * from timings the multiply records itself (record_timings, bsm_plan_timings), and the scheduler
+ * then bins and orders tasks by exp(prediction) instead of by flop count.  Only the schedule
+ * changes; C is bitwise the same.  Parameter layout: W1 (32 x 5, row-major), b1 (32), W2 (32 x 32,
+ * row-major), b2 (32), w3 (32), b3 (1).  Inputs are standardised with per-feature means and
+ * standard deviations, and the output de-standardised, with statistics of the training set
+ * ("norm12": 5 feature means, 5 feature scales, target mean, target scale). */
+typedef struct bsm_costmodel bsm_costmodel;
+
+/* New model with He-uniform initial weights drawn from splitmix64(seed, index), zero biases and
+ * identity normalisation.  Host-only until first used. */
+bsm_status bsm_costmodel_create(bsm_costmodel** out, uint64_t seed);
+int64_t bsm_costmodel_param_count(void);
+/* Copy the parameters (n = bsm_costmodel_param_count(), may be NULL) and/or the 12 normalisation
+ * values (may be NULL) out of / into the model (host arrays). */
+bsm_status bsm_costmodel_params(const bsm_costmodel* m, float* params, int64_t n, float* norm12);
+bsm_status bsm_costmodel_set_params(bsm_costmodel* m, const float* params, int64_t n,
+                                    const float* norm12);
+/* Train on n samples (host: features n x 5, log run times n): set the normalisation from the
+ * samples, then `epochs` passes of mini-batches of `batch` samples in index order, one Adam step
+ * (lr, beta1 0.9, beta2 0.999, eps 1e-8) per mini-batch, all on the device.  *final_loss (may be
+ * NULL) receives the mean squared error over all samples in standardised units.  Synchronises. */
+bsm_status bsm_costmodel_train(bsm_costmodel* m, const float* features, const float* log_seconds,
+                               int64_t n, int64_t epochs, int64_t batch, float lr,
+                               float* final_loss, void* stream);
+/* Predicted log run times (host in, host out; computed on the device).  Synchronises. */
+bsm_status bsm_costmodel_predict(bsm_costmodel* m, const float* features, int64_t n,
+                                 float* log_seconds, void* stream);
+/* Persist / restore parameters, normalisation and Adam state (training can resume). */
+bsm_status bsm_costmodel_save(const bsm_costmodel* m, const char* path);
+bsm_status bsm_costmodel_load(bsm_costmodel** out, const char* path);
+bsm_status bsm_costmodel_destroy(bsm_costmodel* m);
+/* Re-bin and re-order the tasks by the model's predictions (S4 with the learned cost). */
+bsm_status bsm_plan_set_costmodel(bsm_plan* plan, bsm_costmodel* model, void* stream);
+bsm_status bsm_batch_set_costmodel(bsm_batch* batch, bsm_costmodel* model, void* stream);
+
+/* The network's own arithmetic on device buffers, without normalisation: y = f(x) for n samples
+ * (x: n x 5); the mean squared error over n samples and its gradient (d_loss may be NULL;
+ * synchronises); one Adam step over n parameters (step = 1, 2, ...). */
+bsm_status bsm_mlp_forward(const float* d_params, const float* d_x, int64_t n, float* d_y,
+                           void* stream);
+bsm_status bsm_mlp_loss_grad(const float* d_params, const float* d_x, const float* d_t, int64_t n,
+                             float* d_grad, float* d_loss, void* stream);
+bsm_status bsm_adam_step(float* d_params, const float* d_grad, float* d_m, float* d_v, int64_t n,
+                         int64_t step, float lr, float beta1, float beta2, float eps, void* stream);
+
 /* Eq. 1: how many SUMMA iterations are issued at once on a P_row x P_col process grid with K
  * inner blocks: 2 if either grid dimension is below 2, K if both are at least K, else
  * min(P_row, P_col). */

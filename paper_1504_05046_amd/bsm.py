@@ -82,11 +82,31 @@ def load() -> ctypes.CDLL:
     L.bsm_batch_set_costs.argtypes = [_p, _p, _i64]
     L.bsm_batch_autotune.argtypes = [_p, _p, _p, _p, _p, _p]
     L.bsm_batch_destroy.argtypes = [_p]
+    L.bsm_costmodel_create.argtypes = [ctypes.POINTER(_p), ctypes.c_uint64]
+    L.bsm_costmodel_param_count.restype = _i64
+    L.bsm_costmodel_param_count.argtypes = []
+    L.bsm_costmodel_params.argtypes = [_p, _p, _i64, _p]
+    L.bsm_costmodel_set_params.argtypes = [_p, _p, _i64, _p]
+    L.bsm_costmodel_train.argtypes = [_p, _p, _p, _i64, _i64, _i64, ctypes.c_float, _p, _p]
+    L.bsm_costmodel_predict.argtypes = [_p, _p, _i64, _p, _p]
+    L.bsm_costmodel_save.argtypes = [_p, ctypes.c_char_p]
+    L.bsm_costmodel_load.argtypes = [ctypes.POINTER(_p), ctypes.c_char_p]
+    L.bsm_costmodel_destroy.argtypes = [_p]
+    L.bsm_plan_set_costmodel.argtypes = [_p, _p, _p]
+    L.bsm_batch_set_costmodel.argtypes = [_p, _p, _p]
+    L.bsm_mlp_forward.argtypes = [_p, _p, _i64, _p, _p]
+    L.bsm_mlp_loss_grad.argtypes = [_p, _p, _p, _i64, _p, _p, _p]
+    L.bsm_adam_step.argtypes = [_p, _p, _p, _p, _i64, _i64, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, _p]
     for name in ("bsm_plan_create", "bsm_plan_query", "bsm_plan_c_shape", "bsm_plan_c_offsets",
                  "bsm_execute", "bsm_plan_destroy", "bsm_plan_timings", "bsm_plan_features",
                  "bsm_plan_set_costs", "bsm_autotune", "bsm_batch_create", "bsm_batch_query",
                  "bsm_batch_execute", "bsm_batch_timings", "bsm_batch_set_costs",
-                 "bsm_batch_autotune", "bsm_batch_destroy"):
+                 "bsm_batch_autotune", "bsm_batch_destroy", "bsm_costmodel_create",
+                 "bsm_costmodel_params", "bsm_costmodel_set_params", "bsm_costmodel_train",
+                 "bsm_costmodel_predict", "bsm_costmodel_save", "bsm_costmodel_load",
+                 "bsm_costmodel_destroy", "bsm_plan_set_costmodel", "bsm_batch_set_costmodel",
+                 "bsm_mlp_forward", "bsm_mlp_loss_grad", "bsm_adam_step"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -240,6 +260,9 @@ class Plan:
                                    _stream_handle(stream), ctypes.byref(chosen)))
         return int(chosen.value)
 
+    def set_costmodel(self, model: "CostModel", stream=None):
+        _check(load().bsm_plan_set_costmodel(self._h, model.handle, _stream_handle(stream)))
+
     def close(self):
         if getattr(self, "_h", None):
             _check(load().bsm_plan_destroy(self._h))
@@ -308,6 +331,9 @@ class Batch:
                                          _stream_handle(stream), ctypes.byref(chosen)))
         return int(chosen.value)
 
+    def set_costmodel(self, model: "CostModel", stream=None):
+        _check(load().bsm_batch_set_costmodel(self._h, model.handle, _stream_handle(stream)))
+
     def close(self):
         if getattr(self, "_h", None):
             _check(load().bsm_batch_destroy(self._h))
@@ -318,3 +344,91 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+MLP_IN, MLP_HIDDEN = 5, 32
+
+
+def mlp_param_count() -> int:
+    return int(load().bsm_costmodel_param_count())
+
+
+class CostModel:
+    """The learned task cost model (parameters and Adam state live on the device)."""
+
+    def __init__(self, seed: int = 0, _handle=None):
+        if _handle is not None:
+            self._h = _handle
+        else:
+            h = _p()
+            _check(load().bsm_costmodel_create(ctypes.byref(h), int(seed)))
+            self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @classmethod
+    def load_file(cls, path: str) -> "CostModel":
+        h = _p()
+        _check(load().bsm_costmodel_load(ctypes.byref(h), path.encode()))
+        return cls(_handle=h)
+
+    def save(self, path: str):
+        _check(load().bsm_costmodel_save(self._h, path.encode()))
+
+    def params(self):
+        n = mlp_param_count()
+        p = np.zeros(n, dtype=np.float32)
+        norm = np.zeros(12, dtype=np.float32)
+        _check(load().bsm_costmodel_params(self._h, p.ctypes.data, n, norm.ctypes.data))
+        return p, norm
+
+    def set_params(self, params=None, norm=None):
+        p = _arr(params, np.float32) if params is not None else None
+        nm = _arr(norm, np.float32) if norm is not None else None
+        _check(load().bsm_costmodel_set_params(self._h, p.ctypes.data if p is not None else None,
+                                               p.size if p is not None else 0,
+                                               nm.ctypes.data if nm is not None else None))
+
+    def train(self, features, log_seconds, epochs=200, batch=1024, lr=3e-3, stream=None) -> float:
+        f = _arr(features, np.float32).reshape(-1, MLP_IN)
+        t = _arr(log_seconds, np.float32).reshape(-1)
+        loss = ctypes.c_float(0)
+        _check(load().bsm_costmodel_train(self._h, f.ctypes.data, t.ctypes.data, t.size, epochs,
+                                          batch, lr, ctypes.byref(loss), _stream_handle(stream)))
+        return float(loss.value)
+
+    def predict(self, features, stream=None) -> np.ndarray:
+        f = _arr(features, np.float32).reshape(-1, MLP_IN)
+        out = np.zeros(f.shape[0], dtype=np.float32)
+        _check(load().bsm_costmodel_predict(self._h, f.ctypes.data, f.shape[0], out.ctypes.data,
+                                            _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().bsm_costmodel_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlp_forward(d_params, d_x, d_y, stream=None):
+    _check(load().bsm_mlp_forward(_dev_ptr(d_params), _dev_ptr(d_x), d_x.shape[0], _dev_ptr(d_y),
+                                  _stream_handle(stream)))
+
+
+def mlp_loss_grad(d_params, d_x, d_t, d_grad, d_loss=None, stream=None):
+    _check(load().bsm_mlp_loss_grad(_dev_ptr(d_params), _dev_ptr(d_x), _dev_ptr(d_t), d_x.shape[0],
+                                    _dev_ptr(d_grad), _dev_ptr(d_loss), _stream_handle(stream)))
+
+
+def adam_step(d_params, d_grad, d_m, d_v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load().bsm_adam_step(_dev_ptr(d_params), _dev_ptr(d_grad), _dev_ptr(d_m), _dev_ptr(d_v),
+                                d_params.numel(), int(step), lr, beta1, beta2, eps,
+                                _stream_handle(stream)))

@@ -382,6 +382,85 @@ static int num_variants(int precision) {
   return precision == BSM_BF16X3 ? kNumBf16Variants : kNumVariants;
 }
 
+// ------------------------------------------------------------------------------------------------
+// Task cost model (S10): network parameters and Adam state on the device, the feature/target
+// normalisation on the host.
+struct bsm_costmodel {
+  std::vector<float> params;      // host copy, kept in sync with d_params
+  MlpNorm norm{};
+  float* d_params = nullptr;
+  float* d_m = nullptr;
+  float* d_v = nullptr;
+  float* d_grad = nullptr;
+  int64_t step = 0;               // Adam updates so far
+};
+
+static MlpNorm identity_norm() {
+  MlpNorm n{};
+  for (int f = 0; f < kMlpIn; ++f) {
+    n.fmean[f] = 0.f;
+    n.fstd[f] = 1.f;
+  }
+  n.tmean = 0.f;
+  n.tstd = 1.f;
+  return n;
+}
+
+// splitmix64: the counter-based generator behind the initial weights
+static uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+static bsm_status model_device(bsm_costmodel* m) {
+  if (m->d_params) return BSM_OK;
+  int dev;
+  bsm_status st = check_device(&dev);
+  if (st != BSM_OK) return st;
+  const size_t bytes = size_t(kMlpParams) * 4;
+  BSM_HIP(hipMalloc(&m->d_params, bytes), "hipMalloc(model)");
+  BSM_HIP(hipMalloc(&m->d_m, bytes), "hipMalloc(model)");
+  BSM_HIP(hipMalloc(&m->d_v, bytes), "hipMalloc(model)");
+  BSM_HIP(hipMalloc(&m->d_grad, bytes), "hipMalloc(model)");
+  BSM_HIP(hipMemcpy(m->d_params, m->params.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy(model)");
+  std::vector<float> z(size_t(kMlpParams), 0.f);
+  BSM_HIP(hipMemcpy(m->d_m, z.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy(model)");
+  BSM_HIP(hipMemcpy(m->d_v, z.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy(model)");
+  return BSM_OK;
+}
+
+// Predicted log run time of n tasks (features host, n x 5) on the device; out host (n floats).
+static bsm_status model_predict(bsm_costmodel* m, const float* features, int64_t n, float* out,
+                                hipStream_t s) {
+  if (n == 0) return BSM_OK;
+  bsm_status st = model_device(m);
+  if (st != BSM_OK) return st;
+  float *dx = nullptr, *dy = nullptr;
+  BSM_HIP(hipMalloc(&dx, size_t(n) * kMlpIn * 4), "hipMalloc(features)");
+  hipError_t e = hipMalloc(&dy, size_t(n) * 4);
+  if (e == hipSuccess) e = hipMemcpyAsync(dx, features, size_t(n) * kMlpIn * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_mlp_forward(m->d_params, dx, n, dy, m->norm, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dy, size_t(n) * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dx);
+  if (dy) (void)hipFree(dy);
+  if (e != hipSuccess) return hip_fail(e, "cost model inference");
+  return BSM_OK;
+}
+
+static bsm_status apply_model(HostPlan& h, bsm_costmodel* m, hipStream_t s) {
+  const int64_t n = int64_t(h.items.size());
+  std::vector<float> pred(static_cast<size_t>(n));
+  bsm_status st = model_predict(m, h.features.data(), n, pred.data(), s);
+  if (st != BSM_OK) return st;
+  std::vector<double> c(pred.size());
+  for (size_t q = 0; q < pred.size(); ++q) c[q] = std::exp(double(std::min(pred[q], 80.f)));
+  schedule(h, c);
+  return BSM_OK;
+}
+
 extern "C" {
 
 const char* bsm_last_error(void) { return g_error.c_str(); }
@@ -789,6 +868,266 @@ bsm_status bsm_batch_destroy(bsm_batch* batch) {
   if (batch->d_prods) (void)hipFree(batch->d_prods);
   delete batch;
   return st;
+}
+
+// ---- cost model ---------------------------------------------------------------------------------
+bsm_status bsm_costmodel_create(bsm_costmodel** out, uint64_t seed) {
+  if (!out) return fail(BSM_E_INVALID, "out is null");
+  bsm_costmodel* m = new (std::nothrow) bsm_costmodel;
+  if (!m) return fail(BSM_E_NOMEM, "host allocation failed");
+  // He-uniform weights from splitmix64(seed, index); biases 0
+  m->params.assign(size_t(kMlpParams), 0.f);
+  const int H = kMlpHidden, F = kMlpIn;
+  auto u01 = [&](uint64_t i) { return float(double(splitmix64(seed * 0x100000001B3ull + i) >> 11) * 0x1.0p-53); };
+  for (int q = 0; q < H * F; ++q) m->params[size_t(q)] = (2.f * u01(uint64_t(q)) - 1.f) * std::sqrt(6.f / F);
+  const int ow2 = H * F + H;
+  for (int q = 0; q < H * H; ++q) m->params[size_t(ow2 + q)] = (2.f * u01(uint64_t(ow2 + q)) - 1.f) * std::sqrt(6.f / H);
+  const int ow3 = ow2 + H * H + H;
+  for (int q = 0; q < H; ++q) m->params[size_t(ow3 + q)] = (2.f * u01(uint64_t(ow3 + q)) - 1.f) * std::sqrt(6.f / H);
+  m->norm = identity_norm();
+  *out = m;
+  return BSM_OK;
+}
+
+int64_t bsm_costmodel_param_count(void) { return kMlpParams; }
+
+bsm_status bsm_costmodel_params(const bsm_costmodel* m, float* params, int64_t n, float* norm12) {
+  if (!m) return fail(BSM_E_INVALID, "model is null");
+  if (params) {
+    if (n != kMlpParams) return fail(BSM_E_MISMATCH, "n must equal bsm_costmodel_param_count()");
+    std::memcpy(params, m->params.data(), size_t(kMlpParams) * 4);
+  }
+  if (norm12) {
+    for (int f = 0; f < kMlpIn; ++f) {
+      norm12[f] = m->norm.fmean[f];
+      norm12[kMlpIn + f] = m->norm.fstd[f];
+    }
+    norm12[2 * kMlpIn] = m->norm.tmean;
+    norm12[2 * kMlpIn + 1] = m->norm.tstd;
+  }
+  return BSM_OK;
+}
+
+bsm_status bsm_costmodel_set_params(bsm_costmodel* m, const float* params, int64_t n,
+                                    const float* norm12) {
+  if (!m) return fail(BSM_E_INVALID, "model is null");
+  if (params) {
+    if (n != kMlpParams) return fail(BSM_E_MISMATCH, "n must equal bsm_costmodel_param_count()");
+    m->params.assign(params, params + kMlpParams);
+    if (m->d_params)
+      BSM_HIP(hipMemcpy(m->d_params, params, size_t(kMlpParams) * 4, hipMemcpyHostToDevice), "hipMemcpy(model)");
+  }
+  if (norm12) {
+    for (int f = 0; f < kMlpIn; ++f) {
+      if (!(norm12[kMlpIn + f] > 0.f)) return fail(BSM_E_INVALID, "feature scales must be > 0");
+      m->norm.fmean[f] = norm12[f];
+      m->norm.fstd[f] = norm12[kMlpIn + f];
+    }
+    if (!(norm12[2 * kMlpIn + 1] > 0.f)) return fail(BSM_E_INVALID, "target scale must be > 0");
+    m->norm.tmean = norm12[2 * kMlpIn];
+    m->norm.tstd = norm12[2 * kMlpIn + 1];
+  }
+  return BSM_OK;
+}
+
+bsm_status bsm_costmodel_train(bsm_costmodel* m, const float* features, const float* log_seconds,
+                               int64_t n, int64_t epochs, int64_t batch, float lr,
+                               float* final_loss, void* stream) {
+  if (!m) return fail(BSM_E_INVALID, "model is null");
+  if (n <= 0 || !features || !log_seconds) return fail(BSM_E_INVALID, "empty training set");
+  if (epochs < 0 || batch <= 0 || !(lr > 0.f)) return fail(BSM_E_INVALID, "epochs >= 0, batch > 0, lr > 0");
+  bsm_status st = model_device(m);
+  if (st != BSM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // normalisation statistics of this training set (means and standard deviations)
+  MlpNorm nm{};
+  for (int f = 0; f < kMlpIn; ++f) {
+    double mu = 0, sq = 0;
+    for (int64_t q = 0; q < n; ++q) mu += features[q * kMlpIn + f];
+    mu /= double(n);
+    for (int64_t q = 0; q < n; ++q) sq += (features[q * kMlpIn + f] - mu) * (features[q * kMlpIn + f] - mu);
+    double sd = std::sqrt(sq / double(n));
+    nm.fmean[f] = float(mu);
+    nm.fstd[f] = float(sd > 1e-6 ? sd : 1.0);
+  }
+  {
+    double mu = 0, sq = 0;
+    for (int64_t q = 0; q < n; ++q) mu += log_seconds[q];
+    mu /= double(n);
+    for (int64_t q = 0; q < n; ++q) sq += (log_seconds[q] - mu) * (log_seconds[q] - mu);
+    double sd = std::sqrt(sq / double(n));
+    nm.tmean = float(mu);
+    nm.tstd = float(sd > 1e-6 ? sd : 1.0);
+  }
+  m->norm = nm;
+  const int64_t bmax = std::min(batch, n);
+  float *dx = nullptr, *dt = nullptr, *part = nullptr, *pl = nullptr, *dloss = nullptr;
+  hipError_t e = hipMalloc(&dx, size_t(n) * kMlpIn * 4);
+  if (e == hipSuccess) e = hipMalloc(&dt, size_t(n) * 4);
+  const int64_t rows = mlp_partial_rows(std::max(bmax, n));
+  if (e == hipSuccess) e = hipMalloc(&part, size_t(rows) * kMlpParams * 4);
+  if (e == hipSuccess) e = hipMalloc(&pl, size_t(rows) * 4);
+  if (e == hipSuccess) e = hipMalloc(&dloss, 4);
+  if (e == hipSuccess) e = hipMemcpyAsync(dx, features, size_t(n) * kMlpIn * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dt, log_seconds, size_t(n) * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_mlp_normalize(dx, dt, n, nm, s);
+  // mini-batches in a fixed order; Adam after each
+  for (int64_t ep = 0; ep < epochs && e == hipSuccess; ++ep)
+    for (int64_t b0 = 0; b0 < n && e == hipSuccess; b0 += bmax) {
+      const int64_t cnt = std::min(bmax, n - b0);
+      e = launch_mlp_loss_grad(m->d_params, dx + b0 * kMlpIn, dt + b0, cnt, part, pl, m->d_grad,
+                               nullptr, s);
+      if (e == hipSuccess)
+        e = launch_adam(m->d_params, m->d_grad, m->d_m, m->d_v, kMlpParams, ++m->step, lr, 0.9f,
+                        0.999f, 1e-8f, s);
+    }
+  float loss = 0.f;
+  if (e == hipSuccess) e = launch_mlp_loss_grad(m->d_params, dx, dt, n, part, pl, m->d_grad, dloss, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&loss, dloss, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->params.data(), m->d_params, size_t(kMlpParams) * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  for (float* ptr : {dx, dt, part, pl, dloss})
+    if (ptr) (void)hipFree(ptr);
+  if (e != hipSuccess) return hip_fail(e, "cost model training");
+  if (final_loss) *final_loss = loss;  // mean squared error in normalised log-time units
+  return BSM_OK;
+}
+
+bsm_status bsm_costmodel_predict(bsm_costmodel* m, const float* features, int64_t n,
+                                 float* log_seconds, void* stream) {
+  if (!m) return fail(BSM_E_INVALID, "model is null");
+  if (n < 0 || (n > 0 && (!features || !log_seconds))) return fail(BSM_E_INVALID, "null argument");
+  return model_predict(m, features, n, log_seconds, static_cast<hipStream_t>(stream));
+}
+
+bsm_status bsm_costmodel_save(const bsm_costmodel* m, const char* path) {
+  if (!m || !path) return fail(BSM_E_INVALID, "null argument");
+  std::vector<float> mv(size_t(2 * kMlpParams), 0.f);
+  if (m->d_m) {
+    BSM_HIP(hipMemcpy(mv.data(), m->d_m, size_t(kMlpParams) * 4, hipMemcpyDeviceToHost), "hipMemcpy(model)");
+    BSM_HIP(hipMemcpy(mv.data() + kMlpParams, m->d_v, size_t(kMlpParams) * 4, hipMemcpyDeviceToHost), "hipMemcpy(model)");
+  }
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(BSM_E_INVALID, std::string("cannot open ") + path);
+  const char magic[8] = {'B', 'S', 'M', 'C', 'M', '0', '0', '1'};
+  const int32_t count = kMlpParams;
+  bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&count, 4, 1, f) == 1 &&
+            std::fwrite(&m->step, 8, 1, f) == 1 && std::fwrite(&m->norm, sizeof(MlpNorm), 1, f) == 1 &&
+            std::fwrite(m->params.data(), 4, size_t(kMlpParams), f) == size_t(kMlpParams) &&
+            std::fwrite(mv.data(), 4, mv.size(), f) == mv.size();
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? BSM_OK : fail(BSM_E_INVALID, std::string("write failed: ") + path);
+}
+
+bsm_status bsm_costmodel_load(bsm_costmodel** out, const char* path) {
+  if (!out || !path) return fail(BSM_E_INVALID, "null argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(BSM_E_INVALID, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t count = 0;
+  bsm_costmodel* m = new (std::nothrow) bsm_costmodel;
+  if (!m) {
+    std::fclose(f);
+    return fail(BSM_E_NOMEM, "host allocation failed");
+  }
+  m->params.assign(size_t(kMlpParams), 0.f);
+  std::vector<float> mv(size_t(2 * kMlpParams));
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "BSMCM001", 8) == 0 &&
+            std::fread(&count, 4, 1, f) == 1 && count == kMlpParams &&
+            std::fread(&m->step, 8, 1, f) == 1 && std::fread(&m->norm, sizeof(MlpNorm), 1, f) == 1 &&
+            std::fread(m->params.data(), 4, size_t(kMlpParams), f) == size_t(kMlpParams) &&
+            std::fread(mv.data(), 4, mv.size(), f) == mv.size();
+  std::fclose(f);
+  if (!ok) {
+    delete m;
+    return fail(BSM_E_INVALID, std::string("not a cost model file: ") + path);
+  }
+  bsm_status st = model_device(m);
+  if (st == BSM_OK) {
+    hipError_t e = hipMemcpy(m->d_m, mv.data(), size_t(kMlpParams) * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d_v, mv.data() + kMlpParams, size_t(kMlpParams) * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) st = hip_fail(e, "hipMemcpy(model)");
+  }
+  if (st != BSM_OK) {
+    bsm_costmodel_destroy(m);
+    return st;
+  }
+  *out = m;
+  return BSM_OK;
+}
+
+bsm_status bsm_costmodel_destroy(bsm_costmodel* m) {
+  if (!m) return BSM_OK;
+  for (float* ptr : {m->d_params, m->d_m, m->d_v, m->d_grad})
+    if (ptr) (void)hipFree(ptr);
+  delete m;
+  return BSM_OK;
+}
+
+bsm_status bsm_plan_set_costmodel(bsm_plan* plan, bsm_costmodel* model, void* stream) {
+  if (!plan || !model) return fail(BSM_E_INVALID, "null argument");
+  bsm_status st = apply_model(plan->hp, model, static_cast<hipStream_t>(stream));
+  if (st == BSM_OK) {
+    plan->tasks_dirty = true;
+    plan->hp.cfg.sched = BSM_SCHED_MLP;
+  }
+  return st;
+}
+
+bsm_status bsm_batch_set_costmodel(bsm_batch* batch, bsm_costmodel* model, void* stream) {
+  if (!batch || !model) return fail(BSM_E_INVALID, "null argument");
+  bsm_status st = apply_model(batch->hp, model, static_cast<hipStream_t>(stream));
+  if (st == BSM_OK) {
+    batch->tasks_dirty = true;
+    batch->hp.cfg.sched = BSM_SCHED_MLP;
+  }
+  return st;
+}
+
+// Device-pointer entry points of the network itself (no normalisation), for checking its
+// arithmetic: forward, mean-squared-error loss with gradient, and one Adam step.
+bsm_status bsm_mlp_forward(const float* d_params, const float* d_x, int64_t n, float* d_y,
+                           void* stream) {
+  if (n < 0 || (n > 0 && (!d_params || !d_x || !d_y))) return fail(BSM_E_INVALID, "null argument");
+  int dev;
+  bsm_status st = check_device(&dev);
+  if (st != BSM_OK) return st;
+  BSM_HIP(launch_mlp_forward(d_params, d_x, n, d_y, identity_norm(), static_cast<hipStream_t>(stream)),
+          "mlp forward");
+  return BSM_OK;
+}
+
+bsm_status bsm_mlp_loss_grad(const float* d_params, const float* d_x, const float* d_t, int64_t n,
+                             float* d_grad, float* d_loss, void* stream) {
+  if (n <= 0 || !d_params || !d_x || !d_t || !d_grad) return fail(BSM_E_INVALID, "null argument");
+  int dev;
+  bsm_status st = check_device(&dev);
+  if (st != BSM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t rows = mlp_partial_rows(n);
+  float *part = nullptr, *pl = nullptr;
+  hipError_t e = hipMalloc(&part, size_t(rows) * kMlpParams * 4);
+  if (e == hipSuccess) e = hipMalloc(&pl, size_t(rows) * 4);
+  if (e == hipSuccess) e = launch_mlp_loss_grad(d_params, d_x, d_t, n, part, pl, d_grad, d_loss, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the workspace is freed below
+  if (part) (void)hipFree(part);
+  if (pl) (void)hipFree(pl);
+  if (e != hipSuccess) return hip_fail(e, "mlp loss/gradient");
+  return BSM_OK;
+}
+
+bsm_status bsm_adam_step(float* d_params, const float* d_grad, float* d_m, float* d_v, int64_t n,
+                         int64_t step, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (n < 0 || step < 1 || (n > 0 && (!d_params || !d_grad || !d_m || !d_v)))
+    return fail(BSM_E_INVALID, "bad argument");
+  int dev;
+  bsm_status st = check_device(&dev);
+  if (st != BSM_OK) return st;
+  BSM_HIP(launch_adam(d_params, d_grad, d_m, d_v, n, step, lr, beta1, beta2, eps,
+                      static_cast<hipStream_t>(stream)),
+          "adam");
+  return BSM_OK;
 }
 
 }  // extern "C"

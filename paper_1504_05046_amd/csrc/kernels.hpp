@@ -40,4 +40,30 @@ hipError_t launch_split_bf16x3(const SplitBlock* blocks, int64_t nblocks, const 
 
 hipError_t launch_tiles_bf16x3(int variant, int64_t grid, const TileArgs& args, hipStream_t stream);
 
+// Task cost model network: kMlpIn features -> kMlpHidden -> kMlpHidden -> 1, ReLU.
+constexpr int kMlpIn = 5, kMlpHidden = 32;
+constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpHidden + 1;
+
+// Affine maps around the network: x' = (x - fmean) / fstd on the way in, y' = y * tstd + tmean
+// on the way out (identity: means 0, stds 1).
+struct MlpNorm {
+  float fmean[kMlpIn], fstd[kMlpIn];
+  float tmean, tstd;
+};
+
+hipError_t launch_mlp_forward(const float* params, const float* X, int64_t n, float* Y,
+                              const MlpNorm& norm, hipStream_t s);
+// rows of per-chunk partial sums the gradient needs for n samples
+int64_t mlp_partial_rows(int64_t n);
+// grad (kMlpParams) and mean squared error loss over X (n x kMlpIn) against T (n); part must hold
+// mlp_partial_rows(n) x kMlpParams floats, part_loss mlp_partial_rows(n) floats; loss may be NULL.
+hipError_t launch_mlp_loss_grad(const float* params, const float* X, const float* T, int64_t n,
+                                float* part, float* part_loss, float* grad, float* loss,
+                                hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int64_t step,
+                       float lr, float b1, float b2, float eps, hipStream_t s);
+// X[i][f] = (X[i][f] - mean[f]) / std[f], T[i] = (T[i] - tmean) / tstd, in place
+hipError_t launch_mlp_normalize(float* X, float* T, int64_t n, const MlpNorm& norm, hipStream_t s);
+
 }  // namespace bsm

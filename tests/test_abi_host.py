@@ -189,3 +189,20 @@ def test_binding_rejects_short_buffers():
         plan.execute(A[:-1], B, torch.zeros(info.c_elems, dtype=torch.float64))
     with pytest.raises(ValueError, match="device"):
         plan.execute(A, B, torch.zeros(info.c_elems, dtype=torch.float64))
+
+
+def test_costmodel_host_side():
+    m = bsm.CostModel(seed=3)
+    p, norm = m.params()
+    assert p.size == bsm.mlp_param_count() == 32 * 5 + 32 + 32 * 32 + 32 + 32 + 1
+    assert np.all(np.isfinite(p)) and np.all(p[32 * 5:32 * 5 + 32] == 0)        # b1 = 0
+    assert np.abs(p[:160]).max() <= np.sqrt(6 / 5) + 1e-6                        # He-uniform
+    assert list(norm) == [0] * 5 + [1] * 5 + [0, 1]
+    q = bsm.CostModel(seed=3).params()[0]
+    assert np.array_equal(p, q)                                                  # seeded
+    assert not np.array_equal(p, bsm.CostModel(seed=4).params()[0])
+    m.set_params(p * 2, np.array([1, 2, 3, 4, 5, 1, 1, 1, 1, 2, 0.5, 3], np.float32))
+    p2, n2 = m.params()
+    assert np.array_equal(p2, p * 2) and n2[9] == 2 and n2[11] == 3
+    _expect(bsm.E_MISMATCH, lambda: m.set_params(p[:-1]))
+    _expect(bsm.E_INVALID, lambda: m.set_params(None, np.array([0] * 5 + [0] + [1] * 4 + [0, 1], np.float32)))
