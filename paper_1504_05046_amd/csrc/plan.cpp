@@ -159,6 +159,20 @@ void schedule(HostPlan& p, const std::vector<double>& cost) {
       bins[size_t(x)].push_back(q);
       load[size_t(x)] += cost[q];
     }
+  } else if (p.cfg.order == ORDER_INTERLEAVE) {
+    // whole C blocks (consecutive tasks with the same C offset) dealt to the least-loaded XCD in
+    // C-block order
+    std::vector<double> load(kXcds, 0.0);
+    size_t q = 0;
+    while (q < n) {
+      size_t e = q + 1;
+      double c = cost[q];
+      while (e < n && p.items[e].c_off == p.items[q].c_off && p.items[e].product == p.items[q].product) c += cost[e++];
+      int x = int(std::min_element(load.begin(), load.end()) - load.begin());
+      for (size_t r = q; r < e; ++r) bins[size_t(x)].push_back(r);
+      load[size_t(x)] += c;
+      q = e;
+    }
   } else {
     // keep the C-block order (sub-tiles of a block and blocks of a block row stay together, so
     // they share A and B tiles in one XCD's L2) and cut it into kXcds runs of equal cost

@@ -21,7 +21,10 @@ constexpr Variant kBf16Variants[] = {BSM_BF16_VARIANTS(BSM_VARIANT_ROW)};
 constexpr int kNumBf16Variants = int(sizeof(kBf16Variants) / sizeof(kBf16Variants[0]));
 #undef BSM_VARIANT_ROW
 
-enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1 };
+// Task order: LOCALITY keeps C-block order and cuts it into one contiguous run per XCD; LPT sorts
+// by cost and bins greedily; INTERLEAVE keeps C-block order but deals whole C blocks round-robin
+// over the XCDs, so that all XCDs work on the same region of C at the same time.
+enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1, ORDER_INTERLEAVE = 2 };
 
 struct PlanConfig {
   int precision = 0;
