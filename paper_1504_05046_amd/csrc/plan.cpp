@@ -4,6 +4,7 @@
 // one present C block together with that block's whole k-list, so the multiply and the reduction
 // into C are one task (no temporaries, one writer per C element).
 #include "plan.hpp"
+#include "wave_rects.inc"
 
 #include <algorithm>
 #include <array>
@@ -63,8 +64,9 @@ static int64_t pack_offsets(int64_t R, int64_t C, const std::vector<int64_t>& rs
 
 // Sub-tile cuts of one C block.  A dimension of nb16 16-row blocks is cut into the fewest
 // pieces of at most `per` blocks; among all such cuts of both dimensions the planner takes the
-// one whose slowest wave issues the fewest MFMAs (a workgroup's NW waves share a sub-tile's
-// 16x16 output blocks round-robin, so a sub-tile of b blocks costs ceil(b / NW) per k-step).
+// one whose slowest wave issues the fewest MFMAs (each of a workgroup's NW waves owns a rectangle
+// of the sub-tile's 16x16 output blocks; the busiest owns wave_rect_max blocks, which is
+// ceil(blocks / NW) for all but a few shapes).
 static void compositions(int total, int parts, int per, std::vector<int>& cur,
                          std::vector<std::vector<int>>& out) {
   if (parts == 1) {
@@ -113,7 +115,10 @@ static const CutChoice& best_cut(int br, int bc, int per_r, int per_c, int nw, b
     for (auto& c : cc) {
       int64_t cost = 0;
       for (int a : r)
-        for (int b : c) cost += (a * b + nw - 1) / nw;
+        for (int b : c) {
+          const int mx = wave_rect_max(16 * per_r, 16 * per_c, nw, a, b);
+          cost += mx > 0 ? mx : (a * b + nw - 1) / nw;
+        }
       if (best < 0 || cost < best) {
         best = cost;
         choice.rows = r;

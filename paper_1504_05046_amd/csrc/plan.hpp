@@ -32,7 +32,7 @@ struct PlanConfig {
   int64_t k_window = 0;
   int record_timings = 0;
   int tile = 0;       // 0 = auto, else variant id + 1
-  int order = ORDER_LOCALITY;
+  int order = ORDER_INTERLEAVE;
   bool cut_search = false;  // choose sub-tile cuts by slowest-wave cost (else near-equal pieces)
 };
 

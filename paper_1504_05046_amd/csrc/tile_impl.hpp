@@ -3,8 +3,9 @@
 // One workgroup (NW waves) executes one task: a C sub-tile of h x w (h <= TM, w <= TN) and the
 // k-list of its C block (the triples whose k lies in the current k-window).  For every triple, in
 // ascending k, the workgroup streams KC-wide k-chunks of A_ik (rows r0..r0+h) and B_kj (cols
-// c0..c0+w) from HBM into LDS (double-buffered, one barrier per chunk), and the waves share the
-// sub-tile's 16x16 output blocks round-robin.  FP64 form: v_mfma_f64_16x16x4 into FP64
+// c0..c0+w) from HBM into LDS (double-buffered, one barrier per chunk).  Each wave owns a
+// rectangle of na x nb of the sub-tile's 16x16 output blocks (a generated table, balanced across
+// the waves), so that one 4-deep MFMA step reads na + nb fragments from LDS for na * nb MFMAs.  FP64 form: v_mfma_f64_16x16x4 into FP64
 // registers across the whole k-list.  FP32 form: v_mfma_f32_16x16x4 into FP32 registers within
 // one block product A_ik B_kj, folded into FP64 registers when the triple ends.  The epilogue
 // writes alpha*acc (+C) once per element: the paper's multiply task and reduction task fused,
@@ -13,6 +14,7 @@
 
 #pragma once
 #include "kernels.hpp"
+#include "wave_rects.inc"
 
 namespace bsm {
 
@@ -57,22 +59,23 @@ struct TileCfg {
   static constexpr int KC = KC_;            // k-chunk staged per step
   static constexpr int NW = NW_;            // waves per workgroup
   static constexpr int NT = 64 * NW;        // threads per workgroup
-  // A chunk: TM rows x KC.  With KC = 16 the rows are unpadded and the k index is XOR-swizzled
-  // with bits 1..3 of the row, which keeps both the staging stores (two rows per half-wave) and
-  // the fragment reads (16 rows per half-wave) free of bank conflicts; otherwise rows are padded.
-  static constexpr bool SWZ = false;
-  static constexpr int ASTR = SWZ ? KC : (KC == 16 ? KC + 1 : KC + 2);
+  // A chunk (TM rows x KC) in LDS, step-major: k = 4s + g (s = MFMA step, g = lane group) is
+  // stored at s * APL + 4 row + (g ^ 2 * bit3(row)), planes APL = 4 TM + 8 apart.  The XOR on g
+  // separates rows r and r + 8, so a half-wave's fragment reads (16 rows, two g) hit distinct
+  // banks; the 8-element plane padding does the same for the staging stores (two rows, all s);
+  // and every step's reads sit at a compile-time offset from one per-lane address.
+  static constexpr int APL = 4 * TM + 8;
+  __device__ static inline int apos(int row, int k) {
+    return (k >> 2) * APL + 4 * row + ((k & 3) ^ (((row >> 3) & 1) << 1));
+  }
   // B chunk: KC rows x TN, padded so that a half-wave's fragment reads hit distinct banks
   static constexpr int BSTR = TN + 16;
-  __device__ static inline int apos(int row, int k) {
-    return row * ASTR + (SWZ ? (k ^ (row & 14)) : k);
-  }
-  static constexpr int SLOTS = ((TM / 16) * (TN / 16) + NW - 1) / NW;  // 16x16 blocks per wave
+  static constexpr int PA = TM / 16, PB = TN / 16;  // 16x16 output blocks per sub-tile side
   static constexpr int ARP = NT / KC;       // A rows staged per pass (KC threads per row)
   static constexpr int ALD = TM / ARP;      // A elements each thread stages per chunk
   static constexpr int BK = NT / TN;        // B k-rows staged per pass (TN threads per row)
   static constexpr int BLD = KC / BK;       // B elements each thread stages per chunk
-  static constexpr int ASZ = TM * ASTR;     // elements of one A stage
+  static constexpr int ASZ = (KC / 4) * APL;  // elements of one A stage
   static constexpr int BSZ = KC * BSTR;     // elements of one B stage
   static_assert(KC % 16 == 0 && NT % KC == 0 && TM % ARP == 0, "A staging shape");
   static_assert(TN <= NT && NT % TN == 0 && KC % BK == 0, "B staging shape");
@@ -101,31 +104,29 @@ __device__ inline uint32_t lower_bound_k(const Triple* __restrict__ tri, uint32_
   return tb;
 }
 
-// The part of a task one wave runs when it owns NS of the sub-tile's 16x16 output blocks.
-// Every wave of the workgroup walks the same k-chunks and meets the same barriers; NS is a
-// compile-time constant so that the MFMA stream has no per-block branches.
-template <int TM, int TN, int KC, int NW, int FORM, bool RESUME, int NS>
+// The part of a task one wave runs when it owns the NA x NB output blocks whose top-left block
+// is (rb0, cb0); block j = x NB + y is (rb0 + x, cb0 + y).  Every wave of the workgroup walks the
+// same k-chunks and meets the same barriers; NA and NB are compile-time constants so that the
+// MFMA stream has no per-block branches.
+template <int TM, int TN, int KC, int NW, int FORM, bool RESUME, int NA, int NB>
 __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, const ProductArgs& pa,
-                                         int wave, typename FormT<FORM>::T* As,
+                                         int rb0, int cb0, typename FormT<FORM>::T* As,
                                          typename FormT<FORM>::T* Bs) {
   using C = TileCfg<TM, TN, KC, NW, FORM>;
   using F = FormT<FORM>;
   using T = typename C::T;
+  constexpr int NS = NA * NB;
   constexpr int NSA = NS > 0 ? NS : 1;
   const int tid = threadIdx.x, lane = tid & 63;
   const int g = lane >> 4, i16 = lane & 15;
   const int h = it.h, w = it.w, ldc = it.ldc;
-  const int bcn = (w + 15) >> 4;
 
-  // this wave's output blocks q = wave, wave+NW, ... (row-major over the sub-tile's blocks)
-  int a_u[NSA], b_u[NSA];
+  // LDS offsets of this wave's A fragments (per block row) and B fragments (per block column)
+  int a_u[NA > 0 ? NA : 1], b_u[NB > 0 ? NB : 1];
 #pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    int q = wave + NW * j;
-    int rb = q / bcn, cb = q - rb * bcn;
-    a_u[j] = 16 * rb * C::ASTR;
-    b_u[j] = 16 * cb;
-  }
+  for (int x = 0; x < NA; ++x) a_u[x] = 64 * (rb0 + x);
+#pragma unroll
+  for (int y = 0; y < NB; ++y) b_u[y] = 16 * (cb0 + y);
   const int64_t c_base = it.c_off + int64_t(it.r0) * ldc + it.c0;
 
   // FP64 accumulators; with a k-window after the first they resume from the raw partial sums
@@ -137,9 +138,8 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
   for (int j = 0; j < NS; ++j) {
     acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
     if constexpr (RESUME) {
-      int q = wave + NW * j;
-      int rbk = q / bcn, cbk = q - rbk * bcn;
-      int col = 16 * cbk + i16;
+      const int rbk = rb0 + j / (NB > 0 ? NB : 1), cbk = cb0 + j % (NB > 0 ? NB : 1);
+      const int col = 16 * cbk + i16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int row = 16 * rbk + F::out_row(g, r);
@@ -229,34 +229,26 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
     if (NS > 0) {
       const T* as = As + buf * C::ASZ;
       const T* bs = Bs + buf * C::BSZ + g * C::BSTR + i16;
-      // one 4-deep MFMA step per iteration; steps past the block's end hold only zeros and are
-      // skipped (the condition is the same for the whole wave)
+      // one 4-deep MFMA step per iteration: NA A fragments and NB B fragments, then the NA x NB
+      // products; steps past the block's end hold only zeros and are skipped (the condition is the
+      // same for the whole wave)
 #pragma unroll
       for (int s = 0; s < C::KC / 4; ++s) {
         if (s < nsteps) {
-          // fragments are read in groups of up to GM blocks to bound register use
-          constexpr int GM = NW >= 8 ? 4 : 8;
+          T av[NA > 0 ? NA : 1], bv[NB > 0 ? NB : 1];
 #pragma unroll
-          for (int j0 = 0; j0 < NS; j0 += GM) {
-            constexpr int G = NS < GM ? NS : GM;
-            T av[G > 0 ? G : 1], bv[G > 0 ? G : 1];
+          for (int x = 0; x < NA; ++x) av[x] = as[a_u[x] + C::apos(i16, 4 * s + g)];
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-              if (j0 + j < NS) {
-                av[j] = as[a_u[j0 + j] + C::apos(i16, 4 * s + g)];
-                bv[j] = bs[b_u[j0 + j] + 4 * s * C::BSTR];
-              }
+          for (int y = 0; y < NB; ++y) bv[y] = bs[b_u[y] + 4 * s * C::BSTR];
+#pragma unroll
+          for (int x = 0; x < NA; ++x) {
+#pragma unroll
+            for (int y = 0; y < NB; ++y) {
+              if constexpr (FORM == FORM_F64)
+                acc[x * NB + y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x * NB + y], 0, 0, 0);
+              else
+                acc32[x * NB + y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc32[x * NB + y], 0, 0, 0);
             }
-#pragma unroll
-            for (int j = 0; j < G; ++j) {
-              if (j0 + j < NS) {
-                if constexpr (FORM == FORM_F64)
-                  acc[j0 + j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], acc[j0 + j], 0, 0, 0);
-                else
-                  acc32[j0 + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[j], acc32[j0 + j], 0, 0, 0);
-              }
-            }
-            __builtin_amdgcn_sched_barrier(0);
           }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -286,9 +278,8 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
   const double alpha = pa.alpha;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
-    int q = wave + NW * j;
-    int rbk = q / bcn, cbk = q - rbk * bcn;
-    int col = 16 * cbk + i16;
+    const int rbk = rb0 + j / (NB > 0 ? NB : 1), cbk = cb0 + j % (NB > 0 ? NB : 1);
+    const int col = 16 * cbk + i16;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int row = 16 * rbk + F::out_row(g, r);
@@ -305,16 +296,25 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
   }
 }
 
-template <int TM, int TN, int KC, int NW, int FORM, bool RESUME, int NS>
-__device__ __forceinline__ void dispatch_ns(int ns, const TileArgs& a, const Item& it,
-                                            const ProductArgs& pa, int wave,
-                                            typename FormT<FORM>::T* As,
-                                            typename FormT<FORM>::T* Bs) {
-  if constexpr (NS > TileCfg<TM, TN, KC, NW, FORM>::SLOTS) {
+// Selects the instantiation for the wave's rectangle shape among those the table holds.
+template <int TM, int TN, int KC, int NW, int FORM, bool RESUME, int NA, int NB>
+__device__ __forceinline__ void dispatch_rect(int na, int nb, int rb0, int cb0, const TileArgs& a,
+                                              const Item& it, const ProductArgs& pa,
+                                              typename FormT<FORM>::T* As,
+                                              typename FormT<FORM>::T* Bs) {
+  constexpr int PA = TM / 16, PB = TN / 16;
+  if constexpr (NA > PA) {
     return;
+  } else if constexpr (NB > PB) {
+    dispatch_rect<TM, TN, KC, NW, FORM, RESUME, NA + 1, 0>(na, nb, rb0, cb0, a, it, pa, As, Bs);
   } else {
-    if (ns == NS) run_task<TM, TN, KC, NW, FORM, RESUME, NS>(a, it, pa, wave, As, Bs);
-    else dispatch_ns<TM, TN, KC, NW, FORM, RESUME, NS + 1>(ns, a, it, pa, wave, As, Bs);
+    if constexpr (WaveRects<PA, PB, NW>::used[NA][NB]) {
+      if (na == NA && nb == NB) {
+        run_task<TM, TN, KC, NW, FORM, RESUME, NA, NB>(a, it, pa, rb0, cb0, As, Bs);
+        return;
+      }
+    }
+    dispatch_rect<TM, TN, KC, NW, FORM, RESUME, NA, NB + 1>(na, nb, rb0, cb0, a, it, pa, As, Bs);
   }
 }
 
@@ -334,9 +334,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void tiles(TileArgs a) {
   const Item it = a.items[idx];
   const ProductArgs pa = a.prods ? a.prods[it.product] : a.single;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nb = ((it.h + 15) >> 4) * ((it.w + 15) >> 4);
-  const int ns = nb > wave ? (nb - wave + NW - 1) / NW : 0;  // output blocks of this wave
-  dispatch_ns<TM, TN, KC, NW, FORM, RESUME, 0>(ns, a, it, pa, wave, As, Bs);
+  // this wave's rectangle of the sub-tile's output blocks (1 <= h <= TM, 1 <= w <= TN)
+  const uint32_t rect = WaveRects<TM / 16, TN / 16, NW>::get((it.h + 15) >> 4, (it.w + 15) >> 4, wave);
+  const int rb0 = int(rect & 0xFF), cb0 = int((rect >> 8) & 0xFF);
+  const int na = int((rect >> 16) & 0xFF), nb = int(rect >> 24);
+  dispatch_rect<TM, TN, KC, NW, FORM, RESUME, 0, 0>(na, nb, rb0, cb0, a, it, pa, As, Bs);
   if (a.stamps) {
     __syncthreads();
     if (threadIdx.x == 0) a.stamps[2 * idx + 1] = wall_clock64();
