@@ -85,12 +85,47 @@ struct TileCfg {
 // in scalar registers.
 __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ inline uint32_t uni(uint32_t v) { return uint32_t(__builtin_amdgcn_readfirstlane(int(v))); }
-template <typename P>
-__device__ inline P* uni_ptr(P* p) {
-  uint64_t v = reinterpret_cast<uint64_t>(p);
+__device__ inline uint64_t uni(uint64_t v) {
   uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
   uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
-  return reinterpret_cast<P*>((uint64_t(hi) << 32) | lo);
+  return (uint64_t(hi) << 32) | lo;
+}
+template <typename P>
+__device__ inline P* uni_ptr(P* p) {
+  return reinterpret_cast<P*>(uni(reinterpret_cast<uint64_t>(p)));
+}
+// A task, its operands and its triples are the same for the whole wave: keeping them in scalar
+// registers keeps the per-chunk address arithmetic on the scalar unit.
+__device__ inline Triple uni(const Triple& t) {
+  Triple r;
+  r.a = uni(t.a);
+  r.b = uni(t.b);
+  return r;
+}
+__device__ inline Item uni(const Item& it) {
+  Item r;
+  r.c_off = int64_t(uni(uint64_t(it.c_off)));
+  r.tri_begin = uni(it.tri_begin);
+  r.tri_count = uni(it.tri_count);
+  r.r0 = uint16_t(uni(uint32_t(it.r0)));
+  r.c0 = uint16_t(uni(uint32_t(it.c0)));
+  r.h = uint16_t(uni(uint32_t(it.h)));
+  r.w = uint16_t(uni(uint32_t(it.w)));
+  r.ldc = uint16_t(uni(uint32_t(it.ldc)));
+  r.variant = uint16_t(uni(uint32_t(it.variant)));
+  r.product = uni(it.product);
+  return r;
+}
+__device__ inline ProductArgs uni(const ProductArgs& p) {
+  ProductArgs r;
+  r.A = uni_ptr(p.A);
+  r.B = uni_ptr(p.B);
+  r.C = uni_ptr(p.C);
+  r.P = uni_ptr(p.P);
+  r.alpha = __builtin_bit_cast(double, uni(__builtin_bit_cast(uint64_t, p.alpha)));
+  r.a_plane = int64_t(uni(uint64_t(p.a_plane)));
+  r.b_plane = int64_t(uni(uint64_t(p.b_plane)));
+  return r;
 }
 
 // First triple of [tb, te) whose inner block index is >= k (the k-lists are sorted by k).
@@ -204,7 +239,7 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
   int kk = 0;
   Triple tc;
   if (t < te) {
-    tc = a.tri[t];
+    tc = uni(a.tri[t]);
     load(tc, 0);
     store(0);
   }
@@ -221,7 +256,7 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
     if (triple_ends) {
       tn = t + 1;
       kn = 0;
-      if (tn < te) tnx = a.tri[tn];
+      if (tn < te) tnx = uni(a.tri[tn]);
     }
     const bool more = tn < te;
     if (more) load(tnx, kn);
@@ -331,8 +366,8 @@ __global__ __launch_bounds__(64 * NW, OCC) void tiles(TileArgs a) {
   const int idx = a.map.begin[x] + qx;
   if (idx >= a.map.begin[x + 1]) return;
   if (a.stamps && threadIdx.x == 0) a.stamps[2 * idx] = wall_clock64();
-  const Item it = a.items[idx];
-  const ProductArgs pa = a.prods ? a.prods[it.product] : a.single;
+  const Item it = uni(a.items[idx]);
+  const ProductArgs pa = uni(a.prods ? a.prods[it.product] : a.single);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // this wave's rectangle of the sub-tile's output blocks (1 <= h <= TM, 1 <= w <= TN)
   const uint32_t rect = WaveRects<TM / 16, TN / 16, NW>::get((it.h + 15) >> 4, (it.w + 15) >> 4, wave);
