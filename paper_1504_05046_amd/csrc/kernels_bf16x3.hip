@@ -7,8 +7,9 @@
 // triple ends; the epilogue writes alpha*sum (+C) in FP64 once per element.
 //
 // One workgroup of 8 waves runs one task (a C sub-tile of up to 128 x 128 and its k-list).  The
-// k-list is streamed in 32-deep chunks (one MFMA step): the three slices of A (rows) and of B
-// (columns, stored k-contiguous) go through double-buffered LDS with 16-byte loads and stores.
+// k-list is streamed in 32-deep chunks (one MFMA step, one k-panel of the slice planes, whose rows
+// are contiguous): the three slices of A (rows) and of B (columns, stored k-contiguous) go through
+// double-buffered LDS with 16-byte loads and stores.
 // The waves form a 4 x 2 grid; each owns 2 x 4 of the sub-tile's 16x16 output blocks and reuses
 // every fragment it reads from LDS across a row or column of its blocks.
 #include <hip/hip_runtime.h>
@@ -96,20 +97,22 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
   const uint16_t* Ag = static_cast<const uint16_t*>(pa.A);
   const uint16_t* Bg = static_cast<const uint16_t*>(pa.B);
   u4 ra[C::ALD], rb[C::BLD];
-  // granule q of a stage: slice q / (rows*4), row (q % (rows*4)) / 4, k-octet q % 4
+  // granule q of a stage: slice q / (rows*4), row (q % (rows*4)) / 4, k-octet q % 4.  The chunk
+  // is one 32-wide k-panel of the slice planes, whose rows are contiguous: the sub-tile's rows
+  // r0..r0+h of A_ik (a panel of ldm rows) and columns c0..c0+w of B_kj (a panel of ldc columns)
+  // are one run of 64-byte rows each.
   auto load = [&](const Triple& t, int kk) {
-    const int ks32 = int(pad_k(tri_ks(t)));
-    const uint16_t* ab = Ag + tri_a_off(t) + int64_t(it.r0) * ks32 + kk;
-    const uint16_t* bb = Bg + tri_b_off(t) + int64_t(it.c0) * ks32 + kk;
+    const uint16_t* ab = Ag + tri_a_off(t) + int64_t(kk) * it.ldm + int64_t(it.r0) * kSliceK;
+    const uint16_t* bb = Bg + tri_b_off(t) + int64_t(kk) * it.ldc + int64_t(it.c0) * kSliceK;
     // rows past h (columns past w) fall outside the descriptor and read 0
-    const int na = uni(h * ks32 * 2), nb = uni(w * ks32 * 2);
+    const int na = uni(h * kSliceK * 2), nb = uni(w * kSliceK * 2);
 #pragma unroll
     for (int p = 0; p < C::ALD; ++p) {
       const int q = tid + C::NT * p;
       const int s = q / (TM * 4), rem = q - s * (TM * 4);
       const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
           uni_ptr(const_cast<uint16_t*>(ab + s * pa.a_plane)), (short)0, na, kRsrcWord3b);
-      ra[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * ks32 + 8 * (rem & 3)) * 2), 0, 0);
+      ra[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * kSliceK + 8 * (rem & 3)) * 2), 0, 0);
     }
 #pragma unroll
     for (int p = 0; p < C::BLD; ++p) {
@@ -117,7 +120,7 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
       const int s = q / (TN * 4), rem = q - s * (TN * 4);
       const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
           uni_ptr(const_cast<uint16_t*>(bb + s * pa.b_plane)), (short)0, nb, kRsrcWord3b);
-      rb[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * ks32 + 8 * (rem & 3)) * 2), 0, 0);
+      rb[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * kSliceK + 8 * (rem & 3)) * 2), 0, 0);
     }
   };
   auto store = [&](int buf) {

@@ -43,8 +43,9 @@ __device__ inline void split3(double a, uint16_t& s0, uint16_t& s1, uint16_t& s2
 }
 
 // One workgroup per operand block: writes the block's three slices into the planes (plane p at
-// dst + p * plane), inner size padded with zeros to a multiple of 32; B blocks are transposed
-// through LDS in 32 x 64 tiles so that both the reads and the writes are coalesced.
+// dst + p * plane), inner size padded with zeros to a multiple of 32, in 32-wide k-panels (element
+// (r, k) of a block of R rows at (k / 32) * 32 R + 32 r + k % 32); B blocks are transposed through
+// LDS in 32 x 64 tiles so that both the reads and the writes are coalesced.
 __global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict__ blocks,
                                                     const double* __restrict__ src,
                                                     uint16_t* __restrict__ dst, int64_t plane) {
@@ -57,8 +58,10 @@ __global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict
   uint16_t* d2 = d1 + plane;
   if (!b.transpose) {
     const int64_t n = int64_t(b.rows) * ks32;
+    const int64_t panel = int64_t(b.rows) * kSliceK;
     for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-      const int r = int(e / ks32), k = int(e - int64_t(r) * ks32);
+      const int64_t kc = e / panel, rem = e - kc * panel;
+      const int r = int(rem / kSliceK), k = int(kc * kSliceK + (rem - int64_t(r) * kSliceK));
       const double v = k < b.ks ? sb[int64_t(r) * b.ld_src + k] : 0.0;
       uint16_t x0, x1, x2;
       split3(v, x0, x1, x2);
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict
         if (c < b.rows) {
           uint16_t x0, x1, x2;
           split3(tile[kk][cc], x0, x1, x2);
-          const int64_t o = int64_t(c) * ks32 + k0 + kk;
+          const int64_t o = int64_t(k0) * b.rows + int64_t(c) * kSliceK + kk;
           d0[o] = x0;
           d1[o] = x1;
           d2[o] = x2;

@@ -238,7 +238,7 @@ void cut_items(HostPlan& p, int variant) {
         it.c0 = uint16_t(c.first);
         it.w = uint16_t(c.second);
         it.ldc = uint16_t(cb.n);
-        it.variant = uint16_t(variant);
+        it.ldm = uint16_t(cb.m);
         it.product = 0;
         p.items.push_back(it);
         p.features.push_back(std::log(float(it.h)));

@@ -112,7 +112,7 @@ __device__ inline Item uni(const Item& it) {
   r.h = uint16_t(uni(uint32_t(it.h)));
   r.w = uint16_t(uni(uint32_t(it.w)));
   r.ldc = uint16_t(uni(uint32_t(it.ldc)));
-  r.variant = uint16_t(uni(uint32_t(it.variant)));
+  r.ldm = uint16_t(uni(uint32_t(it.ldm)));
   r.product = uni(it.product);
   return r;
 }

@@ -30,8 +30,10 @@ constexpr int kXcds = 8;                       // MI355X: 8 accelerator dies, ea
   X(0, 128, 128, 32, 8, 2)
 
 // Slice planes of the split-bf16 form: each block with its inner size padded to a multiple of 32
-// (zeros), A blocks row-major (rows x s32), B blocks transposed (cols x s32), so that both MFMA
-// operands read 8 consecutive k per lane.
+// (zeros), A blocks as rows x s32 and B blocks transposed (cols x s32), so that both MFMA operands
+// read 8 consecutive k per lane.  Within a block the 32-wide k-panels are stored one after the
+// other, each panel row-major (rows x 32): element (r, k) of a block of R rows sits at
+// (k / 32) * 32 R + 32 r + k % 32, so that the rows of one k-chunk are contiguous in memory.
 constexpr int kSliceK = 32;
 BSM_HD inline int64_t pad_k(int64_t ks) { return (ks + kSliceK - 1) / kSliceK * kSliceK; }
 
@@ -66,7 +68,7 @@ struct Item {
   uint32_t tri_count;
   uint16_t r0, c0, h, w;
   uint16_t ldc;       // C block width = width of every B_kj of the k-list
-  uint16_t variant;   // tile variant that executes it
+  uint16_t ldm;       // C block height = height of every A_ik of the k-list
   uint32_t product;   // index into the batch's operand table (0 for a single product)
 };
 static_assert(sizeof(Item) == 32, "Item layout");
