@@ -193,75 +193,99 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
   // B chunk row-major (TN consecutive threads read one k-row's columns)
   const int ka = tid % KC, ra0 = tid / KC;
   const int cbl = tid % TN, kb0 = tid / TN;
-  T ra[C::ALD], rb[C::BLD];
   const T* Ag = static_cast<const T*>(pa.A);
   const T* Bg = static_cast<const T*>(pa.B);
+
+  // Two sets of staging registers: while chunk c is computed from LDS, the loads of chunk c + 2
+  // are in flight into one set and chunk c + 1 waits in the other for its turn in LDS.
+  struct Regs {
+    T a[C::ALD], b[C::BLD];
+  };
+  Regs R0, R1;
 
   // Staging loads go through buffer descriptors: a load whose offset lies past num_records
   // returns 0 instead of touching memory.  A's descriptor ends at row h of the sub-tile, so rows
   // beyond it read 0; the k-tail (k >= s_k would wrap into the next row) is sent out of range
   // explicitly.  B's descriptor ends at the last element of the sub-tile's columns, so k-rows
   // beyond s_k read 0; columns beyond w read finite neighbours that only feed output columns the
-  // epilogue discards.
-  auto load = [&](const Triple& t, int kk) {
+  // epilogue discards.  A chunk past the end of the k-list is loaded with empty descriptors
+  // (zeros, no memory access), so that every chunk issues the same loads.
+  constexpr int NPART = C::KC / 4;
+  auto load = [&](const Triple& t, int kk, bool valid, Regs& R, int part) {
     const int ks = tri_ks(t);
     const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
         uni_ptr(const_cast<T*>(Ag + tri_a_off(t) + int64_t(it.r0) * ks)), (short)0,
-        uni(h * ks * C::ES), kRsrcWord3);
+        uni(valid ? h * ks * C::ES : 0), kRsrcWord3);
     const __amdgpu_buffer_rsrc_t br = __builtin_amdgcn_make_buffer_rsrc(
         uni_ptr(const_cast<T*>(Bg + tri_b_off(t) + it.c0)), (short)0,
-        uni(((ks - 1) * ldc + w) * C::ES), kRsrcWord3);
+        uni(valid ? ((ks - 1) * ldc + w) * C::ES : 0), kRsrcWord3);
     const bool kin = kk + ka < ks;
 #pragma unroll
     for (int p = 0; p < C::ALD; ++p) {
-      const uint32_t off = kin ? uint32_t(((ra0 + C::ARP * p) * ks + kk + ka) * C::ES) : kOutOfRange;
-      ra[p] = F::load(ar, off);
+      if (part < 0 || p % NPART == part) {
+        const uint32_t off = kin ? uint32_t(((ra0 + C::ARP * p) * ks + kk + ka) * C::ES) : kOutOfRange;
+        R.a[p] = F::load(ar, off);
+      }
     }
 #pragma unroll
     for (int p = 0; p < C::BLD; ++p) {
-      const uint32_t off = uint32_t(((kk + kb0 + C::BK * p) * ldc + cbl) * C::ES);
-      rb[p] = F::load(br, off);
+      if (part < 0 || p % NPART == part) {
+        const uint32_t off = uint32_t(((kk + kb0 + C::BK * p) * ldc + cbl) * C::ES);
+        R.b[p] = F::load(br, off);
+      }
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](const Regs& R, int buf) {
     T* as = As + buf * C::ASZ;
     T* bs = Bs + buf * C::BSZ;
 #pragma unroll
-    for (int p = 0; p < C::ALD; ++p) as[C::apos(ra0 + C::ARP * p, ka)] = ra[p];
+    for (int p = 0; p < C::ALD; ++p) as[C::apos(ra0 + C::ARP * p, ka)] = R.a[p];
 #pragma unroll
-    for (int p = 0; p < C::BLD; ++p) bs[(kb0 + C::BK * p) * C::BSTR + cbl] = rb[p];
+    for (int p = 0; p < C::BLD; ++p) bs[(kb0 + C::BK * p) * C::BSTR + cbl] = R.b[p];
   };
 
+  // A chunk's place in the k-list: triple index t (valid while t < te), its triple, and the
+  // offset kk of the chunk within the block's inner dimension.
+  struct Pos {
+    uint32_t t;
+    int kk;
+    Triple tri;
+  };
   uint32_t te = it.tri_begin + it.tri_count;
-  uint32_t t = it.tri_begin;
-  if (a.k_lo > 0) t = uni(lower_bound_k(a.tri, t, te, a.k_lo));
-  if (a.k_hi < kNoKLimit) te = uni(lower_bound_k(a.tri, t, te, a.k_hi));
-  int kk = 0;
-  Triple tc;
-  if (t < te) {
-    tc = uni(a.tri[t]);
-    load(tc, 0);
-    store(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  while (t < te) {
-    const int ks = tri_ks(tc);
-    const int nsteps = (min(C::KC, ks - kk) + 3) >> 2;  // 4-deep MFMA steps holding data
-    // next chunk: the rest of this block, else the next triple
-    uint32_t tn = t;
-    int kn = kk + C::KC;
-    Triple tnx = tc;
-    const bool triple_ends = kn >= ks;
-    if (triple_ends) {
-      tn = t + 1;
-      kn = 0;
-      if (tn < te) tnx = uni(a.tri[tn]);
+  uint32_t t0 = it.tri_begin;
+  if (a.k_lo > 0) t0 = uni(lower_bound_k(a.tri, t0, te, a.k_lo));
+  if (a.k_hi < kNoKLimit) te = uni(lower_bound_k(a.tri, t0, te, a.k_hi));
+  // the chunk after p: the rest of p's block, else the next triple's first chunk
+  auto next = [&](const Pos& p) {
+    Pos n = p;
+    if (p.t >= te) return n;
+    n.kk = p.kk + C::KC;
+    if (n.kk >= tri_ks(p.tri)) {
+      n.t = p.t + 1;
+      n.kk = 0;
+      if (n.t < te) n.tri = uni(a.tri[n.t]);
     }
-    const bool more = tn < te;
-    if (more) load(tnx, kn);
+    return n;
+  };
+  Pos cur = {t0, 0, {0, 0}};
+  if (t0 < te) cur.tri = uni(a.tri[t0]);
+  if (cur.t < te) {
+    load(cur.tri, 0, true, R0, -1);
+    store(R0, 0);
+  }
+  Pos p1 = next(cur);
+  load(p1.tri, p1.kk, p1.t < te, R1, -1);
+  __syncthreads();
 
-    if (NS > 0) {
+  // one chunk: compute from LDS stage `buf`; issue chunk c + 2 into Rn; move chunk c + 1 from Ro
+  // into the other stage
+  auto chunk = [&](Regs& Rn, Regs& Ro, int buf) {
+    const int ks = tri_ks(cur.tri);
+    const int nsteps = (min(C::KC, ks - cur.kk) + 3) >> 2;  // 4-deep MFMA steps holding data
+    const bool triple_ends = cur.kk + C::KC >= ks;
+    const Pos p2 = next(p1);
+
+    {
       const T* as = As + buf * C::ASZ;
       const T* bs = Bs + buf * C::BSZ + g * C::BSTR + i16;
       // one 4-deep MFMA step per iteration: NA A fragments and NB B fragments, then the NA x NB
@@ -269,7 +293,9 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
       // same for the whole wave)
 #pragma unroll
       for (int s = 0; s < C::KC / 4; ++s) {
-        if (s < nsteps) {
+        // part s of chunk c + 2's loads goes out before step s
+        load(p2.tri, p2.kk, p2.t < te, Rn, s);
+        if (NS > 0 && s < nsteps) {
           T av[NA > 0 ? NA : 1], bv[NB > 0 ? NB : 1];
 #pragma unroll
           for (int x = 0; x < NA; ++x) av[x] = as[a_u[x] + C::apos(i16, 4 * s + g)];
@@ -290,7 +316,7 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
       }
       if constexpr (F::kFold) {
         // the block product A_ik B_kj is complete: add it to the FP64 sum across k
-        if (triple_ends) {
+        if (NS > 0 && triple_ends) {
 #pragma unroll
           for (int j = 0; j < NS; ++j) {
 #pragma unroll
@@ -300,12 +326,15 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
         }
       }
     }
-    if (more) store(buf ^ 1);
+    if (p1.t < te) store(Ro, buf ^ 1);
     __syncthreads();
-    buf ^= 1;
-    t = tn;
-    kk = kn;
-    tc = tnx;
+    cur = p1;
+    p1 = p2;
+  };
+  while (cur.t < te) {
+    chunk(R0, R1, 0);
+    if (cur.t >= te) break;
+    chunk(R1, R0, 1);
   }
 
   // epilogue: the raw sum goes to the partial buffer until the last k-window, which writes
