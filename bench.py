@@ -70,7 +70,7 @@ def recorded_traffic():
     rocprofv3 counter summary, if it was taken on the current kernel sources (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "tiles_f64_nonuniform_16384_traffic.md")
-    srcs = ["tile_impl.hpp", "kernels_tile_f64.hip", "types.hpp", "kernels.hpp"]
+    srcs = ["tile_impl.hpp", "kernels_tile_f64.hip", "types.hpp", "kernels.hpp", "wave_rects.inc"]
     h = hashlib.sha256()
     for name in srcs:
         with open(os.path.join(ROOT, "paper_1504_05046_amd", "csrc", name), "rb") as f:
@@ -182,8 +182,9 @@ def main():
     flops = info.useful_flops
 
     # flop-count schedule (graph-replayed launch)
-    flop_wall, flop_ev, _ = time_plan(plan, A, B, C, max(3, args.steps // 3), args.warmup, stream, torch)
+    flop_wall, flop_ev, flop_sd = time_plan(plan, A, B, C, args.steps, args.warmup, stream, torch)
     sched = {"flop_count_tflops": round(flops / (flop_wall * 1e-3) / 1e12, 3)}
+    best = ("flop count", flop_wall, flop_ev, flop_sd)
     if not args.no_learned:
         # learned schedule: record per-task timings, train the cost model on the device, re-bin
         t0 = time.perf_counter()
@@ -203,9 +204,12 @@ def main():
         sched["train_s"] = round(time.perf_counter() - t0, 2)
         sched["train_loss"] = round(loss, 4)
         sched["samples"] = int(T.size)
-    wall_ms, kern_avg, kern_sd = time_plan(plan, A, B, C, args.steps, args.warmup, stream, torch)
-    if not args.no_learned:
-        sched["learned_tflops"] = round(flops / (wall_ms * 1e-3) / 1e12, 3)
+        l_wall, l_ev, l_sd = time_plan(plan, A, B, C, args.steps, args.warmup, stream, torch)
+        sched["learned_tflops"] = round(flops / (l_wall * 1e-3) / 1e12, 3)
+        if l_wall < flop_wall:
+            best = ("learned cost model", l_wall, l_ev, l_sd)
+    # the library offers both schedules; the step is timed with the faster one (both reported)
+    sched_name, wall_ms, kern_avg, kern_sd = best
     value = flops / (wall_ms * 1e-3) / 1e12
     achieved = flops / (kern_avg * 1e-3) / 1e12
     traffic = recorded_traffic()
@@ -227,7 +231,7 @@ def main():
                    "precision": "fp64", "useful_gflop": round(flops / 1e9, 3),
                    "c_blocks": info.c_blocks, "triples": info.triples, "tasks": info.tasks,
                    "tile": info.tile, "launch": "hipGraph replay",
-                   "schedule": "learned cost model" if not args.no_learned else "flop count",
+                   "schedule": sched_name,
                    "plan_ms": round(plan_ms, 1)},
         "schedules": sched,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,

@@ -293,14 +293,17 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
       // same for the whole wave)
 #pragma unroll
       for (int s = 0; s < C::KC / 4; ++s) {
-        // part s of chunk c + 2's loads goes out before step s
-        load(p2.tri, p2.kk, p2.t < te, Rn, s);
+        // step s reads its fragments, part s of chunk c + 2's loads goes out while they arrive,
+        // then the MFMAs
+        T av[NA > 0 ? NA : 1], bv[NB > 0 ? NB : 1];
         if (NS > 0 && s < nsteps) {
-          T av[NA > 0 ? NA : 1], bv[NB > 0 ? NB : 1];
 #pragma unroll
           for (int x = 0; x < NA; ++x) av[x] = as[a_u[x] + C::apos(i16, 4 * s + g)];
 #pragma unroll
           for (int y = 0; y < NB; ++y) bv[y] = bs[b_u[y] + 4 * s * C::BSTR];
+        }
+        load(p2.tri, p2.kk, p2.t < te, Rn, s);
+        if (NS > 0 && s < nsteps) {
 #pragma unroll
           for (int x = 0; x < NA; ++x) {
 #pragma unroll
@@ -312,7 +315,6 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
             }
           }
         }
-        __builtin_amdgcn_sched_barrier(0);
       }
       if constexpr (F::kFold) {
         // the block product A_ik B_kj is complete: add it to the FP64 sum across k
