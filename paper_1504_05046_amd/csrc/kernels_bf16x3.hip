@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "uniform.hpp"
 
 namespace bsm {
 
@@ -26,15 +27,6 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int kRsrcWord3b = 0x00020000;
-
-__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-template <typename P>
-__device__ inline P* uni_ptr(P* p) {
-  uint64_t v = reinterpret_cast<uint64_t>(p);
-  uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
-  uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
-  return reinterpret_cast<P*>((uint64_t(hi) << 32) | lo);
-}
 
 __device__ inline uint32_t lower_bound_k3(const Triple* __restrict__ tri, uint32_t tb, uint32_t te,
                                           int k) {
@@ -96,23 +88,29 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
 
   const uint16_t* Ag = static_cast<const uint16_t*>(pa.A);
   const uint16_t* Bg = static_cast<const uint16_t*>(pa.B);
-  u4 ra[C::ALD], rb[C::BLD];
+  // Two sets of staging registers: while chunk c is computed from LDS, the loads of chunk c + 2
+  // are in flight into one set and chunk c + 1 waits in the other for its turn in LDS.
+  struct Regs {
+    u4 a[C::ALD], b[C::BLD];
+  };
+  Regs R0, R1;
   // granule q of a stage: slice q / (rows*4), row (q % (rows*4)) / 4, k-octet q % 4.  The chunk
   // is one 32-wide k-panel of the slice planes, whose rows are contiguous: the sub-tile's rows
   // r0..r0+h of A_ik (a panel of ldm rows) and columns c0..c0+w of B_kj (a panel of ldc columns)
-  // are one run of 64-byte rows each.
-  auto load = [&](const Triple& t, int kk) {
+  // are one run of 64-byte rows each.  A chunk past the end of the k-list is loaded through empty
+  // descriptors (zeros, no memory access), so that every chunk issues the same loads.
+  auto load = [&](const Triple& t, int kk, bool valid, Regs& R) {
     const uint16_t* ab = Ag + tri_a_off(t) + int64_t(kk) * it.ldm + int64_t(it.r0) * kSliceK;
     const uint16_t* bb = Bg + tri_b_off(t) + int64_t(kk) * it.ldc + int64_t(it.c0) * kSliceK;
     // rows past h (columns past w) fall outside the descriptor and read 0
-    const int na = uni(h * kSliceK * 2), nb = uni(w * kSliceK * 2);
+    const int na = uni(valid ? h * kSliceK * 2 : 0), nb = uni(valid ? w * kSliceK * 2 : 0);
 #pragma unroll
     for (int p = 0; p < C::ALD; ++p) {
       const int q = tid + C::NT * p;
       const int s = q / (TM * 4), rem = q - s * (TM * 4);
       const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
           uni_ptr(const_cast<uint16_t*>(ab + s * pa.a_plane)), (short)0, na, kRsrcWord3b);
-      ra[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * kSliceK + 8 * (rem & 3)) * 2), 0, 0);
+      R.a[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * kSliceK + 8 * (rem & 3)) * 2), 0, 0);
     }
 #pragma unroll
     for (int p = 0; p < C::BLD; ++p) {
@@ -120,55 +118,65 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
       const int s = q / (TN * 4), rem = q - s * (TN * 4);
       const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
           uni_ptr(const_cast<uint16_t*>(bb + s * pa.b_plane)), (short)0, nb, kRsrcWord3b);
-      rb[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * kSliceK + 8 * (rem & 3)) * 2), 0, 0);
+      R.b[p] = __builtin_amdgcn_raw_buffer_load_b128(r, uint32_t(((rem >> 2) * kSliceK + 8 * (rem & 3)) * 2), 0, 0);
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](const Regs& R, int buf) {
 #pragma unroll
     for (int p = 0; p < C::ALD; ++p) {
       const int q = tid + C::NT * p;
       const int s = q / (TM * 4), rem = q - s * (TM * 4);
-      *reinterpret_cast<u4*>(As + buf * C::ASZ + s * TM * C::RS + (rem >> 2) * C::RS + 8 * (rem & 3)) = ra[p];
+      *reinterpret_cast<u4*>(As + buf * C::ASZ + s * TM * C::RS + (rem >> 2) * C::RS + 8 * (rem & 3)) = R.a[p];
     }
 #pragma unroll
     for (int p = 0; p < C::BLD; ++p) {
       const int q = tid + C::NT * p;
       const int s = q / (TN * 4), rem = q - s * (TN * 4);
-      *reinterpret_cast<u4*>(Bs + buf * C::BSZ + s * TN * C::RS + (rem >> 2) * C::RS + 8 * (rem & 3)) = rb[p];
+      *reinterpret_cast<u4*>(Bs + buf * C::BSZ + s * TN * C::RS + (rem >> 2) * C::RS + 8 * (rem & 3)) = R.b[p];
     }
   };
 
+  // A chunk's place in the k-list: triple index t (valid while t < te), its triple, and the
+  // offset kk of the chunk within the block's padded inner dimension.
+  struct Pos {
+    uint32_t t;
+    int kk;
+    Triple tri;
+  };
   uint32_t te = it.tri_begin + it.tri_count;
-  uint32_t t = it.tri_begin;
-  if (a.k_lo > 0) t = uint32_t(uni(int(lower_bound_k3(a.tri, t, te, a.k_lo))));
-  if (a.k_hi < kNoKLimit) te = uint32_t(uni(int(lower_bound_k3(a.tri, t, te, a.k_hi))));
-  int kk = 0;
-  Triple tc;
-  if (t < te) {
-    tc = a.tri[t];
-    load(tc, 0);
-    store(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  while (t < te) {
-    const int ks32 = int(pad_k(tri_ks(tc)));
-    uint32_t tn = t;
-    int kn = kk + C::KC;
-    Triple tnx = tc;
-    const bool triple_ends = kn >= ks32;
-    if (triple_ends) {
-      tn = t + 1;
-      kn = 0;
-      if (tn < te) tnx = a.tri[tn];
+  uint32_t t0 = it.tri_begin;
+  if (a.k_lo > 0) t0 = uni(lower_bound_k3(a.tri, t0, te, a.k_lo));
+  if (a.k_hi < kNoKLimit) te = uni(lower_bound_k3(a.tri, t0, te, a.k_hi));
+  auto next = [&](const Pos& p) {
+    Pos n = p;
+    if (p.t >= te) return n;
+    n.kk = p.kk + C::KC;
+    if (n.kk >= int(pad_k(tri_ks(p.tri)))) {
+      n.t = p.t + 1;
+      n.kk = 0;
+      if (n.t < te) n.tri = uni(a.tri[n.t]);
     }
-    const bool more = tn < te;
-    if (more) load(tnx, kn);
+    return n;
+  };
+  Pos cur = {t0, 0, {0, 0}};
+  if (t0 < te) cur.tri = uni(a.tri[t0]);
+  if (cur.t < te) {
+    load(cur.tri, 0, true, R0);
+    store(R0, 0);
+  }
+  Pos p1 = next(cur);
+  load(p1.tri, p1.kk, p1.t < te, R1);
+  __syncthreads();
 
+  // one chunk: read the fragments of stage `buf`, issue chunk c + 2 into Rn while they arrive,
+  // run the MFMAs, then move chunk c + 1 from Ro into the other stage
+  auto chunk = [&](Regs& Rn, Regs& Ro, int buf) {
+    const bool triple_ends = cur.kk + C::KC >= int(pad_k(tri_ks(cur.tri)));
+    const Pos p2 = next(p1);
+    bf8 af[3][NRA], bfr[3][NCA];
     if constexpr (NR > 0 && NC > 0) {
       const uint16_t* as = As + buf * C::ASZ + (16 * rb0 + i16) * C::RS + 8 * g;
       const uint16_t* bs = Bs + buf * C::BSZ + (16 * cb0 + i16) * C::RS + 8 * g;
-      bf8 af[3][NRA], bfr[3][NCA];
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
 #pragma unroll
@@ -178,6 +186,9 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
         for (int y = 0; y < NC; ++y)
           bfr[s][y] = *reinterpret_cast<const bf8*>(bs + s * TN * C::RS + 16 * y * C::RS);
       }
+    }
+    load(p2.tri, p2.kk, p2.t < te, Rn);
+    if constexpr (NR > 0 && NC > 0) {
       // the six slice products, smallest first; consecutive MFMAs hit different accumulators
       constexpr int PA[6] = {2, 1, 0, 1, 0, 0};
       constexpr int PB[6] = {0, 1, 2, 0, 1, 0};
@@ -199,12 +210,15 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
           }
       }
     }
-    if (more) store(buf ^ 1);
+    if (p1.t < te) store(Ro, buf ^ 1);
     __syncthreads();
-    buf ^= 1;
-    t = tn;
-    kk = kn;
-    tc = tnx;
+    cur = p1;
+    p1 = p2;
+  };
+  while (cur.t < te) {
+    chunk(R0, R1, 0);
+    if (cur.t >= te) break;
+    chunk(R1, R0, 1);
   }
 
   // epilogue (v_mfma_f32_16x16x32_bf16: register r of lane 16g + i holds row 4g + r, column i)
@@ -254,8 +268,8 @@ __global__ __launch_bounds__(64 * NW, OCC) void tiles_bf16x3(TileArgs a) {
   const int idx = a.map.begin[x] + qx;
   if (idx >= a.map.begin[x + 1]) return;
   if (a.stamps && threadIdx.x == 0) a.stamps[2 * idx] = wall_clock64();
-  const Item it = a.items[idx];
-  const ProductArgs pa = a.prods ? a.prods[it.product] : a.single;
+  const Item it = uni(a.items[idx]);
+  const ProductArgs pa = uni(a.prods ? a.prods[it.product] : a.single);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wr = wave / C::WC, wc = wave % C::WC;
   const int nr = min(max(((it.h + 15) >> 4) - 2 * wr, 0), 2);
