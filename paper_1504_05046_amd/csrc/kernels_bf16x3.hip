@@ -154,7 +154,7 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
     if (n.kk >= int(pad_k(tri_ks(p.tri)))) {
       n.t = p.t + 1;
       n.kk = 0;
-      if (n.t < te) n.tri = uni(a.tri[n.t]);
+      if (n.t < te) n.tri = scalar_triple(a.tri, n.t);
     }
     return n;
   };

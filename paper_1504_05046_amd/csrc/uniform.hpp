@@ -53,4 +53,15 @@ __device__ inline ProductArgs uni(const ProductArgs& p) {
   return r;
 }
 
+// Triple q of a k-list through the scalar cache (the address is uniform): its wait counts
+// against the scalar and LDS operations only, not behind the staging loads in flight.
+__device__ inline Triple scalar_triple(const Triple* tri, uint32_t q) {
+  using TriK = const __attribute__((address_space(4))) Triple;
+  TriK* t = (TriK*)tri;
+  Triple r;
+  r.a = t[q].a;
+  r.b = t[q].b;
+  return r;
+}
+
 }  // namespace bsm
