@@ -70,7 +70,8 @@ def recorded_traffic():
     rocprofv3 counter summary, if it was taken on the current kernel sources (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "tiles_f64_nonuniform_16384_traffic.md")
-    srcs = ["tile_impl.hpp", "kernels_tile_f64.hip", "types.hpp", "kernels.hpp", "wave_rects.inc"]
+    srcs = ["tile_impl.hpp", "kernels_tile_f64.hip", "types.hpp", "kernels.hpp", "wave_rects.inc",
+            "uniform.hpp"]
     h = hashlib.sha256()
     for name in srcs:
         with open(os.path.join(ROOT, "paper_1504_05046_amd", "csrc", name), "rb") as f:
