@@ -42,6 +42,8 @@ __device__ inline void split3(double a, uint16_t& s0, uint16_t& s1, uint16_t& s2
   s2 = bf16_bits(a2);
 }
 
+static_assert(kSliceK == 32, "panel indexing below assumes 32-wide k-panels");
+
 // One workgroup per operand block: writes the block's three slices into the planes (plane p at
 // dst + p * plane), inner size padded with zeros to a multiple of 32, in 32-wide k-panels (element
 // (r, k) of a block of R rows at (k / 32) * 32 R + 32 r + k % 32); B blocks are transposed through
@@ -57,17 +59,19 @@ __global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict
   uint16_t* d1 = d0 + plane;
   uint16_t* d2 = d1 + plane;
   if (!b.transpose) {
-    const int64_t n = int64_t(b.rows) * ks32;
-    const int64_t panel = int64_t(b.rows) * kSliceK;
-    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-      const int64_t kc = e / panel, rem = e - kc * panel;
-      const int r = int(rem / kSliceK), k = int(kc * kSliceK + (rem - int64_t(r) * kSliceK));
-      const double v = k < b.ks ? sb[int64_t(r) * b.ld_src + k] : 0.0;
-      uint16_t x0, x1, x2;
-      split3(v, x0, x1, x2);
-      d0[e] = x0;
-      d1[e] = x1;
-      d2[e] = x2;
+    // panel by panel; inside a panel element e is row e / 32, k e % 32 of the panel
+    const int panel = b.rows * kSliceK;
+    for (int k0 = 0; k0 < ks32; k0 += kSliceK) {
+      const int64_t pbase = int64_t(k0) * b.rows;
+      for (int e = threadIdx.x; e < panel; e += blockDim.x) {
+        const int r = e >> 5, k = k0 + (e & (kSliceK - 1));
+        const double v = k < b.ks ? sb[int64_t(r) * b.ld_src + k] : 0.0;
+        uint16_t x0, x1, x2;
+        split3(v, x0, x1, x2);
+        d0[pbase + e] = x0;
+        d1[pbase + e] = x1;
+        d2[pbase + e] = x2;
+      }
     }
     return;
   }

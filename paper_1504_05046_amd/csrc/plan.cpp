@@ -149,8 +149,35 @@ std::vector<double> flop_costs(const HostPlan& p) {
   return c;
 }
 
-void schedule(HostPlan& p, const std::vector<double>& cost) {
+void schedule(HostPlan& p, const std::vector<double>& cost_in) {
   size_t n = p.items.size();
+  // Every order below is defined on the tasks in C-block order (product, C offset, sub-tile), so
+  // the tasks are put back in that order first: a reschedule then gives the same result whatever
+  // order an earlier schedule left them in.
+  std::vector<double> cost(cost_in);
+  {
+    std::vector<size_t> perm(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](size_t a, size_t b) {
+      const Item& x = p.items[a];
+      const Item& y = p.items[b];
+      if (x.product != y.product) return x.product < y.product;
+      if (x.c_off != y.c_off) return x.c_off < y.c_off;
+      if (x.r0 != y.r0) return x.r0 < y.r0;
+      return x.c0 < y.c0;
+    });
+    std::vector<Item> it2(n);
+    std::vector<double> c2(n);
+    std::vector<float> f2(p.features.size());
+    for (size_t q = 0; q < n; ++q) {
+      it2[q] = p.items[perm[q]];
+      c2[q] = cost_in[perm[q]];
+      for (int f = 0; f < 5; ++f) f2[q * 5 + size_t(f)] = p.features[perm[q] * 5 + size_t(f)];
+    }
+    p.items.swap(it2);
+    p.features.swap(f2);
+    cost.swap(c2);
+  }
   std::vector<size_t> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   std::vector<std::vector<size_t>> bins(kXcds);
