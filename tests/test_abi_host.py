@@ -206,3 +206,20 @@ def test_costmodel_host_side():
     assert np.array_equal(p2, p * 2) and n2[9] == 2 and n2[11] == 3
     _expect(bsm.E_MISMATCH, lambda: m.set_params(p[:-1]))
     _expect(bsm.E_INVALID, lambda: m.set_params(None, np.array([0] * 5 + [0] + [1] * 4 + [0, 1], np.float32)))
+
+
+def test_reschedule_does_not_depend_on_the_previous_order():
+    """Scheduling deals whole C blocks, in C-block order, to the XCDs: costs that differ reorder
+    the tasks, and scheduling again by flop count restores the plan's original order."""
+    p = gen.random_problem(11, 6, 6, 6, 16, 200, 0.6, 0.6)
+    plan = bsm.Plan.from_problem(p)
+    f0 = plan.features().copy()
+    rng = np.random.default_rng(0)
+    plan.set_costs(rng.uniform(1, 10, len(f0)).astype(np.float32))
+    f1 = plan.features().copy()
+    assert not np.array_equal(f0, f1)
+    # the same multiset of tasks either way
+    assert np.array_equal(np.sort(f0.view(np.int32), axis=0), np.sort(f1.view(np.int32), axis=0))
+    flops = (2 * np.exp(f1[:, :3].astype(np.float64).sum(1))).astype(np.float32)
+    plan.set_costs(flops)
+    assert np.array_equal(plan.features(), f0)
