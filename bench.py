@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "useful TFLOP/s, block-sparse MM: FP64 vs split-BF16 at ≤1e-6 rel err, 1 GPU"
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 MFMA (datasheet)
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA (datasheet)
+FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 MFMA (datasheet)
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -159,6 +160,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split-bf16", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="flop-count schedule only")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-form measurement")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--tile", type=int, default=0, help="0 = library choice, else variant id + 1")
     args = ap.parse_args()
@@ -253,6 +255,18 @@ def main():
             "mfma_frac": round(6 * flops / (e3 * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
             "note": "useful flops only; the six slice products per block product are 6x the MFMA work",
         }
+    C32 = None
+    if not args.no_fp32:
+        # the FP32 form on the same inputs: conversion pass + FP32 MFMA tile kernel per step
+        plan32 = bsm.Plan.from_problem(p, precision=bsm.FP32, use_graph=1)
+        C32 = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
+        w32, e32, _ = time_plan(plan32, A, B, C32, args.steps, args.warmup, stream, torch)
+        result["fp32"] = {
+            "value": round(flops / (w32 * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+            "ms_per_step": round(w32, 4), "launch_ms": round(e32, 4),
+            "vs_fp64": round(wall_ms / w32, 3),
+            "mfma_frac": round(flops / (e32 * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+        }
     if not args.no_cpu_baseline:
         got = C.cpu().numpy()[:info.c_elems]
         c_off = plan.c_offsets()
@@ -262,6 +276,9 @@ def main():
         if C3 is not None:
             got3 = C3.cpu().numpy()[:info.c_elems]
             result["split_bf16"]["sample_rel_err"] = sampled_error(p, got3, c_off)
+        if C32 is not None:
+            got32 = C32.cpu().numpy()[:info.c_elems]
+            result["fp32"]["sample_rel_err"] = sampled_error(p, got32, c_off)
     print(json.dumps(result), flush=True)
 
 
