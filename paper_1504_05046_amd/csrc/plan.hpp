@@ -22,8 +22,8 @@ constexpr int kNumBf16Variants = int(sizeof(kBf16Variants) / sizeof(kBf16Variant
 #undef BSM_VARIANT_ROW
 
 // Task order: LOCALITY keeps C-block order and cuts it into one contiguous run per XCD; LPT sorts
-// by cost and bins greedily; INTERLEAVE keeps C-block order but deals whole C blocks round-robin
-// over the XCDs, so that all XCDs work on the same region of C at the same time.
+// by cost and bins greedily; INTERLEAVE deals whole C blocks, in C-block order, each to the
+// least-loaded XCD, so that all XCDs work on the same region of C at the same time.
 enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1, ORDER_INTERLEAVE = 2 };
 
 struct PlanConfig {

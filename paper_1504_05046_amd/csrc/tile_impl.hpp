@@ -3,10 +3,11 @@
 // One workgroup (NW waves) executes one task: a C sub-tile of h x w (h <= TM, w <= TN) and the
 // k-list of its C block (the triples whose k lies in the current k-window).  For every triple, in
 // ascending k, the workgroup streams KC-wide k-chunks of A_ik (rows r0..r0+h) and B_kj (cols
-// c0..c0+w) from HBM into LDS (double-buffered, one barrier per chunk).  Each wave owns a
-// rectangle of na x nb of the sub-tile's 16x16 output blocks (a generated table, balanced across
-// the waves), so that one 4-deep MFMA step reads na + nb fragments from LDS for na * nb MFMAs.  FP64 form: v_mfma_f64_16x16x4 into FP64
-// registers across the whole k-list.  FP32 form: v_mfma_f32_16x16x4 into FP32 registers within
+// c0..c0+w) from HBM into LDS (double-buffered, one barrier per chunk; the loads run two chunks
+// ahead through two sets of staging registers).  Each wave owns a rectangle of na x nb of the
+// sub-tile's 16x16 output blocks (a generated table, balanced across the waves), so that one
+// 4-deep MFMA step reads na + nb fragments from LDS for na * nb MFMAs.  FP64 form:
+// v_mfma_f64_16x16x4 into FP64 registers across the whole k-list.  FP32 form: v_mfma_f32_16x16x4 into FP32 registers within
 // one block product A_ik B_kj, folded into FP64 registers when the triple ends.  The epilogue
 // writes alpha*acc (+C) once per element: the paper's multiply task and reduction task fused,
 // with no temporaries (Sec. 3.2, Fig. 3).
