@@ -277,6 +277,29 @@ def test_mlp_forward_exact_network():
     assert np.array_equal(y, X[:, 2] + 0.25)
 
 
+def test_mlp_forward_exact_network_negative_layer2():
+    """A network whose second layer has pre-activations of both signs and one that is always
+    negative: z2 = (x_2, -x_2, -|x_2| - 1), so y = relu(x_2) + relu(-x_2) + 7 * 0 + 0.25 =
+    |x_2| + 0.25 exactly.  Dropping either ReLU, or applying the first layer's activation where
+    the second one belongs, changes y."""
+    Fi, A1, A2 = 5, 4, 3
+    W1 = np.zeros((A1, Fi)); W1[0, 2] = 1.0; W1[1, 2] = -1.0
+    b1 = np.zeros(A1)
+    W2 = np.zeros((A2, A1))
+    W2[0, :2] = [1.0, -1.0]
+    W2[1, :2] = [-1.0, 1.0]
+    W2[2, :2] = [-1.0, -1.0]
+    b2 = np.array([0.0, 0.0, -1.0])
+    w3 = np.array([1.0, 1.0, 7.0])
+    b3 = np.array([0.25])
+    p = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3, b3])
+    assert p.size == oracle.mlp_param_count(Fi, A1, A2)
+    X = np.random.default_rng(1).standard_normal((64, Fi))
+    X[0, 2] = 0.0
+    y = oracle.mlp_forward(Fi, A1, A2, p, X)
+    assert np.array_equal(y, np.abs(X[:, 2]) + 0.25)
+
+
 def test_mlp_gradient_vs_central_differences():
     rng = np.random.default_rng(7)
     params = _rand_params(7)
@@ -305,6 +328,53 @@ def test_adam_closed_form_constant_gradient():
         before = p.copy()
         oracle.adam_step(p, g.copy(), m, v, step, lr=lr, eps=eps)
         assert np.allclose(before - p, lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-18)
+
+
+def _adam_exact(p0, grads, lr, b1, b2, eps):
+    """Adam (Kingma & Ba 2015) from its update rule, with the moments and their bias corrections
+    in exact rational arithmetic and only the square root and the final division in 60-digit
+    decimal arithmetic."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    b1, b2 = Fraction(b1), Fraction(b2)
+    m = Fraction(0)
+    v = Fraction(0)
+    p = Decimal(p0)
+    out = []
+    for n, g in enumerate(grads, start=1):
+        g = Fraction(g)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        mhat = m / (1 - b1 ** n)
+        vhat = v / (1 - b2 ** n)
+        num = Decimal(mhat.numerator) / Decimal(mhat.denominator)
+        den = (Decimal(vhat.numerator) / Decimal(vhat.denominator)).sqrt() + Decimal(eps)
+        p = p - Decimal(lr) * num / den
+        out.append((float(p), float(m), float(v)))
+    return out
+
+
+def test_adam_varying_gradients_vs_exact_rationals():
+    """Three Adam steps with a different gradient at every step and the usual beta1 = 0.9,
+    beta2 = 0.999: parameters and both moments after each step agree with the update rule evaluated
+    exactly.  Gradients that change sign and size make the first and second moments and their
+    bias corrections distinguishable, so exchanging beta1 and beta2 anywhere fails."""
+    lr, b1, b2, eps = 0.05, 0.9, 0.999, 1e-8
+    steps = [np.array([1.0, -2.0, 0.5, 3.0]),
+             np.array([-0.25, 4.0, 0.5, -1.0]),
+             np.array([2.0, -0.5, -3.0, 0.125])]
+    p0 = np.array([0.5, -1.0, 2.0, 0.0])
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    want = [_adam_exact(p0[q], [s[q] for s in steps], lr, b1, b2, eps) for q in range(4)]
+    for n, g in enumerate(steps, start=1):
+        oracle.adam_step(p, g.copy(), m, v, n, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        for q in range(4):
+            wp, wm, wv = want[q][n - 1]
+            assert abs(p[q] - wp) <= 1e-13 * max(1.0, abs(wp)), (n, q, p[q], wp)
+            assert abs(m[q] - wm) <= 1e-14 * max(1e-300, abs(wm)) + 1e-300, (n, q)
+            assert abs(v[q] - wv) <= 1e-14 * max(1e-300, abs(wv)) + 1e-300, (n, q)
+    # after three steps the moments are not the constant-gradient ones
+    assert not np.allclose(v, m * m)
 
 
 def test_adam_decreases_loss():
