@@ -25,10 +25,16 @@
  *           owned by the caller and must stay valid until the work queued on the stream is done.
  *           dA and dB may be the same buffer (C = A A); dC must not overlap either.
  * Streams   `stream` is a hipStream_t (NULL = the default stream); work is queued on it and the
- *           call returns without waiting.  A plan runs on one stream at a time.
+ *           call returns without waiting.  A plan runs on one stream at a time.  A call that must
+ *           replace a device table a queued launch may still read (new task order after
+ *           bsm_plan_set_costs, new operand pointers of a batch) first waits for the work queued
+ *           on `stream`.
  * Errors    every call returns a bsm_status; nothing is thrown across the ABI.  The text of the
  *           last failure on the calling thread is available from bsm_last_error().  Device faults
- *           appear as BSM_E_HIP at the next call that synchronises.
+ *           appear as BSM_E_HIP at the next call that synchronises.  Every launch counts, per
+ *           task, how often the task ran; the calls that synchronise and read results back
+ *           (bsm_plan_verify, bsm_batch_verify, bsm_plan_timings, bsm_batch_timings) return
+ *           BSM_E_STATE if any task ran a number of times other than the launches queued.
  */
 #ifndef BSM_H
 #define BSM_H
@@ -49,7 +55,7 @@ typedef enum {
   BSM_E_STATE = -6        /* call out of order, e.g. timings requested but never recorded */
 } bsm_status;
 
-/* Arithmetic of the block products.  The result is FP64 in every form. */
+/* Arithmetic of the block products.  Sums across k-blocks are FP64 in every form. */
 typedef enum {
   BSM_FP64 = 0,  /* FP64 MFMA, FP64 accumulation */
   BSM_FP32 = 1,  /* operands rounded to FP32, FP32 MFMA within a block product, FP64 across k */
@@ -58,11 +64,25 @@ typedef enum {
                     across k */
 } bsm_precision;
 
+/* Element type of C (the k-window partial sums stay FP64 either way). */
+typedef enum {
+  BSM_OUT_F64 = 0, /* C holds FP64 elements */
+  BSM_OUT_F32 = 1  /* C holds FP32 elements: alpha * sum (+ C) is formed in FP64, rounded once */
+} bsm_out;
+
 /* How tasks are ordered (never changes the numbers). */
 typedef enum {
   BSM_SCHED_FLOPS = 0, /* cost = flop count */
   BSM_SCHED_MLP = 1    /* cost = the learned model's prediction (set with bsm_plan_set_costmodel) */
 } bsm_sched;
+
+/* How the scheduler deals tasks to the 8 accelerator dies (XCDs, each with its own L2). */
+typedef enum {
+  BSM_ORDER_DEFAULT = 0,    /* = BSM_ORDER_INTERLEAVE */
+  BSM_ORDER_INTERLEAVE = 1, /* whole C blocks, in C-block order, each to the least-loaded XCD */
+  BSM_ORDER_LOCALITY = 2,   /* C-block order cut into 8 runs of equal cost */
+  BSM_ORDER_LPT = 3         /* largest cost first, each task to the least-loaded XCD */
+} bsm_order;
 
 typedef struct {
   int32_t precision;      /* bsm_precision */
@@ -72,6 +92,10 @@ typedef struct {
   int32_t tile;           /* 0 = chosen by the library; otherwise a tile variant id (bsm_tile_*) */
   int32_t use_graph;      /* 1 = bsm_execute captures its launches into a hipGraph and replays it
                              while the operands, alpha and accumulate stay the same */
+  int32_t out;            /* bsm_out: element type of C */
+  int32_t order;          /* bsm_order */
+  const char* tune_cache; /* NULL, or a file where bsm_autotune looks up and records its choices
+                             (lines "signature variant"); the string is copied */
 } bsm_options;
 
 typedef struct {
@@ -84,46 +108,67 @@ typedef struct {
   int64_t workspace_bytes; /* device memory the plan holds besides the caller's buffers */
   int64_t k_windows;       /* launches per execute: ceil(K / k_window) */
   int32_t tile;            /* tile variant in use (variant id + 1) */
+  int32_t out;             /* bsm_out: element type of C */
 } bsm_plan_info;
 
 typedef struct bsm_batch bsm_batch;
 
 typedef struct bsm_plan bsm_plan;
 
-/* Fill opt with the defaults: FP64, flop-count scheduling, all k-iterations in flight,
- * no timings, library-chosen tiles. */
+/* Fill opt with the defaults: FP64 products and FP64 C, flop-count scheduling, interleaved task
+ * order, all k-iterations in flight, no timings, library-chosen tiles, no graph, no tune cache. */
 void bsm_options_default(bsm_options* opt);
 
-/* Build a plan for C = alpha A B (+ C).  Host-only work: validates the tilings and shapes,
- * forms the C-shape (the boolean product of the two shapes), the packed offsets, the task list
- * (each present C block, cut into sub-tiles; its k-list = the k with A_ik and B_kj present, in
- * ascending order) and the task order.  Device memory is allocated at the first execute.
- * opt may be NULL (defaults).  Errors: BSM_E_INVALID for a null pointer, a negative count, a
- * block size outside [1, 65535] or a padding bit set; BSM_E_NOMEM if the host runs out. */
+/* Build a plan for C = alpha A B (+ C) over problem-given, arbitrarily sized blocks (Sec. 3.2's
+ * over-decomposition; Fig. 3 splits one iteration into tasks, each producing one piece of the
+ * process's part of C).  Host-only work: validates the tilings and shapes, forms the C-shape (the
+ * boolean product of the two shapes), the packed offsets, the task list (each present C block,
+ * cut into sub-tiles; its k-list = the k with A_ik and B_kj present, in ascending order) and the
+ * task order.  Device memory is allocated at the first execute.  All arguments are host memory
+ * and are copied; opt may be NULL (defaults).  Errors: BSM_E_INVALID for a null pointer, a
+ * negative count, a block size outside [1, 65535], a padding bit set or an unknown option;
+ * BSM_E_NOMEM if the host runs out or a buffer exceeds 2^48 elements. */
 bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, int64_t K,
                            const int64_t* inner_sizes, int64_t N, const int64_t* col_sizes,
                            const uint64_t* a_bits, const uint64_t* b_bits,
                            const bsm_options* opt);
 
-/* Sizes and counts of a plan (host memory, no device work). */
+/* Sizes and counts of a plan (host memory, no device work).  useful_flops is the work of the
+ * rank-k updates C_ij <- A_ik B_kj + C_ij that the shapes call for (Sec. 2.1). */
 bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info);
 
-/* The C-shape Chat as a bitmap (M * ceil(N/64) words, host memory). */
+/* The C-shape Chat = OR_k (Ahat_ik AND Bhat_kj) as a bitmap (M * ceil(N/64) words, host memory,
+ * caller-owned): the block sparsity the product of two block-sparse operands has (Sec. 1). */
 bsm_status bsm_plan_c_shape(const bsm_plan* plan, uint64_t* c_bits);
 
-/* Packed element offset of every C block, -1 for an absent block (M * N int64, host memory). */
+/* Packed element offset of every C block, -1 for an absent block (M * N int64, host memory,
+ * caller-owned). */
 bsm_status bsm_plan_c_offsets(const bsm_plan* plan, int64_t* c_offsets);
 
-/* C = alpha A B (+ C if accumulate), queued on `stream`.  dA, dB, dC: device pointers to the
- * packed FP64 tiles (a_elems, b_elems, c_elems elements).  With accumulate = 0 every element of
- * C is written (present blocks only); with accumulate = 1 C must hold the previous values.
- * Errors: BSM_E_INVALID for null pointers or overlapping C; BSM_E_UNSUPPORTED without a gfx950
- * device; BSM_E_HIP if a launch fails. */
+/* C = alpha A B (+ C if accumulate), queued on `stream`: Alg. 1's local update
+ * C <- alpha A(*,k) B(k,*) + C for every k-iteration, i.e. all the rank-k updates of Sec. 2.1,
+ * with each C block reduced over its k-list in ascending k.  dA, dB: device pointers to the
+ * packed FP64 tiles (a_elems, b_elems elements); dC: device pointer to the packed C tiles
+ * (c_elems elements of the plan's output type).  With accumulate = 0 every element of C is
+ * written (present blocks only); with accumulate = 1 C must hold the previous values.  dA may
+ * equal dB.  Errors: BSM_E_INVALID for null pointers or overlapping C; BSM_E_UNSUPPORTED without
+ * a gfx950 device; BSM_E_HIP if a launch fails. */
 bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
-                       double* dC, int accumulate, void* stream);
+                       void* dC, int accumulate, void* stream);
+
+/* Waits for `stream`, then checks that every task of the plan ran once per k-window of every
+ * execute queued since the task list was last (re)uploaded.  BSM_E_STATE names the first task
+ * that did not; BSM_E_HIP reports a device fault. */
+bsm_status bsm_plan_verify(bsm_plan* plan, void* stream);
+
+/* Fault injection for tests of the checks above: every later launch of the plan leaves task
+ * `task` out (its workgroup returns at once; C keeps its old values there), -1 = none. */
+bsm_status bsm_plan_debug_skip_task(bsm_plan* plan, int64_t task);
 
 /* Per-task timings of the last execute of a plan created with record_timings = 1 (waits for
- * `stream`).  n must equal the plan's task count.  features (n x 5 floats, host; may be NULL)
+ * `stream` and checks the execution counters as bsm_plan_verify does).  The recorded times are
+ * the training data of the learned cost model that orders tasks for dynamic scheduling (Sec. 3.2
+ * leaves ordering to the runtime; Sec. 4.4 shows the block-level imbalance it has to absorb).  n must equal the plan's task count.  features (n x 5 floats, host; may be NULL)
  * receives each task's cost-model features: log h, log w, log (summed inner size of its k-list),
  * log (number of k-list blocks), k-list density (summed inner size / total inner size);
  * seconds (n floats, host; may be NULL) the task's duration on the device clock.
@@ -138,25 +183,31 @@ bsm_status bsm_plan_features(const bsm_plan* plan, float* features, int64_t n);
 
 /* Re-order and re-bin the tasks by the given per-task costs (n floats, host, >= 0, in the current
  * task order; e.g. a cost model's predictions).  Only the schedule changes: every task still runs
- * once and C is bitwise the same.  The new order is uploaded at the next execute. */
+ * once and C is bitwise the same.  The new order is uploaded at the next execute, after the work
+ * queued on that execute's stream has finished. */
 bsm_status bsm_plan_set_costs(bsm_plan* plan, const float* costs, int64_t n);
 
-/* Autotuner: time every tile variant of the plan's precision form on the given operands (C is
- * overwritten with A B) and keep the fastest; *chosen (may be NULL) receives its id + 1.  When the
- * environment variable BSM_TUNE_CACHE names a file, choices are looked up there by a workload
- * signature first and appended after tuning.  Synchronises `stream`. */
-bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, double* dC,
+/* Autotuner: time every tile variant of the plan's precision form on the given operands (one
+ * warm-up and 5 timed runs each; C is overwritten with A B) and keep the fastest; *chosen (may be
+ * NULL) receives its id + 1.  When the plan's tune_cache option names a file, choices are looked
+ * up there by a workload signature first and appended after tuning.  Synchronises `stream`.
+ * (The paper's performance rests on the block kernel, Sec. 4.3; this picks its tile shape.) */
+bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, void* dC,
                         void* stream, int32_t* chosen);
 
 /* Release the plan (waits for its device work first).  NULL is accepted. */
 bsm_status bsm_plan_destroy(bsm_plan* plan);
 
 /* ---- batches: many independent products in one launch ---------------------------------------
- * A batch concatenates the tasks of n plans (same precision and tile variant, k_window 0) into one
- * task list and one schedule; bsm_batch_execute captures every member's operand conversion plus one
+ * Several matrix multiplications overlapped in one execution (Sec. 1 names the overlap of the
+ * multiplications of one expression as a motivation of the task formulation).  A batch
+ * concatenates the tasks of n plans (same precision and tile variant, k_window 0) into one task
+ * list and one schedule; bsm_batch_execute captures every member's operand conversion plus one
  * tile-kernel launch over all tasks into a hipGraph and replays it while the operand pointers,
  * alphas and accumulate stay the same.  The plans must outlive the batch and must not run
- * elsewhere while the batch executes. */
+ * elsewhere while the batch executes.  An FP64 plan may appear more than once (each entry is a
+ * product with its own operands); an FP32 or split-bf16 plan only once, since it converts its
+ * operands into buffers it owns (BSM_E_INVALID otherwise). */
 bsm_status bsm_batch_create(bsm_batch** out, bsm_plan* const* plans, int64_t n);
 
 /* Task count, total useful flops and tile variant (id + 1) of a batch (any pointer may be NULL). */
@@ -167,8 +218,11 @@ bsm_status bsm_batch_query(const bsm_batch* batch, int64_t* tasks, double* usefu
  * entries (alphas may be NULL = all 1); the pointers they hold are device buffers as for
  * bsm_execute. */
 bsm_status bsm_batch_execute(bsm_batch* batch, const double* alphas, const double* const* dA,
-                             const double* const* dB, double* const* dC, int accumulate,
+                             const double* const* dB, void* const* dC, int accumulate,
                              void* stream);
+
+/* As bsm_plan_verify, over the batch's task list (one execution per bsm_batch_execute). */
+bsm_status bsm_batch_verify(bsm_batch* batch, void* stream);
 
 /* Per-task features and durations of the last batch execute (members created with
  * record_timings = 1), as bsm_plan_timings; n = the batch's task count. */
@@ -180,7 +234,7 @@ bsm_status bsm_batch_set_costs(bsm_batch* batch, const float* costs, int64_t n);
 
 /* Autotuner over the whole batch (every member is re-cut for the chosen variant). */
 bsm_status bsm_batch_autotune(bsm_batch* batch, const double* const* dA, const double* const* dB,
-                              double* const* dC, void* stream, int32_t* chosen);
+                              void* const* dC, void* stream, int32_t* chosen);
 
 bsm_status bsm_batch_destroy(bsm_batch* batch);
 

@@ -17,6 +17,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "bsm.h")
 
 FP64, FP32, BF16X3 = 0, 1, 2
 SCHED_FLOPS, SCHED_MLP = 0, 1
+OUT_F64, OUT_F32 = 0, 1
+ORDER_DEFAULT, ORDER_INTERLEAVE, ORDER_LOCALITY, ORDER_LPT = 0, 1, 2, 3
 
 OK, E_INVALID, E_MISMATCH, E_NOMEM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "OK", -1: "E_INVALID", -2: "E_MISMATCH", -3: "E_NOMEM", -4: "E_HIP",
@@ -32,7 +34,9 @@ class BsmError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sched", ctypes.c_int32),
                 ("k_window", ctypes.c_int64), ("record_timings", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("out", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -42,7 +46,8 @@ class PlanInfo(ctypes.Structure):
                 ("b_elems", ctypes.c_int64), ("c_elems", ctypes.c_int64),
                 ("triples", ctypes.c_int64), ("tasks", ctypes.c_int64),
                 ("useful_flops", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
-                ("k_windows", ctypes.c_int64), ("tile", ctypes.c_int32)]
+                ("k_windows", ctypes.c_int64), ("tile", ctypes.c_int32),
+                ("out", ctypes.c_int32)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -70,6 +75,9 @@ def load() -> ctypes.CDLL:
     L.bsm_plan_c_shape.argtypes = [_p, _p]
     L.bsm_plan_c_offsets.argtypes = [_p, _p]
     L.bsm_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
+    L.bsm_plan_verify.argtypes = [_p, _p]
+    L.bsm_plan_debug_skip_task.argtypes = [_p, _i64]
+    L.bsm_batch_verify.argtypes = [_p, _p]
     L.bsm_plan_destroy.argtypes = [_p]
     L.bsm_plan_timings.argtypes = [_p, _p, _p, _i64, _p]
     L.bsm_plan_features.argtypes = [_p, _p, _i64]
@@ -99,7 +107,8 @@ def load() -> ctypes.CDLL:
     L.bsm_adam_step.argtypes = [_p, _p, _p, _p, _i64, _i64, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, _p]
     for name in ("bsm_plan_create", "bsm_plan_query", "bsm_plan_c_shape", "bsm_plan_c_offsets",
-                 "bsm_execute", "bsm_plan_destroy", "bsm_plan_timings", "bsm_plan_features",
+                 "bsm_execute", "bsm_plan_verify", "bsm_plan_debug_skip_task", "bsm_batch_verify",
+                 "bsm_plan_destroy", "bsm_plan_timings", "bsm_plan_features",
                  "bsm_plan_set_costs", "bsm_autotune", "bsm_batch_create", "bsm_batch_query",
                  "bsm_batch_execute", "bsm_batch_timings", "bsm_batch_set_costs",
                  "bsm_batch_autotune", "bsm_batch_destroy", "bsm_costmodel_create",
@@ -130,11 +139,12 @@ def _arr(a, dtype):
 
 
 def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, tile=0,
-            use_graph=0) -> Options:
+            use_graph=0, out=OUT_F64, order=ORDER_DEFAULT, tune_cache=None) -> Options:
     o = Options()
     load().bsm_options_default(ctypes.byref(o))
     o.precision, o.sched, o.k_window, o.record_timings, o.tile = precision, sched, k_window, record_timings, tile
-    o.use_graph = use_graph
+    o.use_graph, o.out, o.order = use_graph, out, order
+    o.tune_cache = tune_cache.encode() if tune_cache else None
     return o
 
 
@@ -168,8 +178,9 @@ def _dev_ptr(t) -> int:
 
 
 def _check_operands(info, A, B, C):
-    """Device buffers handed to the library must hold the plan's element counts and be FP64,
-    contiguous device tensors (the C ABI only sees the pointers)."""
+    """Device buffers handed to the library must hold the plan's element counts and be
+    contiguous device tensors of the right type: FP64 A and B, C in the plan's output type (the
+    C ABI only sees the pointers)."""
     bufs = (("A", A, info.a_elems), ("B", B, info.b_elems), ("C", C, info.c_elems))
     for name, t, need in bufs:
         if need > 0 and t is None:
@@ -178,8 +189,9 @@ def _check_operands(info, A, B, C):
             raise ValueError(f"{name} holds {t.numel()} elements, the plan needs {need}")
     used = [(name, t) for name, t, need in bufs if need > 0 and t is not None]
     for name, t in used:
-        if getattr(t, "dtype", None) is not None and str(t.dtype) != "torch.float64":
-            raise ValueError(f"{name} must be float64, got {t.dtype}")
+        want = "torch.float32" if (name == "C" and info.out == OUT_F32) else "torch.float64"
+        if getattr(t, "dtype", None) is not None and str(t.dtype) != want:
+            raise ValueError(f"{name} must be {want[6:]}, got {t.dtype}")
     for name, t in used:
         if hasattr(t, "is_contiguous") and not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
@@ -199,6 +211,7 @@ class Plan:
         self._a = _arr(a_bits, np.uint64)
         self._b = _arr(b_bits, np.uint64)
         o = opts if opts is not None else options(**kw)
+        self._opts = o  # keeps the tune-cache string alive for the call
         h = _p()
         _check(L.bsm_plan_create(ctypes.byref(h), self._rows.size, self._rows.ctypes.data,
                                  self._inner.size, self._inner.ctypes.data, self._cols.size,
@@ -230,10 +243,19 @@ class Plan:
         return out.reshape(self._rows.size, self._cols.size)
 
     def execute(self, A, B, C, alpha: float = 1.0, accumulate: bool = False, stream=None):
-        """C = alpha*A*B (+C); A, B, C are FP64 device tensors holding the packed tiles."""
+        """C = alpha*A*B (+C); A, B are FP64 device tensors holding the packed tiles, C a device
+        tensor of the plan's output type."""
         _check_operands(self.info(), A, B, C)
         _check(load().bsm_execute(self._h, float(alpha), _dev_ptr(A), _dev_ptr(B), _dev_ptr(C),
                                   int(bool(accumulate)), _stream_handle(stream)))
+
+    def verify(self, stream=None):
+        """Wait for the stream; raise BsmError(E_STATE) unless every task ran once per launch."""
+        _check(load().bsm_plan_verify(self._h, _stream_handle(stream)))
+
+    def debug_skip_task(self, task: int):
+        """Fault injection for tests: later launches leave task `task` out (-1 = none)."""
+        _check(load().bsm_plan_debug_skip_task(self._h, int(task)))
 
     def timings(self, stream=None):
         """(features[tasks, 5], seconds[tasks]) of the last timed execute."""
@@ -311,6 +333,9 @@ class Batch:
         _check(load().bsm_batch_execute(self._h, al.ctypes.data if al is not None else None,
                                         _ptr_array(As), _ptr_array(Bs), _ptr_array(Cs),
                                         int(bool(accumulate)), _stream_handle(stream)))
+
+    def verify(self, stream=None):
+        _check(load().bsm_batch_verify(self._h, _stream_handle(stream)))
 
     def timings(self, stream=None):
         n = self.query()[0]

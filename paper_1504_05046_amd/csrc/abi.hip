@@ -35,34 +35,46 @@ static bsm_status hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 // ------------------------------------------------------------------------------------------------
-// Device copies of a task list: tasks, triples, optional per-task clocks.
+// Device copies of a task list: tasks, triples, per-task execution counters, optional per-task
+// clocks.
 struct TaskSet {
   Item* items = nullptr;
   Triple* tri = nullptr;
   uint64_t* stamps = nullptr;
+  uint32_t* done = nullptr;  // executions of each task since the last upload
   size_t n_items = 0, n_tri = 0;
-  bool timed = false;  // a launch has recorded clocks since the tasks last changed
+  int64_t expected = 0;      // executions every task should have had by now
+  bool timed = false;        // a launch has recorded clocks since the tasks last changed
+  bool used = false;         // work that reads these buffers may be queued
 
   void release() {
-    if (items) (void)hipFree(items);
-    if (tri) (void)hipFree(tri);
-    if (stamps) (void)hipFree(stamps);
+    for (void* ptr : {static_cast<void*>(items), static_cast<void*>(tri),
+                      static_cast<void*>(stamps), static_cast<void*>(done)})
+      if (ptr) (void)hipFree(ptr);
     items = nullptr;
     tri = nullptr;
     stamps = nullptr;
+    done = nullptr;
     n_items = n_tri = 0;
   }
 
   // (Re-)upload tasks (always) and triples (when their count changed); clocks if asked for.
-  bsm_status upload(const HostPlan& h, bool with_stamps) {
+  // Launches queued earlier on `stream` may still read the old tables, so they are waited for
+  // first.  The execution counters start again from zero.
+  bsm_status upload(const HostPlan& h, bool with_stamps, hipStream_t stream) {
+    if (used) BSM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
     if (h.items.size() != n_items) {
-      if (items) (void)hipFree(items);
-      if (stamps) (void)hipFree(stamps);
+      for (void* ptr : {static_cast<void*>(items), static_cast<void*>(stamps), static_cast<void*>(done)})
+        if (ptr) (void)hipFree(ptr);
       items = nullptr;
       stamps = nullptr;
+      done = nullptr;
       n_items = h.items.size();
       if (n_items) BSM_HIP(hipMalloc(&items, n_items * sizeof(Item)), "hipMalloc(tasks)");
+      if (n_items) BSM_HIP(hipMalloc(&done, n_items * sizeof(uint32_t)), "hipMalloc(counters)");
     }
+    if (n_items) BSM_HIP(hipMemset(done, 0, n_items * sizeof(uint32_t)), "hipMemset(counters)");
+    expected = 0;
     if (n_items)
       BSM_HIP(hipMemcpy(items, h.items.data(), n_items * sizeof(Item), hipMemcpyHostToDevice),
               "hipMemcpy(tasks)");
@@ -78,6 +90,22 @@ struct TaskSet {
     if (with_stamps && !stamps && n_items)
       BSM_HIP(hipMalloc(&stamps, n_items * 16), "hipMalloc(clocks)");
     timed = false;
+    return BSM_OK;
+  }
+
+  // Waits for `stream`, then checks that every task ran exactly `expected` times.
+  bsm_status verify(hipStream_t stream) {
+    BSM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (!n_items) return BSM_OK;
+    std::vector<uint32_t> c(n_items);
+    BSM_HIP(hipMemcpy(c.data(), done, n_items * sizeof(uint32_t), hipMemcpyDeviceToHost),
+            "hipMemcpy(counters)");
+    for (size_t q = 0; q < n_items; ++q)
+      if (int64_t(c[q]) != expected) {
+        g_error = "task " + std::to_string(q) + " ran " + std::to_string(c[q]) +
+                  " times, expected " + std::to_string(expected);
+        return BSM_E_STATE;
+      }
     return BSM_OK;
   }
 };
@@ -147,6 +175,7 @@ struct bsm_plan {
   bool ready = false;               // device buffers allocated
   bool tasks_dirty = true;          // host tasks changed since the last upload
   int use_graph = 0;
+  int skip_task = -1;               // fault injection: task left out of every launch
 };
 
 struct bsm_batch {
@@ -157,6 +186,7 @@ struct bsm_batch {
   std::vector<ProductArgs> h_prods;
   GraphCache gc;
   bool tasks_dirty = true;
+  bool table_used = false;          // a queued launch may read d_prods
 };
 
 static bsm_status check_device(int* dev) {
@@ -201,9 +231,9 @@ static bsm_status prepare(bsm_plan* p) {
   return BSM_OK;
 }
 
-static bsm_status sync_tasks(bsm_plan* p) {
+static bsm_status sync_tasks(bsm_plan* p, hipStream_t stream) {
   if (!p->tasks_dirty) return BSM_OK;
-  bsm_status st = p->ts.upload(p->hp, p->hp.cfg.record_timings != 0);
+  bsm_status st = p->ts.upload(p->hp, p->hp.cfg.record_timings != 0, stream);
   if (st != BSM_OK) return st;
   p->tasks_dirty = false;
   p->gc.invalidate();
@@ -248,11 +278,14 @@ static hipError_t launch_form(int precision, int variant, int64_t grid, const Ti
 
 // S7/S8 (and S5): the tile kernel over a task list, once per k-window.
 static bsm_status enqueue_tiles(const HostPlan& h, TaskSet& ts, const ProductArgs* prods,
-                                const ProductArgs& single, int accumulate, hipStream_t s) {
+                                const ProductArgs& single, int accumulate, int skip_task,
+                                hipStream_t s) {
   if (h.items.empty()) return BSM_OK;
   TileArgs a{};
   a.items = ts.items;
   a.tri = ts.tri;
+  a.done = ts.done;
+  a.skip_task = skip_task;
   for (int x = 0; x <= kXcds; ++x) a.map.begin[x] = h.xcd_begin[x];
   a.prods = prods;
   a.single = single;
@@ -280,10 +313,11 @@ static bool overlaps(const void* a, int64_t na, const void* b, int64_t nb) {
 }
 
 static bsm_status check_operands(const HostPlan& h, const double* dA, const double* dB,
-                                 const double* dC, int accumulate) {
+                                 const void* dC, int accumulate) {
   if ((h.a_elems > 0 && !dA) || (h.b_elems > 0 && !dB) || (h.c_elems > 0 && !dC))
     return fail(BSM_E_INVALID, "null tile buffer");
-  if (overlaps(dC, h.c_elems * 8, dA, h.a_elems * 8) || overlaps(dC, h.c_elems * 8, dB, h.b_elems * 8))
+  const int64_t cb = h.c_elems * (h.cfg.out_f32 ? 4 : 8);
+  if (overlaps(dC, cb, dA, h.a_elems * 8) || overlaps(dC, cb, dB, h.b_elems * 8))
     return fail(BSM_E_INVALID, "C overlaps A or B");
   if (accumulate != 0 && accumulate != 1) return fail(BSM_E_INVALID, "accumulate must be 0 or 1");
   return BSM_OK;
@@ -295,7 +329,8 @@ static bsm_status timings_of(const HostPlan& h, TaskSet& ts, float* features, fl
   if (!ts.timed) return fail(BSM_E_STATE, "no execute with record_timings has run since the tasks last changed");
   if (n == 0) return BSM_OK;
   if (!features && !seconds) return fail(BSM_E_INVALID, "null output");
-  BSM_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "hipStreamSynchronize");
+  bsm_status vs = ts.verify(static_cast<hipStream_t>(stream));  // synchronises the stream
+  if (vs != BSM_OK) return vs;
   std::vector<uint64_t> st(size_t(n) * 2);
   BSM_HIP(hipMemcpy(st.data(), ts.stamps, st.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy(clocks)");
   for (int64_t q = 0; q < n; ++q) {
@@ -321,7 +356,7 @@ static bsm_status set_costs(HostPlan& h, const float* costs, int64_t n) {
 
 // ------------------------------------------------------------------------------------------------
 // Autotuning: time each tile variant on the caller's operands and keep the fastest.  Choices are
-// remembered per workload signature in the file named by BSM_TUNE_CACHE (lines "key variant").
+// remembered per workload signature in the plan's tune-cache file (lines "key variant").
 static std::string tune_key(const std::vector<const HostPlan*>& parts) {
   double nb = 0, sm = 0, sn = 0, sk = 0;
   for (const HostPlan* p : parts)
@@ -337,10 +372,9 @@ static std::string tune_key(const std::vector<const HostPlan*>& parts) {
   return buf;
 }
 
-static int tune_cache_lookup(const std::string& key) {
-  const char* path = std::getenv("BSM_TUNE_CACHE");
-  if (!path) return -1;
-  FILE* f = std::fopen(path, "r");
+static int tune_cache_lookup(const std::string& path, const std::string& key) {
+  if (path.empty()) return -1;
+  FILE* f = std::fopen(path.c_str(), "r");
   if (!f) return -1;
   char k[256];
   int v, found = -1;
@@ -350,10 +384,9 @@ static int tune_cache_lookup(const std::string& key) {
   return found;
 }
 
-static void tune_cache_store(const std::string& key, int v) {
-  const char* path = std::getenv("BSM_TUNE_CACHE");
-  if (!path) return;
-  FILE* f = std::fopen(path, "a");
+static void tune_cache_store(const std::string& path, const std::string& key, int v) {
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "a");
   if (!f) return;
   std::fprintf(f, "%s %d\n", key.c_str(), v);
   std::fclose(f);
@@ -377,6 +410,9 @@ static bsm_status time_body(const std::function<bsm_status(hipStream_t)>& body, 
   (void)hipEventDestroy(e1);
   return st;
 }
+
+// Timed repetitions per tile variant (after one warm-up run).
+constexpr int kTuneReps = 5;
 
 static int num_variants(int precision) {
   return precision == BSM_BF16X3 ? kNumBf16Variants : kNumVariants;
@@ -473,6 +509,9 @@ void bsm_options_default(bsm_options* opt) {
   opt->record_timings = 0;
   opt->tile = 0;
   opt->use_graph = 0;
+  opt->out = BSM_OUT_F64;
+  opt->order = BSM_ORDER_DEFAULT;
+  opt->tune_cache = nullptr;
 }
 
 int32_t bsm_tile_variants(int32_t* tm, int32_t* tn, int32_t cap) {
@@ -499,14 +538,22 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
   bsm_options_default(&o);
   if (opt) o = *opt;
   if (o.use_graph != 0 && o.use_graph != 1) return fail(BSM_E_INVALID, "use_graph must be 0 or 1");
+  if (o.out != BSM_OUT_F64 && o.out != BSM_OUT_F32) return fail(BSM_E_INVALID, "unknown output type");
   PlanConfig cfg;
   cfg.precision = o.precision;
   cfg.sched = o.sched;
   cfg.k_window = o.k_window;
   cfg.record_timings = o.record_timings;
   cfg.tile = o.tile;
-  if (const char* s = getenv("BSM_ORDER")) cfg.order = atoi(s);
-  if (const char* s = getenv("BSM_CUT")) cfg.cut_search = atoi(s) != 0;
+  cfg.out_f32 = o.out == BSM_OUT_F32;
+  switch (o.order) {
+    case BSM_ORDER_DEFAULT:
+    case BSM_ORDER_INTERLEAVE: cfg.order = ORDER_INTERLEAVE; break;
+    case BSM_ORDER_LOCALITY: cfg.order = ORDER_LOCALITY; break;
+    case BSM_ORDER_LPT: cfg.order = ORDER_LPT; break;
+    default: return fail(BSM_E_INVALID, "unknown task order");
+  }
+  if (o.tune_cache) cfg.tune_cache = o.tune_cache;
   bsm_plan* p = new (std::nothrow) bsm_plan;
   if (!p) return fail(BSM_E_NOMEM, "host allocation failed");
   int code = BSM_OK;
@@ -550,6 +597,7 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   info->workspace_bytes = ws;
   info->k_windows = h.windows;
   info->tile = h.variant + 1;
+  info->out = h.cfg.out_f32 ? BSM_OUT_F32 : BSM_OUT_F64;
   return BSM_OK;
 }
 
@@ -568,30 +616,52 @@ bsm_status bsm_plan_c_offsets(const bsm_plan* plan, int64_t* c_offsets) {
 }
 
 bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
-                       double* dC, int accumulate, void* stream) {
+                       void* dC, int accumulate, void* stream) {
   if (!plan) return fail(BSM_E_INVALID, "plan is null");
   const HostPlan& h = plan->hp;
+  hipStream_t s = static_cast<hipStream_t>(stream);
   bsm_status st = check_operands(h, dA, dB, dC, accumulate);
   if (st != BSM_OK) return st;
   if ((st = prepare(plan)) != BSM_OK) return st;
-  if ((st = sync_tasks(plan)) != BSM_OK) return st;
+  if ((st = sync_tasks(plan, s)) != BSM_OK) return st;
   if (h.items.empty()) return BSM_OK;
-  auto body = [&](hipStream_t s) -> bsm_status {
+  auto body = [&](hipStream_t q) -> bsm_status {
     ProductArgs pa{};
-    bsm_status r = enqueue_convert(plan, dA, dB, s, pa);
+    bsm_status r = enqueue_convert(plan, dA, dB, q, pa);
     if (r != BSM_OK) return r;
     pa.C = dC;
+    pa.c_f32 = h.cfg.out_f32;
     pa.P = plan->d_partial;
     pa.alpha = alpha;
-    return enqueue_tiles(h, plan->ts, nullptr, pa, accumulate, s);
+    return enqueue_tiles(h, plan->ts, nullptr, pa, accumulate, plan->skip_task, q);
   };
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!plan->use_graph) return body(s);
-  std::vector<uint64_t> key{uint64_t(uintptr_t(dA)), uint64_t(uintptr_t(dB)), uint64_t(uintptr_t(dC)),
-                            bits_of(alpha), uint64_t(accumulate)};
-  st = plan->gc.run(key, body, s);
-  if (st == BSM_OK && plan->ts.stamps) plan->ts.timed = true;
+  if (!plan->use_graph) {
+    st = body(s);
+  } else {
+    std::vector<uint64_t> key{uint64_t(uintptr_t(dA)), uint64_t(uintptr_t(dB)), uint64_t(uintptr_t(dC)),
+                              bits_of(alpha), uint64_t(accumulate)};
+    st = plan->gc.run(key, body, s);
+    if (st == BSM_OK && plan->ts.stamps) plan->ts.timed = true;
+  }
+  if (st == BSM_OK) {
+    plan->ts.used = true;
+    plan->ts.expected += h.windows;
+  }
   return st;
+}
+
+bsm_status bsm_plan_verify(bsm_plan* plan, void* stream) {
+  if (!plan) return fail(BSM_E_INVALID, "plan is null");
+  return plan->ts.verify(static_cast<hipStream_t>(stream));
+}
+
+bsm_status bsm_plan_debug_skip_task(bsm_plan* plan, int64_t task) {
+  if (!plan) return fail(BSM_E_INVALID, "plan is null");
+  if (task < -1 || task >= int64_t(plan->hp.items.size()))
+    return fail(BSM_E_INVALID, "task must be -1 or a task index");
+  plan->skip_task = int(task);
+  plan->gc.invalidate();
+  return BSM_OK;
 }
 
 bsm_status bsm_plan_timings(bsm_plan* plan, float* features, float* seconds, int64_t n,
@@ -615,46 +685,48 @@ bsm_status bsm_plan_set_costs(bsm_plan* plan, const float* costs, int64_t n) {
   return st;
 }
 
-bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, double* dC,
+bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, void* dC,
                         void* stream, int32_t* chosen) {
   if (!plan) return fail(BSM_E_INVALID, "plan is null");
   HostPlan& h = plan->hp;
+  hipStream_t s = static_cast<hipStream_t>(stream);
   bsm_status st = check_operands(h, dA, dB, dC, 0);
   if (st != BSM_OK) return st;
   if ((st = prepare(plan)) != BSM_OK) return st;
   const std::string key = tune_key({&h});
-  int best = tune_cache_lookup(key);
+  int best = tune_cache_lookup(h.cfg.tune_cache, key);
   if (best < 0 || best >= num_variants(h.cfg.precision)) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
     float best_ms = 0.f;
     best = h.variant;
     for (int v = 0; v < num_variants(h.cfg.precision); ++v) {
       cut_items(h, v);
       schedule(h, flop_costs(h));
       plan->tasks_dirty = true;
-      if ((st = sync_tasks(plan)) != BSM_OK) return st;
+      if ((st = sync_tasks(plan, s)) != BSM_OK) return st;
       auto body = [&](hipStream_t q) -> bsm_status {
         ProductArgs pa{};
         bsm_status r = enqueue_convert(plan, dA, dB, q, pa);
         if (r != BSM_OK) return r;
         pa.C = dC;
+        pa.c_f32 = h.cfg.out_f32;
         pa.P = plan->d_partial;
         pa.alpha = 1.0;
-        return enqueue_tiles(h, plan->ts, nullptr, pa, 0, q);
+        return enqueue_tiles(h, plan->ts, nullptr, pa, 0, -1, q);
       };
+      plan->ts.used = true;
       float ms = 0.f;
-      if ((st = time_body(body, s, 2, &ms)) != BSM_OK) return st;
+      if ((st = time_body(body, s, kTuneReps, &ms)) != BSM_OK) return st;
       if (v == 0 || ms < best_ms) {
         best_ms = ms;
         best = v;
       }
     }
-    tune_cache_store(key, best);
+    tune_cache_store(h.cfg.tune_cache, key, best);
   }
   cut_items(h, best);
   schedule(h, flop_costs(h));
   plan->tasks_dirty = true;
-  if ((st = sync_tasks(plan)) != BSM_OK) return st;
+  if ((st = sync_tasks(plan, s)) != BSM_OK) return st;
   if (chosen) *chosen = best + 1;
   return BSM_OK;
 }
@@ -683,6 +755,13 @@ bsm_status bsm_batch_create(bsm_batch** out, bsm_plan* const* plans, int64_t n) 
   std::vector<const HostPlan*> parts;
   for (int64_t q = 0; q < n; ++q) {
     if (!plans[q]) return fail(BSM_E_INVALID, "null plan in batch");
+    // the FP32 and split-bf16 forms convert a member's operands into buffers the plan owns, so a
+    // plan can stand for one product of the batch only
+    if (plans[q]->hp.cfg.precision != BSM_FP64)
+      for (int64_t r = 0; r < q; ++r)
+        if (plans[r] == plans[q])
+          return fail(BSM_E_INVALID, "plan " + std::to_string(q) + " repeats plan " + std::to_string(r) +
+                                         " (a FP32 or split-bf16 plan can be a batch member once)");
     parts.push_back(&plans[q]->hp);
   }
   bsm_batch* b = new (std::nothrow) bsm_batch;
@@ -713,9 +792,9 @@ bsm_status bsm_batch_query(const bsm_batch* batch, int64_t* tasks, double* usefu
   return BSM_OK;
 }
 
-static bsm_status batch_sync(bsm_batch* b) {
+static bsm_status batch_sync(bsm_batch* b, hipStream_t stream) {
   if (!b->tasks_dirty) return BSM_OK;
-  bsm_status st = b->ts.upload(b->hp, b->members[0]->hp.cfg.record_timings != 0);
+  bsm_status st = b->ts.upload(b->hp, b->members[0]->hp.cfg.record_timings != 0, stream);
   if (st != BSM_OK) return st;
   b->tasks_dirty = false;
   b->gc.invalidate();
@@ -729,12 +808,13 @@ static bsm_status batch_body(bsm_batch* b, const double* const* dA, const double
     bsm_status st = enqueue_convert(b->members[q], dA[q], dB[q], s, pa);
     if (st != BSM_OK) return st;
   }
-  return enqueue_tiles(b->hp, b->ts, b->d_prods, ProductArgs{}, accumulate, s);
+  return enqueue_tiles(b->hp, b->ts, b->d_prods, ProductArgs{}, accumulate, -1, s);
 }
 
-// Operand table of the batch (device copy refreshed only when a pointer or alpha changed).
+// Operand table of the batch (device copy refreshed only when a pointer or alpha changed; a
+// launch queued on `stream` may still read the old one, so it is waited for first).
 static bsm_status batch_table(bsm_batch* b, const double* alphas, const double* const* dA,
-                              const double* const* dB, double* const* dC) {
+                              const double* const* dB, void* const* dC, hipStream_t stream) {
   const size_t n = b->members.size();
   std::vector<ProductArgs> t(n);
   for (size_t q = 0; q < n; ++q) {
@@ -754,12 +834,14 @@ static bsm_status batch_table(bsm_batch* b, const double* alphas, const double* 
       pa.b_plane = h.b_elems32;
     }
     pa.C = dC[q];
+    pa.c_f32 = h.cfg.out_f32;
     pa.P = nullptr;
     pa.alpha = alphas ? alphas[q] : 1.0;
   }
   bool same = t.size() == b->h_prods.size() && b->d_prods &&
               std::memcmp(t.data(), b->h_prods.data(), n * sizeof(ProductArgs)) == 0;
   if (!same) {
+    if (b->table_used) BSM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
     if (!b->d_prods) BSM_HIP(hipMalloc(&b->d_prods, n * sizeof(ProductArgs)), "hipMalloc(operand table)");
     BSM_HIP(hipMemcpy(b->d_prods, t.data(), n * sizeof(ProductArgs), hipMemcpyHostToDevice),
             "hipMemcpy(operand table)");
@@ -769,17 +851,18 @@ static bsm_status batch_table(bsm_batch* b, const double* alphas, const double* 
 }
 
 bsm_status bsm_batch_execute(bsm_batch* batch, const double* alphas, const double* const* dA,
-                             const double* const* dB, double* const* dC, int accumulate,
+                             const double* const* dB, void* const* dC, int accumulate,
                              void* stream) {
   if (!batch) return fail(BSM_E_INVALID, "batch is null");
   if (!dA || !dB || !dC) return fail(BSM_E_INVALID, "null operand array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
   bsm_status st;
   for (size_t q = 0; q < batch->members.size(); ++q) {
     if ((st = check_operands(batch->members[q]->hp, dA[q], dB[q], dC[q], accumulate)) != BSM_OK) return st;
     if ((st = prepare(batch->members[q])) != BSM_OK) return st;
   }
-  if ((st = batch_sync(batch)) != BSM_OK) return st;
-  if ((st = batch_table(batch, alphas, dA, dB, dC)) != BSM_OK) return st;
+  if ((st = batch_sync(batch, s)) != BSM_OK) return st;
+  if ((st = batch_table(batch, alphas, dA, dB, dC, s)) != BSM_OK) return st;
   if (batch->hp.items.empty()) return BSM_OK;
   // one graph: every member's operand conversion, then one tile launch over all tasks
   std::vector<uint64_t> key{uint64_t(accumulate)};
@@ -789,10 +872,20 @@ bsm_status bsm_batch_execute(bsm_batch* batch, const double* alphas, const doubl
     key.push_back(uint64_t(uintptr_t(dC[q])));
     key.push_back(bits_of(alphas ? alphas[q] : 1.0));
   }
-  auto body = [&](hipStream_t s) { return batch_body(batch, dA, dB, accumulate, s); };
-  st = batch->gc.run(key, body, static_cast<hipStream_t>(stream));
-  if (st == BSM_OK && batch->ts.stamps) batch->ts.timed = true;
+  auto body = [&](hipStream_t q) { return batch_body(batch, dA, dB, accumulate, q); };
+  st = batch->gc.run(key, body, s);
+  if (st == BSM_OK) {
+    if (batch->ts.stamps) batch->ts.timed = true;
+    batch->ts.used = true;
+    batch->table_used = true;
+    batch->ts.expected += 1;
+  }
   return st;
+}
+
+bsm_status bsm_batch_verify(bsm_batch* batch, void* stream) {
+  if (!batch) return fail(BSM_E_INVALID, "batch is null");
+  return batch->ts.verify(static_cast<hipStream_t>(stream));
 }
 
 bsm_status bsm_batch_timings(bsm_batch* batch, float* features, float* seconds, int64_t n,
@@ -809,9 +902,10 @@ bsm_status bsm_batch_set_costs(bsm_batch* batch, const float* costs, int64_t n) 
 }
 
 bsm_status bsm_batch_autotune(bsm_batch* batch, const double* const* dA, const double* const* dB,
-                              double* const* dC, void* stream, int32_t* chosen) {
+                              void* const* dC, void* stream, int32_t* chosen) {
   if (!batch) return fail(BSM_E_INVALID, "batch is null");
   if (!dA || !dB || !dC) return fail(BSM_E_INVALID, "null operand array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
   bsm_status st;
   std::vector<const HostPlan*> parts;
   for (size_t q = 0; q < batch->members.size(); ++q) {
@@ -831,25 +925,27 @@ bsm_status bsm_batch_autotune(bsm_batch* batch, const double* const* dA, const d
     std::string err = merge_plans(batch->hp, parts, &code);
     if (code != BSM_OK) return fail(bsm_status(code), err);
     batch->tasks_dirty = true;
-    return batch_sync(batch);
+    return batch_sync(batch, s);
   };
-  int best = tune_cache_lookup(key);
+  const std::string& cache = parts[0]->cfg.tune_cache;
+  int best = tune_cache_lookup(cache, key);
   if (best < 0 || best >= num_variants(prec)) {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((st = batch_table(batch, nullptr, dA, dB, dC)) != BSM_OK) return st;
+    if ((st = batch_table(batch, nullptr, dA, dB, dC, s)) != BSM_OK) return st;
+    batch->table_used = true;
     float best_ms = 0.f;
     best = 0;
     for (int v = 0; v < num_variants(prec); ++v) {
       if ((st = recut(v)) != BSM_OK) return st;
       auto body = [&](hipStream_t q) { return batch_body(batch, dA, dB, 0, q); };
+      batch->ts.used = true;
       float ms = 0.f;
-      if ((st = time_body(body, s, 2, &ms)) != BSM_OK) return st;
+      if ((st = time_body(body, s, kTuneReps, &ms)) != BSM_OK) return st;
       if (v == 0 || ms < best_ms) {
         best_ms = ms;
         best = v;
       }
     }
-    tune_cache_store(key, best);
+    tune_cache_store(cache, key, best);
   }
   if ((st = recut(best)) != BSM_OK) return st;
   if (chosen) *chosen = best + 1;

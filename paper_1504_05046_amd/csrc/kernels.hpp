@@ -26,6 +26,8 @@ struct TileArgs {
   int k_lo, k_hi;            // only triples with k in [k_lo, k_hi) (k-window)
   int win_first, win_last;   // first window starts from 0, later ones from the partial sums
   uint64_t* stamps;          // 2 per task: start/end of the 100 MHz constant clock, or NULL
+  uint32_t* done;            // per task: executions so far (checked by the host), or NULL
+  int skip_task;             // task index the kernel leaves out (fault injection for tests), or -1
 };
 
 hipError_t launch_tiles_f64(int variant, int64_t grid, const TileArgs& args, hipStream_t stream);

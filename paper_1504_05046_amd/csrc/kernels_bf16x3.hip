@@ -233,12 +233,8 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
         const int row = 16 * (rb0 + x) + 4 * g + r;
         if (row < h && col < w) {
           const int64_t e = c_base + int64_t(row) * ldc + col;
-          if (a.win_last) {
-            const double v = alpha * acc[x][y][r];
-            pa.C[e] = a.accumulate ? v + pa.C[e] : v;
-          } else {
-            pa.P[e] = acc[x][y][r];
-          }
+          if (a.win_last) store_c(pa, e, alpha * acc[x][y][r], a.accumulate);
+          else pa.P[e] = acc[x][y][r];
         }
       }
     }
@@ -266,7 +262,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void tiles_bf16x3(TileArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2 * C::BSZ];
   const int x = blockIdx.x % kXcds, qx = blockIdx.x / kXcds;
   const int idx = a.map.begin[x] + qx;
-  if (idx >= a.map.begin[x + 1]) return;
+  if (idx >= a.map.begin[x + 1] || idx == a.skip_task) return;
   if (a.stamps && threadIdx.x == 0) a.stamps[2 * idx] = wall_clock64();
   const Item it = uni(a.items[idx]);
   const ProductArgs pa = uni(a.prods ? a.prods[it.product] : a.single);
@@ -281,6 +277,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void tiles_bf16x3(TileArgs a) {
     __syncthreads();
     if (threadIdx.x == 0) a.stamps[2 * idx + 1] = wall_clock64();
   }
+  if (threadIdx.x == 0) count_task(a.done, idx);
 }
 
 }  // namespace

@@ -1,14 +1,11 @@
 // Host planner.  Paper Sec. 3.2: the matrices are over-decomposed into problem-given blocks and
-// each rank-k update is split into per-block multiply tasks; Fig. 3 decomposes one iteration so
-// that every task computes a small sub-block of the local result.  Here a task is a sub-tile of
+// each rank-k update is split into per-block multiply tasks; Fig. 3 splits one iteration into
+// tasks that each produce one piece of the process's part of C.  Here a task is a sub-tile of
 // one present C block together with that block's whole k-list, so the multiply and the reduction
 // into C are one task (no temporaries, one writer per C element).
 #include "plan.hpp"
-#include "wave_rects.inc"
 
 #include <algorithm>
-#include <array>
-#include <map>
 #include <cmath>
 #include <numeric>
 
@@ -62,77 +59,16 @@ static int64_t pack_offsets(int64_t R, int64_t C, const std::vector<int64_t>& rs
   return pos;
 }
 
-// Sub-tile cuts of one C block.  A dimension of nb16 16-row blocks is cut into the fewest
-// pieces of at most `per` blocks; among all such cuts of both dimensions the planner takes the
-// one whose slowest wave issues the fewest MFMAs (each of a workgroup's NW waves owns a rectangle
-// of the sub-tile's 16x16 output blocks; the busiest owns wave_rect_max blocks, which is
-// ceil(blocks / NW) for all but a few shapes).
-static void compositions(int total, int parts, int per, std::vector<int>& cur,
-                         std::vector<std::vector<int>>& out) {
-  if (parts == 1) {
-    if (total >= 1 && total <= per) {
-      cur.push_back(total);
-      out.push_back(cur);
-      cur.pop_back();
-    }
-    return;
-  }
-  for (int a = 1; a <= per && a <= total - (parts - 1); ++a) {
-    cur.push_back(a);
-    compositions(total - a, parts - 1, per, cur, out);
-    cur.pop_back();
-  }
-}
-
-static std::vector<std::vector<int>> cuts_of(int nb16, int per, bool search) {
-  int parts = (nb16 + per - 1) / per;
-  std::vector<std::vector<int>> out;
-  if (search && parts <= 3) {
-    std::vector<int> cur;
-    compositions(nb16, parts, per, cur, out);
-  } else {  // large blocks: near-equal pieces
-    std::vector<int> c;
-    int base = nb16 / parts, extra = nb16 % parts;
-    for (int p = 0; p < parts; ++p) c.push_back(base + (p < extra ? 1 : 0));
-    out.push_back(c);
-  }
-  return out;
-}
-
-struct CutChoice {
-  std::vector<int> rows, cols;  // piece sizes in 16-blocks
-};
-
-static const CutChoice& best_cut(int br, int bc, int per_r, int per_c, int nw, bool search,
-                                 std::map<std::array<int, 5>, CutChoice>& memo) {
-  std::array<int, 5> key{br, bc, per_r, per_c, nw};
-  auto f = memo.find(key);
-  if (f != memo.end()) return f->second;
-  auto rc = cuts_of(br, per_r, search), cc = cuts_of(bc, per_c, search);
-  int64_t best = -1;
-  CutChoice choice;
-  for (auto& r : rc)
-    for (auto& c : cc) {
-      int64_t cost = 0;
-      for (int a : r)
-        for (int b : c) {
-          const int mx = wave_rect_max(16 * per_r, 16 * per_c, nw, a, b);
-          cost += mx > 0 ? mx : (a * b + nw - 1) / nw;
-        }
-      if (best < 0 || cost < best) {
-        best = cost;
-        choice.rows = r;
-        choice.cols = c;
-      }
-    }
-  return memo.emplace(key, choice).first->second;
-}
-
-static void pieces_to_ranges(const std::vector<int>& blocks, int m,
-                             std::vector<std::pair<int, int>>& out) {
+// Sub-tile cuts of one C block: a dimension of nb16 16-row blocks is cut into the fewest pieces
+// of at most `per` blocks, as equal as the 16-row granule allows (larger pieces first).
+static void cut_dim(int m, int per, std::vector<std::pair<int, int>>& out) {
   out.clear();
+  const int nb16 = (m + 15) / 16;
+  const int parts = (nb16 + per - 1) / per;
+  const int base = nb16 / parts, extra = nb16 % parts;
   int off = 0;
-  for (int nb : blocks) {
+  for (int q = 0; q < parts; ++q) {
+    const int nb = base + (q < extra ? 1 : 0);
     out.emplace_back(off, std::min(nb * 16, m - off));
     off += nb * 16;
   }
@@ -245,15 +181,12 @@ void cut_items(HostPlan& p, int variant) {
   const bool bf16 = p.cfg.precision == 2;
   const Variant& var = bf16 ? kBf16Variants[variant] : kVariants[variant];
   std::vector<std::pair<int, int>> rs, cs;
-  std::map<std::array<int, 5>, CutChoice> cut_memo;
   p.items.clear();
   p.features.clear();
   p.variant = variant;
   for (const CBlock& cb : p.cblocks) {
-    const CutChoice& cut = best_cut((cb.m + 15) / 16, (cb.n + 15) / 16, var.tm / 16, var.tn / 16,
-                                    var.nw, p.cfg.cut_search, cut_memo);
-    pieces_to_ranges(cut.rows, cb.m, rs);
-    pieces_to_ranges(cut.cols, cb.n, cs);
+    cut_dim(cb.m, var.tm / 16, rs);
+    cut_dim(cb.n, var.tn / 16, cs);
     for (auto& r : rs)
       for (auto& c : cs) {
         Item it;
@@ -293,6 +226,7 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   if (cfg.k_window < 0) return "negative k_window";
   if (cfg.tile < 0 || cfg.tile > (cfg.precision == 2 ? kNumBf16Variants : kNumVariants))
     return "unknown tile variant";
+  if (cfg.order < ORDER_LOCALITY || cfg.order > ORDER_INTERLEAVE) return "unknown task order";
 
   p.cfg = cfg;
   p.M = M; p.K = K; p.N = N;

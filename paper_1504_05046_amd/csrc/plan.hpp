@@ -33,7 +33,8 @@ struct PlanConfig {
   int record_timings = 0;
   int tile = 0;       // 0 = auto, else variant id + 1
   int order = ORDER_INTERLEAVE;
-  bool cut_search = false;  // choose sub-tile cuts by slowest-wave cost (else near-equal pieces)
+  int out_f32 = 0;    // C holds FP32 elements
+  std::string tune_cache;  // autotuner choices file ("" = none)
 };
 
 // A present C block and its k-list (the unit tasks are cut from).

@@ -161,19 +161,22 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
   // Staging loads go through buffer descriptors: a load whose offset lies past num_records
   // returns 0 instead of touching memory.  A's descriptor ends at row h of the sub-tile, so rows
   // beyond it read 0; the k-tail (k >= s_k would wrap into the next row) is sent out of range
-  // explicitly.  B's descriptor ends at the last element of the sub-tile's columns, so k-rows
-  // beyond s_k read 0; columns beyond w read finite neighbours that only feed output columns the
-  // epilogue discards.  A chunk past the end of the k-list is loaded with empty descriptors
-  // (zeros, no memory access), so that every chunk issues the same loads.
+  // explicitly.  B's descriptor starts at the chunk's first k-row (64-bit base, so offsets stay
+  // below KC rows of the block whatever its size) and ends at the last element of the sub-tile's
+  // columns in the chunk's last k-row below s_k, so k-rows beyond s_k read 0; columns beyond w
+  // read finite neighbours that only feed output columns the epilogue discards.  A chunk past
+  // the end of the k-list is loaded with empty descriptors (zeros, no memory access), so that
+  // every chunk issues the same loads.
   constexpr int NPART = C::KC / 4;
   auto load = [&](const Triple& t, int kk, bool valid, Regs& R, int part) {
     const int ks = tri_ks(t);
     const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(
         uni_ptr(const_cast<T*>(Ag + tri_a_off(t) + int64_t(it.r0) * ks)), (short)0,
         uni(valid ? h * ks * C::ES : 0), kRsrcWord3);
+    const int krows = min(C::KC, ks - kk);  // k-rows of B_kj in this chunk (>= 1 when valid)
     const __amdgpu_buffer_rsrc_t br = __builtin_amdgcn_make_buffer_rsrc(
-        uni_ptr(const_cast<T*>(Bg + tri_b_off(t) + it.c0)), (short)0,
-        uni(valid ? ((ks - 1) * ldc + w) * C::ES : 0), kRsrcWord3);
+        uni_ptr(const_cast<T*>(Bg + tri_b_off(t) + int64_t(kk) * ldc + it.c0)), (short)0,
+        uni(valid ? ((krows - 1) * ldc + w) * C::ES : 0), kRsrcWord3);
     const bool kin = kk + ka < ks;
 #pragma unroll
     for (int p = 0; p < C::ALD; ++p) {
@@ -185,7 +188,7 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
 #pragma unroll
     for (int p = 0; p < C::BLD; ++p) {
       if (part < 0 || p % NPART == part) {
-        const uint32_t off = uint32_t(((kk + kb0 + C::BK * p) * ldc + cbl) * C::ES);
+        const uint32_t off = uint32_t(((kb0 + C::BK * p) * ldc + cbl) * C::ES);
         R.b[p] = F::load(br, off);
       }
     }
@@ -306,12 +309,8 @@ __device__ __forceinline__ void run_task(const TileArgs& a, const Item& it, cons
       int row = 16 * rbk + F::out_row(g, r);
       if (row < h && col < w) {
         const int64_t e = c_base + int64_t(row) * ldc + col;
-        if (a.win_last) {
-          double v = alpha * acc[j][r];
-          pa.C[e] = a.accumulate ? v + pa.C[e] : v;
-        } else {
-          pa.P[e] = acc[j][r];
-        }
+        if (a.win_last) store_c(pa, e, alpha * acc[j][r], a.accumulate);
+        else pa.P[e] = acc[j][r];
       }
     }
   }
@@ -350,7 +349,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void tiles(TileArgs a) {
   // workgroup 8q + x runs on XCD x and takes that XCD's q-th task.
   const int x = blockIdx.x % kXcds, qx = blockIdx.x / kXcds;
   const int idx = a.map.begin[x] + qx;
-  if (idx >= a.map.begin[x + 1]) return;
+  if (idx >= a.map.begin[x + 1] || idx == a.skip_task) return;
   if (a.stamps && threadIdx.x == 0) a.stamps[2 * idx] = wall_clock64();
   const Item it = uni(a.items[idx]);
   const ProductArgs pa = uni(a.prods ? a.prods[it.product] : a.single);
@@ -364,6 +363,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void tiles(TileArgs a) {
     __syncthreads();
     if (threadIdx.x == 0) a.stamps[2 * idx + 1] = wall_clock64();
   }
+  if (threadIdx.x == 0) count_task(a.done, idx);
 }
 
 // Launches of one precision form (instantiated once per form, in its own translation unit).

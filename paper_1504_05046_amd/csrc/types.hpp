@@ -74,14 +74,17 @@ struct Item {
 static_assert(sizeof(Item) == 32, "Item layout");
 
 // Operands of one product: A and B in the element type of the precision form (FP64 tiles, or
-// their FP32 / bf16-slice copies), C and the k-window partial sums P in FP64.
+// their FP32 / bf16-slice copies), C in FP64 or FP32 (c_f32) and the k-window partial sums P in
+// FP64.
 struct ProductArgs {
   const void* A;
   const void* B;
-  double* C;
+  void* C;
   double* P;
   double alpha;
   int64_t a_plane, b_plane;  // split-bf16 form: elements between consecutive slice planes
+  int32_t c_f32;             // 1: C holds FP32 elements
+  int32_t pad_;
 };
 
 }  // namespace bsm

@@ -50,7 +50,25 @@ __device__ inline ProductArgs uni(const ProductArgs& p) {
   r.alpha = __builtin_bit_cast(double, uni(__builtin_bit_cast(uint64_t, p.alpha)));
   r.a_plane = int64_t(uni(uint64_t(p.a_plane)));
   r.b_plane = int64_t(uni(uint64_t(p.b_plane)));
+  r.c_f32 = uni(p.c_f32);
+  r.pad_ = 0;
   return r;
+}
+
+// The epilogue's store of one C element: alpha * sum (+ the previous C), rounded once to C's type.
+__device__ inline void store_c(const ProductArgs& pa, int64_t e, double v, int accumulate) {
+  if (pa.c_f32) {
+    float* c = static_cast<float*>(pa.C);
+    c[e] = float(accumulate ? v + double(c[e]) : v);
+  } else {
+    double* c = static_cast<double*>(pa.C);
+    c[e] = accumulate ? v + c[e] : v;
+  }
+}
+
+// Marks task idx as executed once more (one lane; no return value, so nothing waits on it).
+__device__ inline void count_task(uint32_t* done, int idx) {
+  if (done) __hip_atomic_fetch_add(done + idx, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Triple q of a k-list through the scalar cache (the address is uniform): its wait counts

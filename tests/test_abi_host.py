@@ -223,3 +223,38 @@ def test_reschedule_does_not_depend_on_the_previous_order():
     flops = (2 * np.exp(f1[:, :3].astype(np.float64).sum(1))).astype(np.float32)
     plan.set_costs(flops)
     assert np.array_equal(plan.features(), f0)
+
+
+def test_options_validated():
+    ok_bits = gen.pack_bits(np.ones((1, 1), bool))
+    _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], ok_bits, ok_bits, out=2))
+    _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], ok_bits, ok_bits, order=9))
+    for order in (bsm.ORDER_DEFAULT, bsm.ORDER_INTERLEAVE, bsm.ORDER_LOCALITY, bsm.ORDER_LPT):
+        bsm.Plan([1], [1], [1], ok_bits, ok_bits, order=order).close()
+    plan = bsm.Plan([1], [1], [1], ok_bits, ok_bits, out=bsm.OUT_F32, tune_cache="/tmp/x")
+    assert plan.info().out == bsm.OUT_F32
+    # the binding wants an FP32 C for such a plan
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError, match="float32"):
+        plan.execute(torch.zeros(1, dtype=torch.float64), torch.zeros(1, dtype=torch.float64),
+                     torch.zeros(1, dtype=torch.float64))
+
+
+def test_reduced_precision_plan_only_once_per_batch():
+    p = gen.random_problem(44, 3, 3, 3, 1, 50, 0.8, 0.8)
+    a = bsm.Plan.from_problem(p)
+    bsm.Batch([a, a]).close()                 # FP64: each entry is its own product
+    for prec in (bsm.FP32, bsm.BF16X3):
+        b = bsm.Plan.from_problem(p, precision=prec)
+        msg = _expect(bsm.E_INVALID, lambda: bsm.Batch([b, b]))
+        assert "repeats" in msg
+
+
+def test_debug_skip_task_validated():
+    p = gen.random_problem(45, 3, 3, 3, 1, 50, 0.8, 0.8)
+    plan = bsm.Plan.from_problem(p)
+    n = plan.info().tasks
+    plan.debug_skip_task(n - 1)
+    plan.debug_skip_task(-1)
+    _expect(bsm.E_INVALID, lambda: plan.debug_skip_task(n))
+    _expect(bsm.E_INVALID, lambda: plan.debug_skip_task(-2))

@@ -131,10 +131,10 @@ def test_costs_reschedule_without_changing_bits():
         assert np.array_equal(C.cpu().numpy(), base)
 
 
-def test_autotune_picks_a_variant_and_stays_correct(tmp_path, monkeypatch):
-    monkeypatch.setenv("BSM_TUNE_CACHE", str(tmp_path / "tune.txt"))
+def test_autotune_picks_a_variant_and_stays_correct(tmp_path):
+    cache = str(tmp_path / "tune.txt")
     probs = small_batch(21, count=4)
-    plans = [bsm.Plan.from_problem(p) for p in probs]
+    plans = [bsm.Plan.from_problem(p, tune_cache=cache) for p in probs]
     batch = bsm.Batch(plans)
     As, Bs, Cs = operands(probs, plans)
     v = batch.autotune(As, Bs, Cs)
@@ -149,7 +149,7 @@ def test_autotune_picks_a_variant_and_stays_correct(tmp_path, monkeypatch):
     assert batch.autotune(As, Bs, Cs) == v
     # single-plan autotune
     p = probs[0]
-    plan = bsm.Plan.from_problem(p)
+    plan = bsm.Plan.from_problem(p, tune_cache=cache)
     C = torch.zeros(plan.info().c_elems, dtype=torch.float64, device=DEV)
     w = plan.autotune(As[0], Bs[0], C)
     assert plan.info().tile == w
@@ -167,3 +167,16 @@ def test_batch_timings():
     f, t = batch.timings()
     assert f.shape == (batch.query()[0], 5)
     assert np.all(t > 0)
+
+
+def test_fp64_plan_twice_in_a_batch():
+    """An FP64 plan may stand for two products of one batch (same structure, different operands)."""
+    p = gen.random_problem(1400, 6, 6, 6, 16, 180, 0.5, 0.5)
+    q = gen.random_problem(1400, 6, 6, 6, 16, 180, 0.5, 0.5, draw=lambda rng, i, j, h, w: rng.uniform(-2, 2, (h, w)))
+    plan = bsm.Plan.from_problem(p)
+    batch = bsm.Batch([plan, plan])
+    As, Bs, Cs = operands([p, q], [plan, plan])
+    batch.execute(As, Bs, Cs, alphas=[1.0, -2.0])
+    batch.verify()
+    assert rel_fro(host(Cs[0], plan), ref(p)) <= 1e-12
+    assert rel_fro(host(Cs[1], plan), ref(q, -2.0)) <= 1e-12

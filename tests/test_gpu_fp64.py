@@ -91,13 +91,11 @@ def test_every_tile_variant(tile):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("order", ["0", "1"])
-def test_task_orders_bitwise_identical(order, monkeypatch):
+@pytest.mark.parametrize("order", [bsm.ORDER_LOCALITY, bsm.ORDER_LPT, bsm.ORDER_INTERLEAVE])
+def test_task_orders_bitwise_identical(order):
     p = gen.random_problem(300, 8, 8, 8, 20, 200, 0.5, 0.5)
-    monkeypatch.setenv("BSM_ORDER", "0")
     a, _ = run_gpu(p)
-    monkeypatch.setenv("BSM_ORDER", order)
-    b, _ = run_gpu(p)
+    b, _ = run_gpu(p, order=order)
     assert np.array_equal(a, b)
 
 
@@ -181,3 +179,86 @@ def _sampled_check(p: gen.Problem, nsample: int, seed: int, **kw):
 
 def test_nonuniform_16384_sampled():
     _sampled_check(gen.nonuniform_16384(), nsample=64, seed=1)
+
+
+def _int_draw(rng, i, j, h, w):
+    return rng.integers(-8, 9, (h, w)).astype(np.float64)
+
+
+@pytest.mark.parametrize("precision", [bsm.FP64, bsm.FP32, bsm.BF16X3])
+def test_block_larger_than_2gib(precision):
+    """One B block of 16384 x 17000 FP64 elements (2.2 GB, byte offsets past 2^31) with integer
+    values in [-8, 8]: every form reproduces the oracle bit for bit (sums stay below 2^24)."""
+    _say(f"[big block] precision={precision}")
+    p = gen.make_problem("bigB", 77, [3, 2], [16384], [17000], np.ones((2, 1), bool),
+                         np.ones((1, 1), bool), draw=_int_draw)
+    got, plan = run_gpu(p, precision=precision)
+    plan.verify()
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    assert np.array_equal(got, ref)
+
+
+def _run_f32_out(p, precision, alpha=1.0, C0=None, **kw):
+    plan = bsm.Plan.from_problem(p, precision=precision, out=bsm.OUT_F32, **kw)
+    info = plan.info()
+    assert info.out == bsm.OUT_F32
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(p.a_data).to(dev)
+    B = A if p.b_is_a else torch.from_numpy(p.b_data).to(dev)
+    C = (torch.full((max(1, info.c_elems),), float("nan"), dtype=torch.float32, device=dev)
+         if C0 is None else torch.from_numpy(C0.copy()).to(dev))
+    plan.execute(A, B, C, alpha=alpha, accumulate=C0 is not None)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()[:info.c_elems]
+
+
+@pytest.mark.parametrize("precision", [bsm.FP64, bsm.FP32, bsm.BF16X3])
+def test_fp32_output(precision):
+    """C in FP32: alpha * sum (+ C) is formed in FP64 and rounded once."""
+    _say(f"[fp32 out] precision={precision}")
+    p = gen.random_problem(1900 + precision, 7, 8, 6, 1, 200, 0.5, 0.5)
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data, -0.75)
+    got = _run_f32_out(p, precision, alpha=-0.75)
+    assert got.dtype == np.float32 and np.all(np.isfinite(got))
+    gate = {bsm.FP64: 1e-12, bsm.FP32: 1e-5, bsm.BF16X3: 1e-6}[precision]
+    # the FP32 rounding of C adds at most 2^-24 relative per element
+    assert np.all(np.abs(got.astype(np.float64) - ref) <= 2.0 ** -24 * np.abs(ref) + gate * np.abs(ref).max())
+    # integers: exact, also with accumulation into an FP32 C and k-windows
+    q = gen.integer_problem(1950 + precision, 6, 7, 5, 1, 150, 0.6, 0.6)
+    refq = oracle.bsmm(q.rows, q.inner, q.cols, q.a_bits(), q.b_bits(), q.a_data, q.b_data)
+    assert np.array_equal(_run_f32_out(q, precision), refq.astype(np.float32))
+    C0 = np.random.default_rng(3).integers(-100, 100, refq.size).astype(np.float32)
+    want = (2.0 * refq + C0.astype(np.float64)).astype(np.float32)
+    assert np.array_equal(_run_f32_out(q, precision, alpha=2.0, C0=C0, k_window=2), want)
+
+
+def test_execution_counters_catch_a_skipped_task():
+    """Every launch counts each task's executions; a task left out by the host-set fault-injection
+    flag makes the synchronising checks fail with E_STATE, and the kernel still exits normally."""
+    p = gen.random_problem(1990, 6, 6, 6, 16, 200, 0.6, 0.6)
+    for use_graph in (0, 1):
+        plan = bsm.Plan.from_problem(p, use_graph=use_graph, record_timings=1)
+        dev = torch.device("cuda:0")
+        A = torch.from_numpy(p.a_data).to(dev)
+        B = torch.from_numpy(p.b_data).to(dev)
+        C = torch.zeros(plan.info().c_elems, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            plan.execute(A, B, C)
+        plan.verify()
+        plan.timings()
+        plan.debug_skip_task(2)
+        plan.execute(A, B, C)
+        with pytest.raises(bsm.BsmError) as ei:
+            plan.verify()
+        assert ei.value.code == bsm.E_STATE and "task 2" in str(ei.value)
+        with pytest.raises(bsm.BsmError) as ei:
+            plan.timings()
+        assert ei.value.code == bsm.E_STATE
+        # a new schedule uploads the tasks again and restarts the counts
+        plan.debug_skip_task(-1)
+        plan.set_costs(np.ones(plan.info().tasks, np.float32))
+        plan.execute(A, B, C)
+        plan.verify()
+        torch.cuda.synchronize()
+        ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+        assert rel_fro(C.cpu().numpy(), ref) <= 1e-12
