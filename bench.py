@@ -1,13 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark: useful TFLOP/s of the block-sparse multiply on one MI355X.
 
-Default workload: N = 16384, row/inner/col block sizes drawn from U{32..256} (last block takes the
-remainder), Bernoulli(0.3) block shapes for A and B, N(0,1) FP64 values, C = A*B.  One step = one
-execution of the planned multiply (every task of every k-iteration, one launch) on inputs that
-already sit in HBM; the plan (host: validation, C-shape, packing, tasks, order) is built once and
-reported separately as plan_ms.
+Headline workload (`value`): N = 16384, row/inner/col block sizes drawn from U{32..256} (last block
+takes the remainder), Bernoulli(0.3) block shapes for A and B, N(0,1) FP64 values, C = A*B.  One
+step = one execution of the planned FP64 multiply (every task of every k-iteration, one graph
+replay) on inputs that already sit in HBM; the plan (host: validation, C-shape, packing, tasks,
+order) is built once and reported separately as plan_ms.
 
-Prints ONE JSON line.  --gpus above 1 is refused: this build measures one GPU.
+Beside it, in the same JSON line:
+  schedules       flop-count vs learned task order on the headline workload, n = 30 interleaved
+                  launches each (mean, sd); the headline uses the learned order only when it is
+                  faster by more than three standard errors of the difference
+  split_bf16/fp32 the same workload in the split-bf16 and FP32 forms (conversion pass included)
+  precision_32768 N = 32768, sizes U{64..256}, Bernoulli(0.4), N(0,1) * 10^U(-4,0) per block:
+                  FP64, FP32 and split-bf16 throughput and each form's relative Frobenius error
+                  over ALL C blocks against the oracle's full product
+  batch64         64 independent products (N in {1024..8192}, sizes U{16..192}, density U[0.1,0.9])
+                  in one graph launch: total useful TFLOP/s and sampled per-product error
+  uniform_1024    N = 1024, 64 x 64 blocks, Bernoulli(0.5): latency of one graph replay
+  roofline        the headline FP64 tile kernel against the FP64 MFMA peak
+  cpu_baseline    the oracle on the host cores, on a sample of the headline workload's C blocks
+
+Prints ONE JSON line on stdout (progress goes to stderr).  --gpus above 1 is refused: this build
+measures one GPU.
 """
 from __future__ import annotations
 
@@ -27,6 +42,7 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 MFMA (datasheet)
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 MFMA (datasheet)
 FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 MFMA (datasheet)
 HBM_PEAK_GBS = 8000.0
+GATES = {"fp64": 1e-12, "fp32": 1e-5, "split_bf16": 1e-6}
 
 WORKLOADS = {
     "nonuniform_16384": ("N=16384, block sizes U{32..256} (last = remainder), Bernoulli(0.3) "
@@ -34,7 +50,13 @@ WORKLOADS = {
     "uniform_1024": "N=1024, 16x16 blocks of 64, Bernoulli(0.5) shapes, U[-1,1] FP64 values",
     "precision_32768": ("N=32768, block sizes U{64..256}, Bernoulli(0.4) shapes, N(0,1) values "
                         "scaled per block by 10^U(-4,0), C = A*B"),
+    "batch64": ("64 products, N in {1024,2048,4096,8192}, block sizes U{16..192}, density "
+                "U[0.1,0.9] per product, N(0,1) FP64 values, one graph launch"),
 }
+
+
+def say(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def make_workload(name):
@@ -46,6 +68,12 @@ def make_workload(name):
     if name == "precision_32768":
         return gen.precision_32768()
     raise SystemExit(f"unknown workload {name}")
+
+
+def to_device(p, torch, dev):
+    A = torch.from_numpy(p.a_data).to(dev)
+    B = A if p.b_is_a else torch.from_numpy(p.b_data).to(dev)
+    return A, B
 
 
 def time_plan(plan, A, B, C, steps, warmup, stream, torch):
@@ -64,6 +92,22 @@ def time_plan(plan, A, B, C, steps, warmup, stream, torch):
     wall = (time.perf_counter() - t0) / steps * 1e3
     ev = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     return wall, float(np.mean(ev)), float(np.std(ev))
+
+
+def interleaved(plans, A, B, C, reps, stream, torch):
+    """Event times (ms) of `reps` rounds in which every plan runs once, in turn."""
+    for pl in plans:
+        pl.execute(A, B, C, stream=stream)
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)] for _ in plans]
+    for r in range(reps):
+        for q, pl in enumerate(plans):
+            ev[q][r][0].record(stream)
+            pl.execute(A, B, C, stream=stream)
+            ev[q][r][1].record(stream)
+    torch.cuda.synchronize()
+    return [np.array([a.elapsed_time(b) for a, b in row]) for row in ev]
 
 
 def recorded_traffic():
@@ -95,6 +139,8 @@ def sampled_error(p, got_c, c_off, nsample=48, seed=7):
     """Relative Frobenius error of a random sample of C blocks against the oracle."""
     import oracle
     present = np.argwhere(c_off >= 0)
+    if len(present) == 0:
+        return 0.0
     rng = np.random.default_rng(seed)
     pick = rng.choice(len(present), min(nsample, len(present)), replace=False)
     sel = [tuple(int(v) for v in present[q]) for q in pick]
@@ -106,7 +152,19 @@ def sampled_error(p, got_c, c_off, nsample=48, seed=7):
         g = got_c[o:o + blk.size].reshape(blk.shape)
         num += float(np.sum((g - blk) ** 2))
         den += float(np.sum(blk ** 2))
-    return (num / den) ** 0.5 if den > 0 else 0.0
+    return (num / den) ** 0.5 if den > 0 else num ** 0.5
+
+
+def rel_fro_chunked(got, ref, chunk=1 << 26):
+    """||got - ref||_F / ||ref||_F over two long vectors, in chunks (bounded temporaries)."""
+    num = den = 0.0
+    for s in range(0, ref.size, chunk):
+        g = got[s:s + chunk]
+        r = ref[s:s + chunk]
+        d = g - r
+        num += float(np.dot(d, d))
+        den += float(np.dot(r, r))
+    return (num / den) ** 0.5 if den > 0 else num ** 0.5
 
 
 def cpu_baseline(p, got_c, c_off, target_s: float, seed: int = 12345):
@@ -151,17 +209,226 @@ def cpu_baseline(p, got_c, c_off, target_s: float, seed: int = 12345):
     }, (num / den) ** 0.5 if den > 0 else 0.0
 
 
+# ---- sections ------------------------------------------------------------------------------------
+def schedules_ab(p, plan_f, A, B, C, stream, torch, bsm, reps):
+    """Learned vs flop-count task order on the same product: train the cost model on timings the
+    multiply records, re-bin a second plan by its predictions, then time both plans interleaved."""
+    t0 = time.perf_counter()
+    timed = bsm.Plan.from_problem(p, record_timings=1)
+    feats, secs = [], []
+    for _ in range(2):
+        timed.execute(A, B, C, stream=stream)
+        f, t = timed.timings(stream=stream)
+        feats.append(f)
+        secs.append(t)
+    timed.close()
+    X = np.concatenate(feats)
+    T = np.log(np.maximum(np.concatenate(secs), 1e-7)).astype(np.float32)
+    model = bsm.CostModel(seed=1)
+    loss = model.train(X, T, epochs=60, batch=2048, lr=3e-3, stream=stream)
+    plan_l = bsm.Plan.from_problem(p, use_graph=1)
+    plan_l.set_costmodel(model, stream=stream)
+    train_s = time.perf_counter() - t0
+    ev_f, ev_l = interleaved([plan_f, plan_l], A, B, C, reps, stream, torch)
+    diff = ev_l - ev_f
+    se = float(np.std(diff, ddof=1) / np.sqrt(reps))
+    flops = plan_f.info().useful_flops
+    out = {
+        "n": reps, "order": "interleaved launches, HIP events",
+        "flop_count_ms_mean": round(float(ev_f.mean()), 4), "flop_count_ms_sd": round(float(ev_f.std(ddof=1)), 4),
+        "learned_ms_mean": round(float(ev_l.mean()), 4), "learned_ms_sd": round(float(ev_l.std(ddof=1)), 4),
+        "learned_minus_flop_ms": round(float(diff.mean()), 4), "diff_standard_error_ms": round(se, 4),
+        "flop_count_tflops": round(flops / (ev_f.mean() * 1e-3) / 1e12, 3),
+        "learned_tflops": round(flops / (ev_l.mean() * 1e-3) / 1e12, 3),
+        "train_s": round(train_s, 2), "train_loss": round(loss, 4), "samples": int(T.size),
+    }
+    learned_wins = diff.mean() < -3.0 * se
+    out["headline"] = "learned cost model" if learned_wins else "flop count"
+    return out, (plan_l if learned_wins else plan_f), model
+
+
+def forms_section(p, A, B, steps, warmup, stream, torch, bsm, dev, c_elems, ref_wall_ms):
+    """The headline workload in the split-bf16 and FP32 forms (graph replay, conversion included)."""
+    out, results = {}, {}
+    flops = None
+    for key, prec, peak, mult in (("split_bf16", bsm.BF16X3, BF16_PEAK_TFLOPS, 6),
+                                  ("fp32", bsm.FP32, FP32_PEAK_TFLOPS, 1)):
+        plan = bsm.Plan.from_problem(p, precision=prec, use_graph=1)
+        flops = plan.info().useful_flops
+        C = torch.zeros(max(1, c_elems), dtype=torch.float64, device=dev)
+        w, e, _ = time_plan(plan, A, B, C, steps, warmup, stream, torch)
+        out[key] = {
+            "value": round(flops / (w * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+            "ms_per_step": round(w, 4), "launch_ms": round(e, 4),
+            "vs_fp64": round(ref_wall_ms / w, 3),
+            "mfma_frac": round(mult * flops / (e * 1e-3) / 1e12 / peak, 4),
+        }
+        if mult > 1:
+            out[key]["note"] = "useful flops only; the six slice products per block product are 6x the MFMA work"
+        results[key] = C
+        plan.close()
+    return out, results
+
+
+def precision_section(torch, bsm, dev, stream, steps=5, warmup=2):
+    """Config 4: the three forms on N = 32768 with per-block scaled values; every form's relative
+    Frobenius error over all C blocks against the oracle's full product."""
+    import oracle
+    from paper_1504_05046_amd import gen
+    say("precision_32768: generating inputs")
+    t0 = time.perf_counter()
+    p = gen.precision_32768()
+    gen_s = time.perf_counter() - t0
+    A, B = to_device(p, torch, dev)
+    sec = {"workload": f"precision_32768: {WORKLOADS['precision_32768']}", "gen_s": round(gen_s, 1)}
+    got = {}
+    wall64 = None
+    for key, prec, peak, mult in (("fp64", bsm.FP64, FP64_PEAK_TFLOPS, 1),
+                                  ("fp32", bsm.FP32, FP32_PEAK_TFLOPS, 1),
+                                  ("split_bf16", bsm.BF16X3, BF16_PEAK_TFLOPS, 6)):
+        say(f"precision_32768: {key}")
+        plan = bsm.Plan.from_problem(p, precision=prec, use_graph=1)
+        info = plan.info()
+        C = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
+        w, e, sd = time_plan(plan, A, B, C, steps, warmup, stream, torch)
+        plan.verify(stream=stream)
+        flops = info.useful_flops
+        if key == "fp64":
+            wall64 = w
+            sec.update({"useful_gflop": round(flops / 1e9, 1), "c_blocks": info.c_blocks,
+                        "triples": info.triples, "tasks": info.tasks})
+        sec[key] = {"value": round(flops / (w * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+                    "ms_per_step": round(w, 3), "launch_ms": round(e, 3), "launch_ms_sd": round(sd, 3),
+                    "mfma_frac": round(mult * flops / (e * 1e-3) / 1e12 / peak, 4),
+                    "vs_fp64": round(wall64 / w, 3)}
+        got[key] = C.cpu().numpy()[:info.c_elems]
+        if key == "fp64":
+            offsets = plan.c_offsets()
+        del C
+        plan.close()
+    del A, B
+    torch.cuda.empty_cache()
+    # the oracle over every C block, a band of C-block rows at a time; each band is compared with
+    # every form's result as soon as it is computed
+    c_off = offsets
+    rows = p.M
+    band = max(1, rows // 10)
+    num = {k: 0.0 for k in got}
+    den = 0.0
+    t0 = time.perf_counter()
+    for r0 in range(0, rows, band):
+        sel = [(int(i), int(j)) for i, j in np.argwhere(c_off[r0:r0 + band] >= 0) + np.array([r0, 0])]
+        blocks, _ = oracle.bsmm_blocks(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data,
+                                       p.b_data, sel)
+        for (i, j), blk in zip(sel, blocks):
+            o = int(c_off[i, j])
+            r = blk.reshape(-1)
+            den += float(np.dot(r, r))
+            for k, g in got.items():
+                d = g[o:o + r.size] - r
+                num[k] += float(np.dot(d, d))
+        say(f"precision_32768: oracle rows {r0}..{min(rows, r0 + band) - 1} of {rows} "
+            f"({time.perf_counter() - t0:.0f} s)")
+    osec = time.perf_counter() - t0
+    sec["oracle"] = {"seconds": round(osec, 1), "threads": oracle.threads(),
+                     "tflops": round(sec["useful_gflop"] / 1e3 / osec, 4)}
+    for key in got:
+        err = (num[key] / den) ** 0.5 if den > 0 else num[key] ** 0.5
+        sec[key]["rel_err"] = err
+        sec[key]["gate"] = GATES[key]
+        sec[key]["within_gate"] = bool(err <= GATES[key])
+    sec["error"] = "relative Frobenius norm over all C blocks vs the oracle's FP64 full product"
+    return sec
+
+
+def batch_section(torch, bsm, dev, stream, steps=5, warmup=2, nsample=8):
+    """Config 3: 64 products in one graph-captured launch (tile variant autotuned over the batch)."""
+    from paper_1504_05046_amd import gen
+    say("batch64: generating inputs")
+    t0 = time.perf_counter()
+    probs = gen.batch64()
+    gen_s = time.perf_counter() - t0
+    plans = [bsm.Plan.from_problem(p) for p in probs]
+    batch = bsm.Batch(plans)
+    As, Bs, Cs = [], [], []
+    for p, pl in zip(probs, plans):
+        A, B = to_device(p, torch, dev)
+        As.append(A)
+        Bs.append(B)
+        Cs.append(torch.zeros(max(1, pl.info().c_elems), dtype=torch.float64, device=dev))
+    say("batch64: autotune")
+    t0 = time.perf_counter()
+    tile = batch.autotune(As, Bs, Cs, stream=stream)
+    tune_s = time.perf_counter() - t0
+    tasks, flops, _ = batch.query()
+    for _ in range(warmup):
+        batch.execute(As, Bs, Cs, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        batch.execute(As, Bs, Cs, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    launch = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    batch.verify(stream=stream)
+    say("batch64: sampled oracle check")
+    errs = []
+    for q, (p, pl, C) in enumerate(zip(probs, plans, Cs)):
+        got = C.cpu().numpy()[:pl.info().c_elems]
+        errs.append(sampled_error(p, got, pl.c_offsets(), nsample=nsample, seed=q))
+    sizes = sorted({int(p.rows.sum()) for p in probs})
+    return {
+        "workload": f"batch64: {WORKLOADS['batch64']}", "products": len(probs),
+        "sizes": {str(n): sum(1 for p in probs if int(p.rows.sum()) == n) for n in sizes},
+        "useful_gflop": round(flops / 1e9, 1), "tasks": tasks, "tile": tile,
+        "value": round(flops / (wall * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+        "ms_per_step": round(wall, 3), "launch_ms": round(launch, 3),
+        "mfma_frac": round(flops / (launch * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        "max_sampled_rel_err": max(errs), "gate": GATES["fp64"],
+        "error": f"per product, {nsample} random C blocks vs the oracle",
+        "gen_s": round(gen_s, 1), "autotune_s": round(tune_s, 1), "launch": "one hipGraph replay",
+    }
+
+
+def latency_section(torch, bsm, dev, stream, steps=50, warmup=5):
+    """Config 1: the small uniform product, launch-bound; full-product error."""
+    import oracle
+    from paper_1504_05046_amd import gen
+    p = gen.uniform_1024()
+    plan = bsm.Plan.from_problem(p, use_graph=1)
+    info = plan.info()
+    A, B = to_device(p, torch, dev)
+    C = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
+    w, e, sd = time_plan(plan, A, B, C, steps, warmup, stream, torch)
+    got = C.cpu().numpy()[:info.c_elems]
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    return {
+        "workload": f"uniform_1024: {WORKLOADS['uniform_1024']}",
+        "useful_gflop": round(info.useful_flops / 1e9, 3), "tasks": info.tasks,
+        "us_per_step": round(w * 1e3, 1), "launch_us": round(e * 1e3, 1), "launch_us_sd": round(sd * 1e3, 1),
+        "value": round(info.useful_flops / (w * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+        "rel_err": rel_fro_chunked(got, ref), "gate": GATES["fp64"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="nonuniform_16384", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="nonuniform_16384",
+                    choices=["nonuniform_16384", "uniform_1024", "precision_32768"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-split-bf16", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the split-bf16 and FP32 forms")
     ap.add_argument("--no-learned", action="store_true", help="flop-count schedule only")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-form measurement")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-precision", action="store_true", help="skip the N=32768 precision section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-product batch section")
+    ap.add_argument("--no-latency", action="store_true", help="skip the N=1024 latency section")
+    ap.add_argument("--ab-reps", type=int, default=30)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", type=int, default=0, help="0 = library choice, else variant id + 1")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -173,50 +440,29 @@ def main():
     from paper_1504_05046_amd import bsm
 
     dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    say(f"{args.workload}: generating inputs")
     p = make_workload(args.workload)
     t0 = time.perf_counter()
     plan = bsm.Plan.from_problem(p, tile=args.tile, use_graph=1)
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
-    A = torch.from_numpy(p.a_data).to(dev)
-    B = A if p.b_is_a else torch.from_numpy(p.b_data).to(dev)
+    A, B = to_device(p, torch, dev)
     C = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
     flops = info.useful_flops
 
-    # flop-count schedule (graph-replayed launch)
-    flop_wall, flop_ev, flop_sd = time_plan(plan, A, B, C, args.steps, args.warmup, stream, torch)
-    sched = {"flop_count_tflops": round(flops / (flop_wall * 1e-3) / 1e12, 3)}
-    best = ("flop count", flop_wall, flop_ev, flop_sd)
+    sched = {"headline": "flop count"}
+    head = plan
     if not args.no_learned:
-        # learned schedule: record per-task timings, train the cost model on the device, re-bin
-        t0 = time.perf_counter()
-        timed = bsm.Plan.from_problem(p, tile=args.tile, record_timings=1)
-        feats, secs = [], []
-        for _ in range(2):
-            timed.execute(A, B, C, stream=stream)
-            f, t = timed.timings(stream=stream)
-            feats.append(f)
-            secs.append(t)
-        timed.close()
-        X = np.concatenate(feats)
-        T = np.log(np.maximum(np.concatenate(secs), 1e-7)).astype(np.float32)
-        model = bsm.CostModel(seed=1)
-        loss = model.train(X, T, epochs=60, batch=2048, lr=3e-3, stream=stream)
-        plan.set_costmodel(model, stream=stream)
-        sched["train_s"] = round(time.perf_counter() - t0, 2)
-        sched["train_loss"] = round(loss, 4)
-        sched["samples"] = int(T.size)
-        l_wall, l_ev, l_sd = time_plan(plan, A, B, C, args.steps, args.warmup, stream, torch)
-        sched["learned_tflops"] = round(flops / (l_wall * 1e-3) / 1e12, 3)
-        if l_wall < flop_wall:
-            best = ("learned cost model", l_wall, l_ev, l_sd)
-    # the library offers both schedules; the step is timed with the faster one (both reported)
-    sched_name, wall_ms, kern_avg, kern_sd = best
+        say("schedules: learned vs flop count, interleaved")
+        sched, head, _ = schedules_ab(p, plan, A, B, C, stream, torch, bsm, args.ab_reps)
+
+    # the timed region: K steps of the headline schedule
+    say(f"timed region: {args.steps} steps ({sched['headline']})")
+    wall_ms, kern_avg, kern_sd = time_plan(head, A, B, C, args.steps, args.warmup, stream, torch)
+    head.verify(stream=stream)
     value = flops / (wall_ms * 1e-3) / 1e12
     achieved = flops / (kern_avg * 1e-3) / 1e12
-    traffic = recorded_traffic()
-
     result = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -234,51 +480,39 @@ def main():
                    "precision": "fp64", "useful_gflop": round(flops / 1e9, 3),
                    "c_blocks": info.c_blocks, "triples": info.triples, "tasks": info.tasks,
                    "tile": info.tile, "launch": "hipGraph replay",
-                   "schedule": sched_name,
-                   "plan_ms": round(plan_ms, 1)},
+                   "schedule": sched["headline"], "plan_ms": round(plan_ms, 1)},
         "schedules": sched,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": traffic, "kernel": "tiles (FP64 form)", "kernel_ms": round(kern_avg, 4),
+                     "traffic": recorded_traffic() if args.workload == "nonuniform_16384" else None,
+                     "kernel": "tiles (FP64 form)", "kernel_ms": round(kern_avg, 4),
                      "kernel_ms_sd": round(kern_sd, 4)},
     }
-    C3 = None
-    if not args.no_split_bf16:
-        # the split-bf16 form on the same inputs: split pass + bf16 MFMA tile kernel per step
-        plan3 = bsm.Plan.from_problem(p, precision=bsm.BF16X3)
-        C3 = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
-        w3, e3, sd3 = time_plan(plan3, A, B, C3, args.steps, args.warmup, stream, torch)
-        result["split_bf16"] = {
-            "value": round(flops / (w3 * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
-            "ms_per_step": round(w3, 4), "launch_ms": round(e3, 4),
-            "vs_fp64": round(wall_ms / w3, 3),
-            "mfma_frac": round(6 * flops / (e3 * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
-            "note": "useful flops only; the six slice products per block product are 6x the MFMA work",
-        }
-    C32 = None
-    if not args.no_fp32:
-        # the FP32 form on the same inputs: conversion pass + FP32 MFMA tile kernel per step
-        plan32 = bsm.Plan.from_problem(p, precision=bsm.FP32, use_graph=1)
-        C32 = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
-        w32, e32, _ = time_plan(plan32, A, B, C32, args.steps, args.warmup, stream, torch)
-        result["fp32"] = {
-            "value": round(flops / (w32 * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
-            "ms_per_step": round(w32, 4), "launch_ms": round(e32, 4),
-            "vs_fp64": round(wall_ms / w32, 3),
-            "mfma_frac": round(flops / (e32 * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
-        }
+    forms_c = {}
+    if not args.no_forms:
+        say("forms: split-bf16 and FP32 on the headline workload")
+        fs, forms_c = forms_section(p, A, B, args.steps, args.warmup, stream, torch, bsm, dev,
+                                    info.c_elems, wall_ms)
+        result.update(fs)
     if not args.no_cpu_baseline:
+        say("cpu baseline: oracle on a sample of C blocks")
         got = C.cpu().numpy()[:info.c_elems]
         c_off = plan.c_offsets()
         cb, err = cpu_baseline(p, got, c_off, args.cpu_seconds)
         result["cpu_baseline"] = cb
         result["sample_rel_err"] = err
-        if C3 is not None:
-            got3 = C3.cpu().numpy()[:info.c_elems]
-            result["split_bf16"]["sample_rel_err"] = sampled_error(p, got3, c_off)
-        if C32 is not None:
-            got32 = C32.cpu().numpy()[:info.c_elems]
-            result["fp32"]["sample_rel_err"] = sampled_error(p, got32, c_off)
+        for key, Cf in forms_c.items():
+            result[key]["sample_rel_err"] = sampled_error(p, Cf.cpu().numpy()[:info.c_elems], c_off)
+    del A, B, C, forms_c
+    torch.cuda.empty_cache()
+    if not args.no_latency:
+        say("uniform_1024: latency")
+        result["uniform_1024"] = latency_section(torch, bsm, dev, stream)
+    if not args.no_batch:
+        result["batch64"] = batch_section(torch, bsm, dev, stream)
+        torch.cuda.empty_cache()
+    if not args.no_precision:
+        result["precision_32768"] = precision_section(torch, bsm, dev, stream)
     print(json.dumps(result), flush=True)
 
 
