@@ -156,6 +156,21 @@ bsm_status bsm_plan_c_offsets(const bsm_plan* plan, int64_t* c_offsets);
 bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
                        void* dC, int accumulate, void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same product as bsm_execute, with the same kernels
+ * and task order (so bitwise the same C), that allocates nothing.  Everything bsm_execute would
+ * allocate on the device -- task list, k-list triples, split tables, converted FP32 / bf16-slice
+ * operands, FP64 partial sums between k-windows -- is placed in one static device array of
+ * 64 MiB that each GPU the library runs on holds until the process ends; the tables are copied in
+ * from the plan's host copy at every call (queued on `stream`).  Nothing in it needs to start at
+ * zero.  Calls on one GPU share that array: calls on the same stream run one after the other,
+ * calls that overlap on different streams of one GPU race and give wrong results.  Execution
+ * counters and per-task clocks are not kept (bsm_plan_verify does not cover these calls), and the
+ * plan's graph option is ignored.  Errors: as bsm_execute; BSM_E_NOMEM (checked before any device
+ * work) if the plan needs more than the 64 MiB, with the size in bsm_last_error(). */
+bsm_status bsm_execute_static(const bsm_plan* plan, double alpha, const double* dA,
+                              const double* dB, void* dC, int accumulate, void* stream);
+
 /* Waits for `stream`, then checks that every task of the plan ran once per k-window of every
  * execute queued since the task list was last (re)uploaded.  BSM_E_STATE names the first task
  * that did not; BSM_E_HIP reports a device fault. */

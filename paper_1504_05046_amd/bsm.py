@@ -75,6 +75,7 @@ def load() -> ctypes.CDLL:
     L.bsm_plan_c_shape.argtypes = [_p, _p]
     L.bsm_plan_c_offsets.argtypes = [_p, _p]
     L.bsm_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
+    L.bsm_execute_static.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
     L.bsm_plan_verify.argtypes = [_p, _p]
     L.bsm_plan_debug_skip_task.argtypes = [_p, _i64]
     L.bsm_batch_verify.argtypes = [_p, _p]
@@ -107,7 +108,7 @@ def load() -> ctypes.CDLL:
     L.bsm_adam_step.argtypes = [_p, _p, _p, _p, _i64, _i64, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, _p]
     for name in ("bsm_plan_create", "bsm_plan_query", "bsm_plan_c_shape", "bsm_plan_c_offsets",
-                 "bsm_execute", "bsm_plan_verify", "bsm_plan_debug_skip_task", "bsm_batch_verify",
+                 "bsm_execute", "bsm_execute_static", "bsm_plan_verify", "bsm_plan_debug_skip_task", "bsm_batch_verify",
                  "bsm_plan_destroy", "bsm_plan_timings", "bsm_plan_features",
                  "bsm_plan_set_costs", "bsm_autotune", "bsm_batch_create", "bsm_batch_query",
                  "bsm_batch_execute", "bsm_batch_timings", "bsm_batch_set_costs",
@@ -248,6 +249,13 @@ class Plan:
         _check_operands(self.info(), A, B, C)
         _check(load().bsm_execute(self._h, float(alpha), _dev_ptr(A), _dev_ptr(B), _dev_ptr(C),
                                   int(bool(accumulate)), _stream_handle(stream)))
+
+    def execute_static(self, A, B, C, alpha: float = 1.0, accumulate: bool = False, stream=None):
+        """As execute, with every device buffer the library needs taken from its static scratch
+        (no allocation; calls that overlap on one GPU race)."""
+        _check_operands(self.info(), A, B, C)
+        _check(load().bsm_execute_static(self._h, float(alpha), _dev_ptr(A), _dev_ptr(B),
+                                         _dev_ptr(C), int(bool(accumulate)), _stream_handle(stream)))
 
     def verify(self, stream=None):
         """Wait for the stream; raise BsmError(E_STATE) unless every task ran once per launch."""

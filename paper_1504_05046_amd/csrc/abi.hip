@@ -7,6 +7,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -240,33 +241,39 @@ static bsm_status sync_tasks(bsm_plan* p, hipStream_t stream) {
   return BSM_OK;
 }
 
-// S6: operands in the precision form's element type and layout (queued on s).
-static bsm_status enqueue_convert(bsm_plan* p, const double* dA, const double* dB, hipStream_t s,
-                                  ProductArgs& pa) {
-  const HostPlan& h = p->hp;
+// S6: operands in the precision form's element type and layout (queued on s), written into opA
+// and opB (FP32 copies, or bf16 slice planes built with the split tables sa and sb).
+static bsm_status convert_into(const HostPlan& h, const double* dA, const double* dB, void* opA,
+                               void* opB, const SplitBlock* sa, const SplitBlock* sb, hipStream_t s,
+                               ProductArgs& pa) {
   pa.A = dA;
   pa.B = dB;
   pa.a_plane = pa.b_plane = 0;
   if (h.cfg.precision == BSM_FP32) {
-    BSM_HIP(launch_to_f32(dA, static_cast<float*>(p->d_opA), h.a_elems, s), "convert A");
-    pa.A = p->d_opA;
+    BSM_HIP(launch_to_f32(dA, static_cast<float*>(opA), h.a_elems, s), "convert A");
+    pa.A = opA;
     if (dB == dA && h.b_elems == h.a_elems) {
-      pa.B = p->d_opA;  // C = A A: one conversion
+      pa.B = opA;  // C = A A: one conversion
     } else {
-      BSM_HIP(launch_to_f32(dB, static_cast<float*>(p->d_opB), h.b_elems, s), "convert B");
-      pa.B = p->d_opB;
+      BSM_HIP(launch_to_f32(dB, static_cast<float*>(opB), h.b_elems, s), "convert B");
+      pa.B = opB;
     }
   } else if (h.cfg.precision == BSM_BF16X3) {
     pa.a_plane = h.a_elems32;
     pa.b_plane = h.b_elems32;
-    BSM_HIP(launch_split_bf16x3(p->d_split_a, int64_t(h.split_a.size()), dA,
-                                static_cast<uint16_t*>(p->d_opA), pa.a_plane, s), "split A");
-    BSM_HIP(launch_split_bf16x3(p->d_split_b, int64_t(h.split_b.size()), dB,
-                                static_cast<uint16_t*>(p->d_opB), pa.b_plane, s), "split B");
-    pa.A = p->d_opA;
-    pa.B = p->d_opB;
+    BSM_HIP(launch_split_bf16x3(sa, int64_t(h.split_a.size()), dA, static_cast<uint16_t*>(opA),
+                                pa.a_plane, s), "split A");
+    BSM_HIP(launch_split_bf16x3(sb, int64_t(h.split_b.size()), dB, static_cast<uint16_t*>(opB),
+                                pa.b_plane, s), "split B");
+    pa.A = opA;
+    pa.B = opB;
   }
   return BSM_OK;
+}
+
+static bsm_status enqueue_convert(bsm_plan* p, const double* dA, const double* dB, hipStream_t s,
+                                  ProductArgs& pa) {
+  return convert_into(p->hp, dA, dB, p->d_opA, p->d_opB, p->d_split_a, p->d_split_b, s, pa);
 }
 
 static hipError_t launch_form(int precision, int variant, int64_t grid, const TileArgs& a,
@@ -497,9 +504,115 @@ static bsm_status apply_model(HostPlan& h, bsm_costmodel* m, hipStream_t s) {
   return BSM_OK;
 }
 
+// ------------------------------------------------------------------------------------------------
+// Allocation-free execution.  bsm_execute_static places everything the plan would otherwise
+// allocate on the device -- the task list, the k-list triples, the split pass's block tables, the
+// converted operands of the FP32 / split-bf16 forms and the FP64 partial sums between k-windows --
+// in this one file-scope array, so that the call makes no allocation.  Each device holds its own
+// copy for the life of the process.  In host code `scratch` only names the symbol: its device
+// address comes from hipGetSymbolAddress, taken once per device (with that device current) and
+// kept in g_scratch.
+constexpr int64_t kStaticScratchBytes = int64_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices] = {};
+
+static bsm_status scratch_of(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(BSM_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    BSM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch[dev]);
+  return BSM_OK;
+}
+
+// Byte offsets of each buffer inside the static scratch (256-byte aligned); total = bytes used.
+struct StaticLayout {
+  int64_t items = 0, tri = 0, split_a = 0, split_b = 0, opA = 0, opB = 0, partial = 0, total = 0;
+};
+
+static StaticLayout static_layout(const HostPlan& h) {
+  StaticLayout L;
+  int64_t pos = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = pos;
+    pos += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  L.items = take(int64_t(h.items.size() * sizeof(Item)));
+  L.tri = take(int64_t(h.tri.size() * sizeof(Triple)));
+  if (h.cfg.precision == BSM_FP32) {
+    L.opA = take(h.a_elems * 4);
+    L.opB = take(h.b_elems * 4);
+  } else if (h.cfg.precision == BSM_BF16X3) {
+    L.split_a = take(int64_t(h.split_a.size() * sizeof(SplitBlock)));
+    L.split_b = take(int64_t(h.split_b.size() * sizeof(SplitBlock)));
+    L.opA = take(h.a_elems32 * 6);
+    L.opB = take(h.b_elems32 * 6);
+  }
+  if (h.windows > 1) L.partial = take(h.c_elems * 8);
+  L.total = pos;
+  return L;
+}
+
 extern "C" {
 
 const char* bsm_last_error(void) { return g_error.c_str(); }
+
+bsm_status bsm_execute_static(const bsm_plan* plan, double alpha, const double* dA,
+                              const double* dB, void* dC, int accumulate, void* stream) {
+  if (!plan) return fail(BSM_E_INVALID, "plan is null");
+  const HostPlan& h = plan->hp;
+  bsm_status st = check_operands(h, dA, dB, dC, accumulate);
+  if (st != BSM_OK) return st;
+  const StaticLayout L = static_layout(h);
+  if (L.total > kStaticScratchBytes)
+    return fail(BSM_E_NOMEM, "the plan needs " + std::to_string(L.total) +
+                                 " bytes of device scratch; bsm_execute_static has " +
+                                 std::to_string(kStaticScratchBytes));
+  if (h.items.empty()) return BSM_OK;
+  int dev;
+  if ((st = check_device(&dev)) != BSM_OK) return st;
+  unsigned char* base = nullptr;
+  if ((st = scratch_of(dev, &base)) != BSM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // tables into the scratch (queued behind any earlier call on this stream)
+  Item* items = reinterpret_cast<Item*>(base + L.items);
+  Triple* tri = reinterpret_cast<Triple*>(base + L.tri);
+  BSM_HIP(hipMemcpyAsync(items, h.items.data(), h.items.size() * sizeof(Item), hipMemcpyHostToDevice, s),
+          "hipMemcpyAsync(tasks)");
+  if (!h.tri.empty())
+    BSM_HIP(hipMemcpyAsync(tri, h.tri.data(), h.tri.size() * sizeof(Triple), hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync(triples)");
+  SplitBlock* sa = reinterpret_cast<SplitBlock*>(base + L.split_a);
+  SplitBlock* sb = reinterpret_cast<SplitBlock*>(base + L.split_b);
+  if (h.cfg.precision == BSM_BF16X3) {
+    if (!h.split_a.empty())
+      BSM_HIP(hipMemcpyAsync(sa, h.split_a.data(), h.split_a.size() * sizeof(SplitBlock),
+                             hipMemcpyHostToDevice, s), "hipMemcpyAsync(split table)");
+    if (!h.split_b.empty())
+      BSM_HIP(hipMemcpyAsync(sb, h.split_b.data(), h.split_b.size() * sizeof(SplitBlock),
+                             hipMemcpyHostToDevice, s), "hipMemcpyAsync(split table)");
+  }
+  ProductArgs pa{};
+  if ((st = convert_into(h, dA, dB, base + L.opA, base + L.opB, sa, sb, s, pa)) != BSM_OK) return st;
+  pa.C = dC;
+  pa.c_f32 = h.cfg.out_f32;
+  pa.P = h.windows > 1 ? reinterpret_cast<double*>(base + L.partial) : nullptr;
+  pa.alpha = alpha;
+  TaskSet ts;  // views into the scratch; no counters, no clocks
+  ts.items = items;
+  ts.tri = tri;
+  st = enqueue_tiles(h, ts, nullptr, pa, accumulate, -1, s);
+  ts.items = nullptr;  // not owned
+  ts.tri = nullptr;
+  return st;
+}
 
 void bsm_options_default(bsm_options* opt) {
   if (!opt) return;

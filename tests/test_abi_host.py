@@ -258,3 +258,15 @@ def test_debug_skip_task_validated():
     plan.debug_skip_task(-1)
     _expect(bsm.E_INVALID, lambda: plan.debug_skip_task(n))
     _expect(bsm.E_INVALID, lambda: plan.debug_skip_task(-2))
+
+
+def test_static_entry_rejects_plans_beyond_its_scratch():
+    """bsm_execute_static refuses, before any device work, a plan whose device buffers exceed its
+    64 MiB static scratch (here: FP32 copies of two 4096 x 4096 blocks)."""
+    bits = gen.pack_bits(np.ones((1, 1), bool))
+    plan = bsm.Plan([4096], [4096], [4096], bits, bits, precision=bsm.FP32)
+    L = bsm.load()
+    st = L.bsm_execute_static(plan.handle, 1.0, 1 << 32, 1 << 36, 1 << 40, 0, None)
+    assert st == bsm.E_NOMEM
+    assert "64" in L.bsm_last_error().decode() or "67108864" in L.bsm_last_error().decode()
+    assert L.bsm_execute_static(None, 1.0, 0, 0, 0, 0, None) == bsm.E_INVALID
