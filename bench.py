@@ -115,7 +115,7 @@ def recorded_traffic():
     rocprofv3 counter summary, if it was taken on the current kernel sources (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "tiles_f64_nonuniform_16384_traffic.md")
-    srcs = ["tile_impl.hpp", "kernels_tile_f64.hip", "types.hpp", "kernels.hpp", "wave_rects.inc",
+    srcs = ["tile_impl.hpp", "kernels_tile.hip", "tile_dispatch.hip", "types.hpp", "kernels.hpp", "wave_rects.inc",
             "uniform.hpp"]
     h = hashlib.sha256()
     for name in srcs:

@@ -1,13 +1,15 @@
 """Compile the HIP library (libbsm.so) for gfx950, in-tree.
 
 hipcc cross-compiles without a GPU.  Host-only planner sources are compiled with g++; the HIP
-sources (kernels and the C ABI) with hipcc; the objects are linked into one shared library next
-to this file.  Every build recompiles from scratch.
+sources (kernels and the C ABI) with hipcc, the FP64/FP32 tile kernel once per instantiation so
+that they compile in parallel; the objects are linked into one shared library next to this file.
+Every build recompiles from scratch.
 """
 from __future__ import annotations
 
 import glob
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -25,6 +27,17 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+
+
+TILE_UNIT = "kernels_tile.hip"
+
+
+def tile_variant_ids():
+    """Variant ids of the BSM_TILE_VARIANTS table in csrc/types.hpp."""
+    text = open(os.path.join(CSRC, "types.hpp")).read()
+    body = text[text.index("#define BSM_TILE_VARIANTS(X)"):]
+    body = body[:body.index("\n\n")]
+    return [int(m) for m in re.findall(r"X\((\d+),", body)]
 
 
 def _run(cmd):
@@ -45,8 +58,20 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         jobs.append((["g++"] + CXX_FLAGS + ["-c", src, "-o", obj], obj))
     for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        if os.path.basename(src) == TILE_UNIT:
+            continue
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         jobs.append(([HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj], obj))
+    # the FP64/FP32 tile kernel: one translation unit per (form, variant, window kind)
+    unit = os.path.join(CSRC, TILE_UNIT)
+    for form in (0, 1):
+        for vid in tile_variant_ids():
+            for resume in (0, 1):
+                obj = os.path.join(BUILD, f"tile_{form}_{vid}_{resume}.o")
+                defs = [f"-DBSM_UNIT_FORM={form}", f"-DBSM_UNIT_ID={vid}", f"-DBSM_UNIT_RESUME={resume}"]
+                jobs.append(([HIPCC] + HIP_FLAGS + defs + ["-c", unit, "-o", obj], obj))
+    # longest first: the tile units dominate
+    jobs.sort(key=lambda j: 0 if os.path.basename(j[1]).startswith("tile_") else 1)
     # translation units compile independently (the tile kernels dominate; one per form)
     workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     with ThreadPoolExecutor(max_workers=workers) as ex:

@@ -33,6 +33,17 @@ struct TileArgs {
 hipError_t launch_tiles_f64(int variant, int64_t grid, const TileArgs& args, hipStream_t stream);
 hipError_t launch_tiles_f32(int variant, int64_t grid, const TileArgs& args, hipStream_t stream);
 
+// The FP64/FP32 tile kernels are compiled one instantiation per translation unit
+// (kernels_tile.hip, built once per form F = FORM_F64 / FORM_F32, variant ID and window kind R =
+// 0 first / 1 later); each defines launch_tile_unit_<F>_<ID>_<R>.
+#define BSM_DECLARE_TILE_UNITS(ID, TM, TN, KC, NW, OCC)                                 \
+  hipError_t launch_tile_unit_0_##ID##_0(int64_t, const TileArgs&, hipStream_t);       \
+  hipError_t launch_tile_unit_0_##ID##_1(int64_t, const TileArgs&, hipStream_t);       \
+  hipError_t launch_tile_unit_1_##ID##_0(int64_t, const TileArgs&, hipStream_t);       \
+  hipError_t launch_tile_unit_1_##ID##_1(int64_t, const TileArgs&, hipStream_t);
+BSM_TILE_VARIANTS(BSM_DECLARE_TILE_UNITS)
+#undef BSM_DECLARE_TILE_UNITS
+
 // dst[i] = src[i] rounded to FP32 for i < n.
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t stream);
 

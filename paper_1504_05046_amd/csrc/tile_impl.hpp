@@ -366,25 +366,23 @@ __global__ __launch_bounds__(64 * NW, OCC) void tiles(TileArgs a) {
   if (threadIdx.x == 0) count_task(a.done, idx);
 }
 
-// Launches of one precision form (instantiated once per form, in its own translation unit).
-template <int FORM>
-hipError_t launch_tiles_form(int variant, int64_t grid, const TileArgs& args, hipStream_t stream) {
-  const uint32_t grid32 = static_cast<uint32_t>(grid);
-#define BSM_TILE_LAUNCH(ID, TM, TN, KC, NW, OCC)                                                  \
-  case ID:                                                                                        \
-    if (args.win_first)                                                                           \
-      hipLaunchKernelGGL((tiles<TM, TN, KC, NW, OCC, FORM, false>), dim3(grid32), dim3(64 * NW), 0, \
-                         stream, args);                                                           \
-    else                                                                                          \
-      hipLaunchKernelGGL((tiles<TM, TN, KC, NW, OCC, FORM, true>), dim3(grid32), dim3(64 * NW), 0,  \
-                         stream, args);                                                           \
-    break;
-  switch (variant) {
-    BSM_TILE_VARIANTS(BSM_TILE_LAUNCH)
-    default:
-      return hipErrorInvalidValue;
-  }
-#undef BSM_TILE_LAUNCH
+// One tile-kernel instantiation: variant row ID of BSM_TILE_VARIANTS, precision form FORM,
+// first window (RESUME = false) or a later one.
+template <int ID>
+struct VariantRow;
+#define BSM_VARIANT_ROW_TRAITS(ID_, TM_, TN_, KC_, NW_, OCC_)                          \
+  template <>                                                                        \
+  struct VariantRow<ID_> {                                                           \
+    static constexpr int TM = TM_, TN = TN_, KC = KC_, NW = NW_, OCC = OCC_;         \
+  };
+BSM_TILE_VARIANTS(BSM_VARIANT_ROW_TRAITS)
+#undef BSM_VARIANT_ROW_TRAITS
+
+template <int ID, int FORM, bool RESUME>
+hipError_t launch_tile_instance(int64_t grid, const TileArgs& args, hipStream_t stream) {
+  using R = VariantRow<ID>;
+  hipLaunchKernelGGL((tiles<R::TM, R::TN, R::KC, R::NW, R::OCC, FORM, RESUME>),
+                     dim3(static_cast<uint32_t>(grid)), dim3(64 * R::NW), 0, stream, args);
   return hipGetLastError();
 }
 
