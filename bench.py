@@ -342,7 +342,8 @@ def precision_section(torch, bsm, dev, stream, steps=5, warmup=2):
 
 
 def batch_section(torch, bsm, dev, stream, steps=5, warmup=2, nsample=8):
-    """Config 3: 64 products in one graph-captured launch (tile variant autotuned over the batch)."""
+    """Config 3: 64 products in one graph replay; the tile variant of each C-block size class is
+    autotuned over the whole batch (one kernel launch per variant in use)."""
     from paper_1504_05046_amd import gen
     say("batch64: generating inputs")
     t0 = time.perf_counter()
@@ -384,6 +385,7 @@ def batch_section(torch, bsm, dev, stream, steps=5, warmup=2, nsample=8):
         "workload": f"batch64: {WORKLOADS['batch64']}", "products": len(probs),
         "sizes": {str(n): sum(1 for p in probs if int(p.rows.sum()) == n) for n in sizes},
         "useful_gflop": round(flops / 1e9, 1), "tasks": tasks, "tile": tile,
+        "tile_classes": batch.tile_classes(),
         "value": round(flops / (wall * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
         "ms_per_step": round(wall, 3), "launch_ms": round(launch, 3),
         "mfma_frac": round(flops / (launch * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),

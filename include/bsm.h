@@ -107,7 +107,8 @@ typedef struct {
   double useful_flops;     /* 2 * sum over triples of r_i s_k t_j */
   int64_t workspace_bytes; /* device memory the plan holds besides the caller's buffers */
   int64_t k_windows;       /* launches per execute: ceil(K / k_window) */
-  int32_t tile;            /* tile variant in use (variant id + 1) */
+  int32_t tile;            /* tile variant every task uses (variant id + 1), or 0 when the size
+                              classes use different variants (bsm_plan_tile_classes) */
   int32_t out;             /* bsm_out: element type of C */
 } bsm_plan_info;
 
@@ -202,13 +203,24 @@ bsm_status bsm_plan_features(const bsm_plan* plan, float* features, int64_t n);
  * queued on that execute's stream has finished. */
 bsm_status bsm_plan_set_costs(bsm_plan* plan, const float* costs, int64_t n);
 
-/* Autotuner: time every tile variant of the plan's precision form on the given operands (one
- * warm-up and 5 timed runs each; C is overwritten with A B) and keep the fastest; *chosen (may be
- * NULL) receives its id + 1.  When the plan's tune_cache option names a file, choices are looked
- * up there by a workload signature first and appended after tuning.  Synchronises `stream`.
- * (The paper's performance rests on the block kernel, Sec. 4.3; this picks its tile shape.) */
+/* Autotuner.  C blocks fall into four size classes by their larger size (<= 32, <= 64, <= 128,
+ * more); each class has its own tile variant, and the tasks of one variant are launched together.
+ * For every class that carries work (most work first) every variant of the plan's precision form
+ * is timed with the other classes fixed (one warm-up and 5 timed runs of the whole product on the
+ * given operands; C is overwritten with A B), and the fastest is kept.  *chosen (may be NULL)
+ * receives the variant id + 1 if all classes ended on one variant, else 0.  When the plan's
+ * tune_cache option names a file, choices are looked up there by a workload signature first and
+ * appended after tuning.  Synchronises `stream`.  (The paper's performance rests on the block
+ * kernel, Sec. 4.3; this picks its tile shape per block size.) */
 bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, void* dC,
                         void* stream, int32_t* chosen);
+
+/* The tile variant (id + 1) of each of the four size classes (writes min(cap, 4) entries). */
+bsm_status bsm_plan_tile_classes(const bsm_plan* plan, int32_t* variants, int32_t cap);
+
+/* Set the tile variant (id + 1) of each of the four size classes (4 entries, host) and re-cut the
+ * tasks (flop-count order).  Only the tiling changes; results stay within the form's gate. */
+bsm_status bsm_plan_set_tile_classes(bsm_plan* plan, const int32_t* variants);
 
 /* Release the plan (waits for its device work first).  NULL is accepted. */
 bsm_status bsm_plan_destroy(bsm_plan* plan);
@@ -216,16 +228,17 @@ bsm_status bsm_plan_destroy(bsm_plan* plan);
 /* ---- batches: many independent products in one launch ---------------------------------------
  * Several matrix multiplications overlapped in one execution (Sec. 1 names the overlap of the
  * multiplications of one expression as a motivation of the task formulation).  A batch
- * concatenates the tasks of n plans (same precision and tile variant, k_window 0) into one task
- * list and one schedule; bsm_batch_execute captures every member's operand conversion plus one
- * tile-kernel launch over all tasks into a hipGraph and replays it while the operand pointers,
- * alphas and accumulate stay the same.  The plans must outlive the batch and must not run
+ * concatenates the tasks of n plans (same precision, k_window 0) into one task
+ * list and one schedule; bsm_batch_execute captures every member's operand conversion plus the
+ * tile-kernel launches over all tasks (one per tile variant in use) into a hipGraph and replays it
+ * while the operand pointers, alphas and accumulate stay the same.  The plans must outlive the batch and must not run
  * elsewhere while the batch executes.  An FP64 plan may appear more than once (each entry is a
  * product with its own operands); an FP32 or split-bf16 plan only once, since it converts its
  * operands into buffers it owns (BSM_E_INVALID otherwise). */
 bsm_status bsm_batch_create(bsm_batch** out, bsm_plan* const* plans, int64_t n);
 
-/* Task count, total useful flops and tile variant (id + 1) of a batch (any pointer may be NULL). */
+/* Task count, total useful flops and tile variant (id + 1, or 0 when the tasks mix variants) of a
+ * batch (any pointer may be NULL). */
 bsm_status bsm_batch_query(const bsm_batch* batch, int64_t* tasks, double* useful_flops,
                            int32_t* tile);
 
@@ -247,9 +260,13 @@ bsm_status bsm_batch_timings(bsm_batch* batch, float* features, float* seconds, 
 /* Re-order and re-bin the batch's tasks by per-task costs, as bsm_plan_set_costs. */
 bsm_status bsm_batch_set_costs(bsm_batch* batch, const float* costs, int64_t n);
 
-/* Autotuner over the whole batch (every member is re-cut for the chosen variant). */
+/* Autotuner over the whole batch, per size class as bsm_autotune (every member is re-cut with the
+ * chosen class variants; the batch's tune cache is its first member's). */
 bsm_status bsm_batch_autotune(bsm_batch* batch, const double* const* dA, const double* const* dB,
                               void* const* dC, void* stream, int32_t* chosen);
+
+/* The tile variant (id + 1) of each size class of the batch (writes min(cap, 4) entries). */
+bsm_status bsm_batch_tile_classes(const bsm_batch* batch, int32_t* variants, int32_t cap);
 
 bsm_status bsm_batch_destroy(bsm_batch* batch);
 

@@ -77,6 +77,9 @@ def load() -> ctypes.CDLL:
     L.bsm_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
     L.bsm_execute_static.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
     L.bsm_plan_verify.argtypes = [_p, _p]
+    L.bsm_plan_tile_classes.argtypes = [_p, _p, ctypes.c_int32]
+    L.bsm_plan_set_tile_classes.argtypes = [_p, _p]
+    L.bsm_batch_tile_classes.argtypes = [_p, _p, ctypes.c_int32]
     L.bsm_plan_debug_skip_task.argtypes = [_p, _i64]
     L.bsm_batch_verify.argtypes = [_p, _p]
     L.bsm_plan_destroy.argtypes = [_p]
@@ -108,7 +111,8 @@ def load() -> ctypes.CDLL:
     L.bsm_adam_step.argtypes = [_p, _p, _p, _p, _i64, _i64, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, _p]
     for name in ("bsm_plan_create", "bsm_plan_query", "bsm_plan_c_shape", "bsm_plan_c_offsets",
-                 "bsm_execute", "bsm_execute_static", "bsm_plan_verify", "bsm_plan_debug_skip_task", "bsm_batch_verify",
+                 "bsm_execute", "bsm_execute_static", "bsm_plan_verify", "bsm_plan_tile_classes",
+                 "bsm_plan_set_tile_classes", "bsm_batch_tile_classes", "bsm_plan_debug_skip_task", "bsm_batch_verify",
                  "bsm_plan_destroy", "bsm_plan_timings", "bsm_plan_features",
                  "bsm_plan_set_costs", "bsm_autotune", "bsm_batch_create", "bsm_batch_query",
                  "bsm_batch_execute", "bsm_batch_timings", "bsm_batch_set_costs",
@@ -293,6 +297,18 @@ class Plan:
     def set_costmodel(self, model: "CostModel", stream=None):
         _check(load().bsm_plan_set_costmodel(self._h, model.handle, _stream_handle(stream)))
 
+    def tile_classes(self):
+        """Tile variant (id + 1) of each of the four C-block size classes."""
+        out = np.zeros(4, np.int32)
+        _check(load().bsm_plan_tile_classes(self._h, out.ctypes.data, 4))
+        return out.tolist()
+
+    def set_tile_classes(self, variants):
+        v = _arr(variants, np.int32)
+        if v.size != 4:
+            raise ValueError("one tile variant per size class (4)")
+        _check(load().bsm_plan_set_tile_classes(self._h, v.ctypes.data))
+
     def close(self):
         if getattr(self, "_h", None):
             _check(load().bsm_plan_destroy(self._h))
@@ -366,6 +382,11 @@ class Batch:
 
     def set_costmodel(self, model: "CostModel", stream=None):
         _check(load().bsm_batch_set_costmodel(self._h, model.handle, _stream_handle(stream)))
+
+    def tile_classes(self):
+        out = np.zeros(4, np.int32)
+        _check(load().bsm_batch_tile_classes(self._h, out.ctypes.data, 4))
+        return out.tolist()
 
     def close(self):
         if getattr(self, "_h", None):

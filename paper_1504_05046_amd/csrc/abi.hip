@@ -288,25 +288,28 @@ static bsm_status enqueue_tiles(const HostPlan& h, TaskSet& ts, const ProductArg
                                 const ProductArgs& single, int accumulate, int skip_task,
                                 hipStream_t s) {
   if (h.items.empty()) return BSM_OK;
-  TileArgs a{};
-  a.items = ts.items;
-  a.tri = ts.tri;
-  a.done = ts.done;
-  a.skip_task = skip_task;
-  for (int x = 0; x <= kXcds; ++x) a.map.begin[x] = h.xcd_begin[x];
-  a.prods = prods;
-  a.single = single;
-  a.accumulate = accumulate;
-  a.stamps = ts.stamps;
   // k-windows of I consecutive inner blocks, issued in order on the stream; each window resumes
-  // from the raw FP64 sums of the previous one, so C does not depend on I
+  // from the raw FP64 sums of the previous one, so C does not depend on I.  Within a window, one
+  // launch per segment (the tasks of one tile variant).
   const int64_t I = h.k_window_eff;
   for (int64_t wdx = 0; wdx < h.windows; ++wdx) {
-    a.k_lo = int(wdx * I);
-    a.k_hi = wdx + 1 == h.windows ? kNoKLimit : int((wdx + 1) * I);
-    a.win_first = wdx == 0;
-    a.win_last = wdx + 1 == h.windows;
-    BSM_HIP(launch_form(h.cfg.precision, h.variant, h.grid, a, s), "tile kernel launch");
+    for (const Segment& g : h.segs) {
+      TileArgs a{};
+      a.items = ts.items + g.begin;
+      a.tri = ts.tri;
+      a.done = ts.done ? ts.done + g.begin : nullptr;
+      a.stamps = ts.stamps ? ts.stamps + 2 * int64_t(g.begin) : nullptr;
+      a.skip_task = (skip_task >= g.begin && skip_task < g.end) ? skip_task - g.begin : -1;
+      for (int x = 0; x <= kXcds; ++x) a.map.begin[x] = g.xcd_begin[x];
+      a.prods = prods;
+      a.single = single;
+      a.accumulate = accumulate;
+      a.k_lo = int(wdx * I);
+      a.k_hi = wdx + 1 == h.windows ? kNoKLimit : int((wdx + 1) * I);
+      a.win_first = wdx == 0;
+      a.win_last = wdx + 1 == h.windows;
+      BSM_HIP(launch_form(h.cfg.precision, g.variant, g.grid, a, s), "tile kernel launch");
+    }
   }
   if (ts.stamps) ts.timed = true;
   return BSM_OK;
@@ -379,24 +382,43 @@ static std::string tune_key(const std::vector<const HostPlan*>& parts) {
   return buf;
 }
 
-static int tune_cache_lookup(const std::string& path, const std::string& key) {
-  if (path.empty()) return -1;
+// A cache line holds the key and the variant of each size class ("key v0,v1,v2,v3"); the last
+// line for a key wins.  Returns false if the key is absent or a variant is out of range.
+static bool tune_cache_lookup(const std::string& path, const std::string& key, int nvar,
+                              int cv[kSizeClasses]) {
+  if (path.empty()) return false;
   FILE* f = std::fopen(path.c_str(), "r");
-  if (!f) return -1;
+  if (!f) return false;
   char k[256];
-  int v, found = -1;
-  while (std::fscanf(f, "%255s %d", k, &v) == 2)
-    if (key == k) found = v;
+  int v[kSizeClasses];
+  bool found = false;
+  while (std::fscanf(f, "%255s %d,%d,%d,%d", k, &v[0], &v[1], &v[2], &v[3]) == 5) {
+    if (key != k) continue;
+    bool ok = true;
+    for (int c = 0; c < kSizeClasses; ++c) ok = ok && v[c] >= 0 && v[c] < nvar;
+    if (!ok) continue;
+    for (int c = 0; c < kSizeClasses; ++c) cv[c] = v[c];
+    found = true;
+  }
   std::fclose(f);
   return found;
 }
 
-static void tune_cache_store(const std::string& path, const std::string& key, int v) {
+static void tune_cache_store(const std::string& path, const std::string& key,
+                             const int cv[kSizeClasses]) {
   if (path.empty()) return;
   FILE* f = std::fopen(path.c_str(), "a");
   if (!f) return;
-  std::fprintf(f, "%s %d\n", key.c_str(), v);
+  std::fprintf(f, "%s %d,%d,%d,%d\n", key.c_str(), cv[0], cv[1], cv[2], cv[3]);
   std::fclose(f);
+}
+
+// Useful flops of each size class over the given plans.
+static std::vector<double> class_work(const std::vector<const HostPlan*>& parts) {
+  std::vector<double> w(kSizeClasses, 0.0);
+  for (const HostPlan* p : parts)
+    for (const CBlock& c : p->cblocks) w[size_class(c.m, c.n)] += 2.0 * c.m * c.n * c.sk;
+  return w;
 }
 
 static bsm_status time_body(const std::function<bsm_status(hipStream_t)>& body, hipStream_t s,
@@ -423,6 +445,40 @@ constexpr int kTuneReps = 5;
 
 static int num_variants(int precision) {
   return precision == BSM_BF16X3 ? kNumBf16Variants : kNumVariants;
+}
+
+// Per-size-class tuning by coordinate descent: the classes that carry work, most work first, each
+// try every variant with the other classes fixed (recut re-cuts and re-uploads the tasks for a
+// choice of class variants, timeit times the whole product); cv holds the start and the result.
+static bsm_status tune_classes(int nvar, const std::vector<double>& work, int cv[kSizeClasses],
+                               const std::function<bsm_status(const int*)>& recut,
+                               const std::function<bsm_status(float*)>& timeit) {
+  std::vector<int> order;
+  for (int c = 0; c < kSizeClasses; ++c)
+    if (work[size_t(c)] > 0) order.push_back(c);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[size_t(a)] > work[size_t(b)]; });
+  bsm_status st;
+  for (int c : order) {
+    int best = cv[c];
+    float best_ms = 0.f;
+    for (int v = 0; v < nvar; ++v) {
+      cv[c] = v;
+      if ((st = recut(cv)) != BSM_OK) return st;
+      float ms = 0.f;
+      if ((st = timeit(&ms)) != BSM_OK) return st;
+      if (v == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    cv[c] = best;
+  }
+  return recut(cv);
+}
+
+static int32_t reported_tile(const HostPlan& h) {
+  const int v = h.uniform_variant();
+  return v < 0 ? 0 : v + 1;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -709,7 +765,7 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   if (h.cfg.record_timings) ws += int64_t(h.items.size()) * 16;
   info->workspace_bytes = ws;
   info->k_windows = h.windows;
-  info->tile = h.variant + 1;
+  info->tile = reported_tile(h);
   info->out = h.cfg.out_f32 ? BSM_OUT_F32 : BSM_OUT_F64;
   return BSM_OK;
 }
@@ -806,41 +862,58 @@ bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, void
   bsm_status st = check_operands(h, dA, dB, dC, 0);
   if (st != BSM_OK) return st;
   if ((st = prepare(plan)) != BSM_OK) return st;
+  const int nvar = num_variants(h.cfg.precision);
   const std::string key = tune_key({&h});
-  int best = tune_cache_lookup(h.cfg.tune_cache, key);
-  if (best < 0 || best >= num_variants(h.cfg.precision)) {
-    float best_ms = 0.f;
-    best = h.variant;
-    for (int v = 0; v < num_variants(h.cfg.precision); ++v) {
-      cut_items(h, v);
-      schedule(h, flop_costs(h));
-      plan->tasks_dirty = true;
-      if ((st = sync_tasks(plan, s)) != BSM_OK) return st;
-      auto body = [&](hipStream_t q) -> bsm_status {
-        ProductArgs pa{};
-        bsm_status r = enqueue_convert(plan, dA, dB, q, pa);
-        if (r != BSM_OK) return r;
-        pa.C = dC;
-        pa.c_f32 = h.cfg.out_f32;
-        pa.P = plan->d_partial;
-        pa.alpha = 1.0;
-        return enqueue_tiles(h, plan->ts, nullptr, pa, 0, -1, q);
-      };
+  int cv[kSizeClasses];
+  for (int c = 0; c < kSizeClasses; ++c) cv[c] = h.class_var[c];
+  auto recut = [&](const int* v) -> bsm_status {
+    cut_items(h, v);
+    schedule(h, flop_costs(h));
+    plan->tasks_dirty = true;
+    return sync_tasks(plan, s);
+  };
+  if (!tune_cache_lookup(h.cfg.tune_cache, key, nvar, cv)) {
+    auto body = [&](hipStream_t q) -> bsm_status {
+      ProductArgs pa{};
+      bsm_status r = enqueue_convert(plan, dA, dB, q, pa);
+      if (r != BSM_OK) return r;
+      pa.C = dC;
+      pa.c_f32 = h.cfg.out_f32;
+      pa.P = plan->d_partial;
+      pa.alpha = 1.0;
+      return enqueue_tiles(h, plan->ts, nullptr, pa, 0, -1, q);
+    };
+    auto timeit = [&](float* ms) {
       plan->ts.used = true;
-      float ms = 0.f;
-      if ((st = time_body(body, s, kTuneReps, &ms)) != BSM_OK) return st;
-      if (v == 0 || ms < best_ms) {
-        best_ms = ms;
-        best = v;
-      }
-    }
-    tune_cache_store(h.cfg.tune_cache, key, best);
+      return time_body(body, s, kTuneReps, ms);
+    };
+    if ((st = tune_classes(nvar, class_work({&h}), cv, recut, timeit)) != BSM_OK) return st;
+    tune_cache_store(h.cfg.tune_cache, key, cv);
+  } else if ((st = recut(cv)) != BSM_OK) {
+    return st;
   }
-  cut_items(h, best);
+  if (chosen) *chosen = reported_tile(h);
+  return BSM_OK;
+}
+
+bsm_status bsm_plan_set_tile_classes(bsm_plan* plan, const int32_t* variants) {
+  if (!plan || !variants) return fail(BSM_E_INVALID, "null argument");
+  HostPlan& h = plan->hp;
+  int cv[kSizeClasses];
+  for (int c = 0; c < kSizeClasses; ++c) {
+    if (variants[c] < 1 || variants[c] > num_variants(h.cfg.precision))
+      return fail(BSM_E_INVALID, "tile variant of size class " + std::to_string(c) + " out of range");
+    cv[c] = variants[c] - 1;
+  }
+  cut_items(h, cv);
   schedule(h, flop_costs(h));
   plan->tasks_dirty = true;
-  if ((st = sync_tasks(plan, s)) != BSM_OK) return st;
-  if (chosen) *chosen = best + 1;
+  return BSM_OK;
+}
+
+bsm_status bsm_plan_tile_classes(const bsm_plan* plan, int32_t* variants, int32_t cap) {
+  if (!plan || (cap > 0 && !variants)) return fail(BSM_E_INVALID, "null argument");
+  for (int c = 0; c < kSizeClasses && c < cap; ++c) variants[c] = plan->hp.class_var[c] + 1;
   return BSM_OK;
 }
 
@@ -901,7 +974,7 @@ bsm_status bsm_batch_query(const bsm_batch* batch, int64_t* tasks, double* usefu
   if (!batch) return fail(BSM_E_INVALID, "batch is null");
   if (tasks) *tasks = int64_t(batch->hp.items.size());
   if (useful_flops) *useful_flops = batch->hp.useful_flops;
-  if (tile) *tile = batch->hp.variant + 1;
+  if (tile) *tile = reported_tile(batch->hp);
   return BSM_OK;
 }
 
@@ -1026,9 +1099,10 @@ bsm_status bsm_batch_autotune(bsm_batch* batch, const double* const* dA, const d
     if ((st = prepare(batch->members[q])) != BSM_OK) return st;
     parts.push_back(&batch->members[q]->hp);
   }
-  const int prec = parts[0]->cfg.precision;
+  const int nvar = num_variants(parts[0]->cfg.precision);
   const std::string key = tune_key(parts);
-  auto recut = [&](int v) -> bsm_status {
+  // every member is re-cut with the same class variants, then the batch is merged again
+  auto recut = [&](const int* v) -> bsm_status {
     for (bsm_plan* p : batch->members) {
       cut_items(p->hp, v);
       schedule(p->hp, flop_costs(p->hp));
@@ -1040,28 +1114,29 @@ bsm_status bsm_batch_autotune(bsm_batch* batch, const double* const* dA, const d
     batch->tasks_dirty = true;
     return batch_sync(batch, s);
   };
+  int cv[kSizeClasses];
+  for (int c = 0; c < kSizeClasses; ++c) cv[c] = parts[0]->class_var[c];
   const std::string& cache = parts[0]->cfg.tune_cache;
-  int best = tune_cache_lookup(cache, key);
-  if (best < 0 || best >= num_variants(prec)) {
+  if (!tune_cache_lookup(cache, key, nvar, cv)) {
     if ((st = batch_table(batch, nullptr, dA, dB, dC, s)) != BSM_OK) return st;
     batch->table_used = true;
-    float best_ms = 0.f;
-    best = 0;
-    for (int v = 0; v < num_variants(prec); ++v) {
-      if ((st = recut(v)) != BSM_OK) return st;
-      auto body = [&](hipStream_t q) { return batch_body(batch, dA, dB, 0, q); };
+    auto body = [&](hipStream_t q) { return batch_body(batch, dA, dB, 0, q); };
+    auto timeit = [&](float* ms) {
       batch->ts.used = true;
-      float ms = 0.f;
-      if ((st = time_body(body, s, kTuneReps, &ms)) != BSM_OK) return st;
-      if (v == 0 || ms < best_ms) {
-        best_ms = ms;
-        best = v;
-      }
-    }
-    tune_cache_store(cache, key, best);
+      return time_body(body, s, kTuneReps, ms);
+    };
+    if ((st = tune_classes(nvar, class_work(parts), cv, recut, timeit)) != BSM_OK) return st;
+    tune_cache_store(cache, key, cv);
+  } else if ((st = recut(cv)) != BSM_OK) {
+    return st;
   }
-  if ((st = recut(best)) != BSM_OK) return st;
-  if (chosen) *chosen = best + 1;
+  if (chosen) *chosen = reported_tile(batch->hp);
+  return BSM_OK;
+}
+
+bsm_status bsm_batch_tile_classes(const bsm_batch* batch, int32_t* variants, int32_t cap) {
+  if (!batch || (cap > 0 && !variants)) return fail(BSM_E_INVALID, "null argument");
+  for (int c = 0; c < kSizeClasses && c < cap; ++c) variants[c] = batch->hp.class_var[c] + 1;
   return BSM_OK;
 }
 

@@ -85,6 +85,54 @@ std::vector<double> flop_costs(const HostPlan& p) {
   return c;
 }
 
+// Deals the tasks of one segment (indices `idx` into the canonically ordered task list) to the
+// XCDs; returns one list of task indices per XCD.
+static std::vector<std::vector<size_t>> deal(const HostPlan& p, const std::vector<size_t>& idx,
+                                             const std::vector<double>& cost) {
+  std::vector<std::vector<size_t>> bins(kXcds);
+  std::vector<double> load(kXcds, 0.0);
+  if (p.cfg.order == ORDER_LPT) {
+    // longest processing time first: largest task to the least-loaded XCD, each XCD then runs
+    // its tasks largest first (its 32 CUs pick them up in that order)
+    std::vector<size_t> o(idx);
+    std::stable_sort(o.begin(), o.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    for (size_t q : o) {
+      int x = int(std::min_element(load.begin(), load.end()) - load.begin());
+      bins[size_t(x)].push_back(q);
+      load[size_t(x)] += cost[q];
+    }
+  } else if (p.cfg.order == ORDER_INTERLEAVE) {
+    // whole C blocks (consecutive tasks with the same C offset) dealt to the least-loaded XCD in
+    // C-block order
+    size_t u = 0;
+    while (u < idx.size()) {
+      size_t e = u + 1;
+      double c = cost[idx[u]];
+      const Item& first = p.items[idx[u]];
+      while (e < idx.size() && p.items[idx[e]].c_off == first.c_off &&
+             p.items[idx[e]].product == first.product)
+        c += cost[idx[e++]];
+      int x = int(std::min_element(load.begin(), load.end()) - load.begin());
+      for (size_t r = u; r < e; ++r) bins[size_t(x)].push_back(idx[r]);
+      load[size_t(x)] += c;
+      u = e;
+    }
+  } else {
+    // keep the C-block order (sub-tiles of a block and blocks of a block row stay together, so
+    // they share A and B tiles in one XCD's L2) and cut it into kXcds runs of equal cost
+    double total = 0;
+    for (size_t q : idx) total += cost[q];
+    double acc = 0;
+    int x = 0;
+    for (size_t q : idx) {
+      while (x < kXcds - 1 && acc >= total * (x + 1) / kXcds) ++x;
+      bins[size_t(x)].push_back(q);
+      acc += cost[q];
+    }
+  }
+  return bins;
+}
+
 void schedule(HostPlan& p, const std::vector<double>& cost_in) {
   size_t n = p.items.size();
   // Every order below is defined on the tasks in C-block order (product, C offset, sub-tile), so
@@ -103,88 +151,77 @@ void schedule(HostPlan& p, const std::vector<double>& cost_in) {
       return x.c0 < y.c0;
     });
     std::vector<Item> it2(n);
+    std::vector<uint8_t> v2(n);
     std::vector<double> c2(n);
     std::vector<float> f2(p.features.size());
     for (size_t q = 0; q < n; ++q) {
       it2[q] = p.items[perm[q]];
+      v2[q] = p.ivar[perm[q]];
       c2[q] = cost_in[perm[q]];
       for (int f = 0; f < 5; ++f) f2[q * 5 + size_t(f)] = p.features[perm[q] * 5 + size_t(f)];
     }
     p.items.swap(it2);
+    p.ivar.swap(v2);
     p.features.swap(f2);
     cost.swap(c2);
   }
-  std::vector<size_t> idx(n);
-  std::iota(idx.begin(), idx.end(), 0);
-  std::vector<std::vector<size_t>> bins(kXcds);
-  if (p.cfg.order == ORDER_LPT) {
-    // longest processing time first: largest task to the least-loaded XCD, each XCD then runs
-    // its tasks largest first (its 32 CUs pick them up in that order)
-    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<double> load(kXcds, 0.0);
-    for (size_t q : idx) {
-      int x = int(std::min_element(load.begin(), load.end()) - load.begin());
-      bins[size_t(x)].push_back(q);
-      load[size_t(x)] += cost[q];
-    }
-  } else if (p.cfg.order == ORDER_INTERLEAVE) {
-    // whole C blocks (consecutive tasks with the same C offset) dealt to the least-loaded XCD in
-    // C-block order
-    std::vector<double> load(kXcds, 0.0);
-    size_t q = 0;
-    while (q < n) {
-      size_t e = q + 1;
-      double c = cost[q];
-      while (e < n && p.items[e].c_off == p.items[q].c_off && p.items[e].product == p.items[q].product) c += cost[e++];
-      int x = int(std::min_element(load.begin(), load.end()) - load.begin());
-      for (size_t r = q; r < e; ++r) bins[size_t(x)].push_back(r);
-      load[size_t(x)] += c;
-      q = e;
-    }
-  } else {
-    // keep the C-block order (sub-tiles of a block and blocks of a block row stay together, so
-    // they share A and B tiles in one XCD's L2) and cut it into kXcds runs of equal cost
-    double total = 0;
-    for (size_t q = 0; q < n; ++q) total += cost[q];
-    double acc = 0;
-    int x = 0;
-    for (size_t q = 0; q < n; ++q) {
-      while (x < kXcds - 1 && acc >= total * (x + 1) / kXcds) ++x;
-      bins[size_t(x)].push_back(q);
-      acc += cost[q];
-    }
-  }
+  // one segment per tile variant in use, each dealt to the XCDs on its own
   std::vector<Item> items;
+  std::vector<uint8_t> vars;
   std::vector<double> c2;
   std::vector<float> f2;
   items.reserve(n);
+  vars.reserve(n);
   c2.reserve(n);
   f2.reserve(p.features.size());
-  int64_t maxc = 0;
-  for (int x = 0; x < kXcds; ++x) {
-    p.xcd_begin[x] = int32_t(items.size());
-    for (size_t q : bins[size_t(x)]) {
-      items.push_back(p.items[q]);
-      c2.push_back(cost[q]);
-      for (int f = 0; f < 5; ++f) f2.push_back(p.features[q * 5 + size_t(f)]);
+  p.segs.clear();
+  for (int v = 0; v < 256; ++v) {
+    std::vector<size_t> idx;
+    for (size_t q = 0; q < n; ++q)
+      if (p.ivar[q] == v) idx.push_back(q);
+    if (idx.empty()) continue;
+    Segment g;
+    g.variant = v;
+    g.begin = int32_t(items.size());
+    int64_t maxc = 0;
+    const auto bins = deal(p, idx, cost);
+    for (int x = 0; x < kXcds; ++x) {
+      g.xcd_begin[x] = int32_t(items.size()) - g.begin;
+      for (size_t q : bins[size_t(x)]) {
+        items.push_back(p.items[q]);
+        vars.push_back(p.ivar[q]);
+        c2.push_back(cost[q]);
+        for (int f = 0; f < 5; ++f) f2.push_back(p.features[q * 5 + size_t(f)]);
+      }
+      maxc = std::max<int64_t>(maxc, int64_t(bins[size_t(x)].size()));
     }
-    maxc = std::max<int64_t>(maxc, int64_t(bins[size_t(x)].size()));
+    g.xcd_begin[kXcds] = int32_t(items.size()) - g.begin;
+    g.end = int32_t(items.size());
+    g.grid = maxc * kXcds;
+    p.segs.push_back(g);
   }
-  p.xcd_begin[kXcds] = int32_t(items.size());
   p.items.swap(items);
+  p.ivar.swap(vars);
   p.cost.swap(c2);
   p.features.swap(f2);
-  p.grid = maxc * kXcds;
 }
 
 void cut_items(HostPlan& p, int variant) {
+  int cv[kSizeClasses];
+  for (int c = 0; c < kSizeClasses; ++c) cv[c] = variant;
+  cut_items(p, cv);
+}
+
+void cut_items(HostPlan& p, const int class_var[kSizeClasses]) {
   const bool bf16 = p.cfg.precision == 2;
-  const Variant& var = bf16 ? kBf16Variants[variant] : kVariants[variant];
   std::vector<std::pair<int, int>> rs, cs;
   p.items.clear();
+  p.ivar.clear();
   p.features.clear();
-  p.variant = variant;
+  for (int c = 0; c < kSizeClasses; ++c) p.class_var[c] = class_var[c];
   for (const CBlock& cb : p.cblocks) {
+    const int variant = class_var[size_class(cb.m, cb.n)];
+    const Variant& var = bf16 ? kBf16Variants[variant] : kVariants[variant];
     cut_dim(cb.m, var.tm / 16, rs);
     cut_dim(cb.n, var.tn / 16, cs);
     for (auto& r : rs)
@@ -201,6 +238,7 @@ void cut_items(HostPlan& p, int variant) {
         it.ldm = uint16_t(cb.m);
         it.product = 0;
         p.items.push_back(it);
+        p.ivar.push_back(uint8_t(variant));
         p.features.push_back(std::log(float(it.h)));
         p.features.push_back(std::log(float(it.w)));
         p.features.push_back(std::log(float(std::max(1.0, cb.sk))));
@@ -356,13 +394,12 @@ std::string merge_plans(HostPlan& out, const std::vector<const HostPlan*>& parts
   const HostPlan& p0 = *parts[0];
   out = HostPlan();
   out.cfg = p0.cfg;
-  out.variant = p0.variant;
+  for (int c = 0; c < kSizeClasses; ++c) out.class_var[c] = p0.class_var[c];
   out.windows = 1;
   out.k_window_eff = 1;
   for (size_t q = 0; q < parts.size(); ++q) {
     const HostPlan& p = *parts[q];
     if (p.cfg.precision != p0.cfg.precision) return "batch members differ in precision";
-    if (p.variant != p0.variant) return "batch members differ in tile variant";
     if (p.windows != 1) return "batch members must issue all k-iterations at once (k_window 0)";
     const uint64_t tb = out.tri.size();
     if (tb + p.tri.size() >= (uint64_t(1) << 32)) {
@@ -376,6 +413,7 @@ std::string merge_plans(HostPlan& out, const std::vector<const HostPlan*>& parts
       it.product = uint32_t(q);
       out.items.push_back(it);
     }
+    out.ivar.insert(out.ivar.end(), p.ivar.begin(), p.ivar.end());
     out.features.insert(out.features.end(), p.features.begin(), p.features.end());
     out.useful_flops += p.useful_flops;
     out.c_blocks += p.c_blocks;

@@ -37,6 +37,23 @@ struct PlanConfig {
   std::string tune_cache;  // autotuner choices file ("" = none)
 };
 
+// Size classes of C blocks (by the larger of the block's two sizes): <= 32, <= 64, <= 128, more.
+// Each class has its own tile variant, so one plan or batch can mix variants.
+constexpr int kSizeClasses = 4;
+inline int size_class(int m, int n) {
+  const int d = m > n ? m : n;
+  return d <= 32 ? 0 : d <= 64 ? 1 : d <= 128 ? 2 : 3;
+}
+
+// A run of tasks that share one tile variant, launched together: tasks [begin, end) of the task
+// list, dealt to the XCDs (tasks begin + xcd_begin[x] .. begin + xcd_begin[x+1] - 1 on XCD x).
+struct Segment {
+  int variant = 0;
+  int32_t begin = 0, end = 0;
+  int32_t xcd_begin[kXcds + 1] = {0};
+  int64_t grid = 0;  // workgroups of the launch
+};
+
 // A present C block and its k-list (the unit tasks are cut from).
 struct CBlock {
   int64_t c_off;
@@ -58,17 +75,25 @@ struct HostPlan {
   std::vector<Triple> tri;       // k-lists of all C blocks, C blocks in row-major order
   std::vector<CBlock> cblocks;   // present C blocks, row-major
   double k_total = 0;            // summed inner size of all K blocks
-  int variant = 0;               // tile variant the tasks are cut for
-  std::vector<Item> items;       // tasks in execution order, grouped by XCD
+  int class_var[kSizeClasses] = {0, 0, 0, 0};  // tile variant of each size class
+  std::vector<Item> items;       // tasks in execution order: segment by segment, XCD by XCD
+  std::vector<uint8_t> ivar;     // tile variant of items[q]
   std::vector<double> cost;      // scheduler cost of items[q]
   std::vector<float> features;   // 5 per item: log h, log w, log sum_k, log #k, density
+  std::vector<Segment> segs;     // one per tile variant in use, in variant order
   // split-bf16 form: slice-plane layout of A and B and the split pass's block table
   int64_t a_elems32 = 0, b_elems32 = 0;
   std::vector<SplitBlock> split_a, split_b;
-  int32_t xcd_begin[kXcds + 1] = {0};
   int64_t k_window_eff = 0;      // inner blocks per k-window
   int64_t windows = 1;           // number of k-windows
-  int64_t grid = 0;              // workgroups of the launch
+
+  // The tile variant every task uses, or -1 if the tasks mix variants.
+  int uniform_variant() const {
+    if (segs.empty()) return class_var[0];
+    for (const Segment& g : segs)
+      if (g.variant != segs[0].variant) return -1;
+    return segs[0].variant;
+  }
 };
 
 int64_t words_for(int64_t ncols);
@@ -79,14 +104,17 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
                        const uint64_t* a_bits, const uint64_t* b_bits, const PlanConfig& cfg,
                        int* code);
 
-// Cut every C block into tasks for the given tile variant (replaces items and features).
+// Cut every C block into tasks with the tile variant of its size class (replaces items, ivar and
+// features; sets p.class_var).
+void cut_items(HostPlan& p, const int class_var[kSizeClasses]);
+// The same variant for every size class.
 void cut_items(HostPlan& p, int variant);
 
 // Re-order and re-partition the tasks from per-item costs (never changes the task set).
 void schedule(HostPlan& p, const std::vector<double>& cost);
 
-// Concatenate the tasks of several plans (same precision, tile variant, one k-window) into one
-// schedule; task q of part p keeps its triples and is tagged with product p.
+// Concatenate the tasks of several plans (same precision, one k-window) into one schedule; task q
+// of part p keeps its triples and tile variant and is tagged with product p.
 std::string merge_plans(HostPlan& out, const std::vector<const HostPlan*>& parts, int* code);
 
 // Flop-count cost of every item.

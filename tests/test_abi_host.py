@@ -147,8 +147,10 @@ def test_batch_rules_checked_on_host():
     assert flops == a.info().useful_flops + b.info().useful_flops
     assert tile == a.info().tile
     _expect(bsm.E_MISMATCH, lambda: bsm.Batch([a, bsm.Plan.from_problem(q, precision=bsm.FP32)]))
-    _expect(bsm.E_MISMATCH, lambda: bsm.Batch([a, bsm.Plan.from_problem(q, tile=2)]))
     _expect(bsm.E_MISMATCH, lambda: bsm.Batch([a, bsm.Plan.from_problem(q, k_window=1)]))
+    # members may use different tile variants: their tasks run in one launch per variant
+    mixed = bsm.Batch([a, bsm.Plan.from_problem(q, tile=3)])
+    assert mixed.query()[2] == 0 and mixed.query()[0] == tasks - b.info().tasks + bsm.Plan.from_problem(q, tile=3).info().tasks
     L = bsm.load()
     assert L.bsm_batch_create(None, None, 0) == bsm.E_INVALID
 
@@ -270,3 +272,19 @@ def test_static_entry_rejects_plans_beyond_its_scratch():
     assert st == bsm.E_NOMEM
     assert "64" in L.bsm_last_error().decode() or "67108864" in L.bsm_last_error().decode()
     assert L.bsm_execute_static(None, 1.0, 0, 0, 0, 0, None) == bsm.E_INVALID
+
+
+def test_size_classes_and_segments():
+    """Tile variants per size class: tasks of a class are cut with its variant; a plan whose
+    classes use one variant reports it, and the class table reads back."""
+    p = gen.random_problem(46, 6, 5, 6, 8, 200, 0.7, 0.7)
+    plan = bsm.Plan.from_problem(p, tile=2)
+    assert plan.info().tile == 2 and plan.tile_classes() == [2, 2, 2, 2]
+    plan = bsm.Plan.from_problem(p)
+    assert plan.tile_classes() == [1, 1, 1, 1]
+    plan.set_tile_classes([4, 3, 2, 1])
+    assert plan.tile_classes() == [4, 3, 2, 1]
+    # sizes 8..200 fall in several classes, so the tasks now mix variants
+    assert plan.info().tile == 0
+    _expect(bsm.E_INVALID, lambda: plan.set_tile_classes([0, 1, 1, 1]))
+    _expect(bsm.E_INVALID, lambda: plan.set_tile_classes([1, 1, 1, 5]))

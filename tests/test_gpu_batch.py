@@ -138,15 +138,19 @@ def test_autotune_picks_a_variant_and_stays_correct(tmp_path):
     batch = bsm.Batch(plans)
     As, Bs, Cs = operands(probs, plans)
     v = batch.autotune(As, Bs, Cs)
-    assert 1 <= v <= len(bsm.tile_variants())
+    assert 0 <= v <= len(bsm.tile_variants())
     assert batch.query()[2] == v
+    classes = batch.tile_classes()
+    assert all(1 <= c <= len(bsm.tile_variants()) for c in classes)
+    _say(f"[autotune] batch class variants {classes}")
     batch.execute(As, Bs, Cs)
-    torch.cuda.synchronize()
+    batch.verify()
     for p, C, pl in zip(probs, Cs, plans):
         assert rel_fro(host(C, pl), ref(p)) <= 1e-12
     # the choice was cached: a second tune returns it without timing
-    assert (tmp_path / "tune.txt").read_text().strip().endswith(str(v - 1))
-    assert batch.autotune(As, Bs, Cs) == v
+    line = (tmp_path / "tune.txt").read_text().strip().splitlines()[-1]
+    assert line.endswith(",".join(str(c - 1) for c in classes))
+    assert batch.autotune(As, Bs, Cs) == v and batch.tile_classes() == classes
     # single-plan autotune
     p = probs[0]
     plan = bsm.Plan.from_problem(p, tune_cache=cache)
@@ -154,8 +158,29 @@ def test_autotune_picks_a_variant_and_stays_correct(tmp_path):
     w = plan.autotune(As[0], Bs[0], C)
     assert plan.info().tile == w
     plan.execute(As[0], Bs[0], C)
-    torch.cuda.synchronize()
+    plan.verify()
     assert rel_fro(C.cpu().numpy(), ref(p)) <= 1e-12
+
+
+@pytest.mark.parametrize("precision,gate", [(bsm.FP64, 1e-12), (bsm.FP32, 1e-5)])
+def test_mixed_variants_in_one_launch(precision, gate):
+    """Members cut with different tile variants run in one graph launch (one kernel per variant);
+    each product matches the oracle and its own single run bit for bit."""
+    probs = small_batch(41 + precision, count=4)
+    plans = [bsm.Plan.from_problem(p, precision=precision, tile=1 + q % len(bsm.tile_variants()))
+             for q, p in enumerate(probs)]
+    batch = bsm.Batch(plans)
+    assert batch.query()[2] == 0
+    As, Bs, Cs = operands(probs, plans)
+    batch.execute(As, Bs, Cs)
+    batch.verify()
+    for p, pl, A, B, C in zip(probs, plans, As, Bs, Cs):
+        g = host(C, pl)
+        assert rel_fro(g, ref(p)) <= gate
+        C1 = torch.full_like(C, float("nan"))
+        pl.execute(A, B, C1)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(C1, pl), g)
 
 
 def test_batch_timings():

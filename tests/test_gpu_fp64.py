@@ -262,3 +262,22 @@ def test_execution_counters_catch_a_skipped_task():
         torch.cuda.synchronize()
         ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
         assert rel_fro(C.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", [bsm.FP64, bsm.FP32])
+def test_mixed_tile_classes_single_plan(precision):
+    """One plan whose size classes use four different tile variants (one launch each): matches
+    the oracle, and k-windows give the same bits."""
+    p = gen.random_problem(2300 + precision, 9, 9, 9, 8, 200, 0.5, 0.5)
+    plan = bsm.Plan.from_problem(p, precision=precision)
+    plan.set_tile_classes([4, 3, 2, 1])
+    assert plan.info().tile == 0
+    got, _ = run_gpu(p, plan=plan)
+    plan.verify()
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    assert rel_fro(got, ref) <= (1e-12 if precision == bsm.FP64 else 1e-5)
+    win = bsm.Plan.from_problem(p, precision=precision, k_window=2)
+    win.set_tile_classes([4, 3, 2, 1])
+    got2, _ = run_gpu(p, plan=win)
+    win.verify()
+    assert np.array_equal(got, got2)
