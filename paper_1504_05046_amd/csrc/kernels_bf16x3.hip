@@ -10,12 +10,20 @@
 // k-list is streamed in 32-deep chunks (one MFMA step, one k-panel of the slice planes, whose rows
 // are contiguous): the three slices of A (rows) and of B (columns, stored k-contiguous) go through
 // double-buffered LDS with 16-byte loads and stores.
-// The waves form a 4 x 2 grid; each owns 2 x 4 of the sub-tile's 16x16 output blocks and reuses
-// every fragment it reads from LDS across a row or column of its blocks.
+// Each wave owns one rectangle of the sub-tile's 16x16 output blocks, from the same balanced table
+// as the FP64/FP32 kernel (the busiest wave owns the fewest blocks any rectangle tiling allows), and
+// reuses every fragment it reads from LDS across a row or column of its blocks.
+//
+// LDS layout: one 64-byte row (32 bf16 of a k-panel) per A row or B column, no padding; the
+// 16-byte granule o of row r sits at granule o ^ ((r >> 1) & 3).  Measured on gfx950 with the LDS
+// bank-conflict counter, this makes both the fragment reads (16 rows x 4 granules per ds_read_b128)
+// and the staging stores (4 lanes per row per ds_write_b128) conflict-free, where plain 64-byte or
+// 80-byte rows conflict on one of the two.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
 #include "uniform.hpp"
+#include "wave_rects.inc"
 
 namespace bsm {
 
@@ -42,28 +50,26 @@ template <int TM, int TN, int NW>
 struct B3Cfg {
   static constexpr int KC = kSliceK;           // one MFMA step per chunk
   static constexpr int NT = 64 * NW;
-  static constexpr int RS = KC + 8;            // LDS row stride (bf16): 80 bytes, conflict-free
+  static constexpr int RS = KC;                // LDS row: 32 bf16 = 64 bytes
   static constexpr int ASZ = 3 * TM * RS;      // bf16 elements of one A stage (3 slices)
   static constexpr int BSZ = 3 * TN * RS;
-  static constexpr int WR = TM / 32;           // wave grid rows; each wave covers 32 rows
-  static constexpr int WC = NW / WR;           // wave grid cols
-  static constexpr int MC = TN / WC / 16;      // 16-col blocks per wave
   static constexpr int AG = 3 * TM * (KC / 8); // 16-byte granules of one A stage
   static constexpr int BG = 3 * TN * (KC / 8);
   static constexpr int ALD = AG / NT, BLD = BG / NT;
-  static_assert(WR * WC == NW && AG % NT == 0 && BG % NT == 0, "bf16 tile shape");
+  static_assert(AG % NT == 0 && BG % NT == 0, "bf16 tile shape");
+  // bf16 offset of granule o (8 bf16) of LDS row r
+  __device__ static inline int gpos(int r, int o) { return r * RS + ((o ^ ((r >> 1) & 3)) << 3); }
 };
 
 template <int TM, int TN, int NW, bool RESUME, int NR, int NC>
 __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const ProductArgs& pa,
-                                       int wr, int wc, uint16_t* As, uint16_t* Bs) {
+                                       int rb0, int cb0, uint16_t* As, uint16_t* Bs) {
   using C = B3Cfg<TM, TN, NW>;
   constexpr int NRA = NR > 0 ? NR : 1, NCA = NC > 0 ? NC : 1;
   const int tid = threadIdx.x, lane = tid & 63;
   const int g = lane >> 4, i16 = lane & 15;
   const int h = it.h, w = it.w, ldc = it.ldc;
   const int64_t c_base = it.c_off + int64_t(it.r0) * ldc + it.c0;
-  const int rb0 = 2 * wr, cb0 = C::MC * wc;
 
   d4 acc[NRA][NCA];
   f4 acc32[NRA][NCA];
@@ -126,13 +132,13 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
     for (int p = 0; p < C::ALD; ++p) {
       const int q = tid + C::NT * p;
       const int s = q / (TM * 4), rem = q - s * (TM * 4);
-      *reinterpret_cast<u4*>(As + buf * C::ASZ + s * TM * C::RS + (rem >> 2) * C::RS + 8 * (rem & 3)) = R.a[p];
+      *reinterpret_cast<u4*>(As + buf * C::ASZ + s * TM * C::RS + C::gpos(rem >> 2, rem & 3)) = R.a[p];
     }
 #pragma unroll
     for (int p = 0; p < C::BLD; ++p) {
       const int q = tid + C::NT * p;
       const int s = q / (TN * 4), rem = q - s * (TN * 4);
-      *reinterpret_cast<u4*>(Bs + buf * C::BSZ + s * TN * C::RS + (rem >> 2) * C::RS + 8 * (rem & 3)) = R.b[p];
+      *reinterpret_cast<u4*>(Bs + buf * C::BSZ + s * TN * C::RS + C::gpos(rem >> 2, rem & 3)) = R.b[p];
     }
   };
 
@@ -175,8 +181,10 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
     const Pos p2 = next(p1);
     bf8 af[3][NRA], bfr[3][NCA];
     if constexpr (NR > 0 && NC > 0) {
-      const uint16_t* as = As + buf * C::ASZ + (16 * rb0 + i16) * C::RS + 8 * g;
-      const uint16_t* bs = Bs + buf * C::BSZ + (16 * cb0 + i16) * C::RS + 8 * g;
+      // rows 16 (rb0 + x) + i16 share (row >> 1) & 3 with i16, so one swizzled offset serves all
+      const int fo = C::gpos(i16, g);
+      const uint16_t* as = As + buf * C::ASZ + 16 * rb0 * C::RS + fo;
+      const uint16_t* bs = Bs + buf * C::BSZ + 16 * cb0 * C::RS + fo;
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
 #pragma unroll
@@ -240,24 +248,31 @@ __device__ __forceinline__ void run_b3(const TileArgs& a, const Item& it, const 
     }
 }
 
-template <int TM, int TN, int NW, bool RESUME, int NR>
-__device__ __forceinline__ void dispatch_nc(int nc, const TileArgs& a, const Item& it,
-                                            const ProductArgs& pa, int wr, int wc, uint16_t* As,
+// Selects the instantiation for the wave's rectangle shape among those the table holds.
+template <int TM, int TN, int NW, bool RESUME, int NA, int NB>
+__device__ __forceinline__ void dispatch_b3(int na, int nb, int rb0, int cb0, const TileArgs& a,
+                                            const Item& it, const ProductArgs& pa, uint16_t* As,
                                             uint16_t* Bs) {
-  constexpr int MC = B3Cfg<TM, TN, NW>::MC;
-  switch (nc) {
-    case 0: run_b3<TM, TN, NW, RESUME, NR, 0>(a, it, pa, wr, wc, As, Bs); break;
-    case 1: run_b3<TM, TN, NW, RESUME, NR, (1 <= MC ? 1 : MC)>(a, it, pa, wr, wc, As, Bs); break;
-    case 2: run_b3<TM, TN, NW, RESUME, NR, (2 <= MC ? 2 : MC)>(a, it, pa, wr, wc, As, Bs); break;
-    case 3: run_b3<TM, TN, NW, RESUME, NR, (3 <= MC ? 3 : MC)>(a, it, pa, wr, wc, As, Bs); break;
-    default: run_b3<TM, TN, NW, RESUME, NR, (4 <= MC ? 4 : MC)>(a, it, pa, wr, wc, As, Bs); break;
+  constexpr int PA = TM / 16, PB = TN / 16;
+  if constexpr (NA > PA) {
+    return;
+  } else if constexpr (NB > PB) {
+    dispatch_b3<TM, TN, NW, RESUME, NA + 1, 0>(na, nb, rb0, cb0, a, it, pa, As, Bs);
+  } else {
+    if constexpr (WaveRects<PA, PB, NW>::used[NA][NB]) {
+      if (na == NA && nb == NB) {
+        run_b3<TM, TN, NW, RESUME, NA, NB>(a, it, pa, rb0, cb0, As, Bs);
+        return;
+      }
+    }
+    dispatch_b3<TM, TN, NW, RESUME, NA, NB + 1>(na, nb, rb0, cb0, a, it, pa, As, Bs);
   }
 }
 
 template <int TM, int TN, int KC, int NW, int OCC, bool RESUME>
 __global__ __launch_bounds__(64 * NW, OCC) void tiles_bf16x3(TileArgs a) {
   using C = B3Cfg<TM, TN, NW>;
-  static_assert(KC == kSliceK && C::MC <= 4, "bf16 variant");
+  static_assert(KC == kSliceK, "bf16 variant");
   __shared__ __attribute__((aligned(16))) uint16_t As[2 * C::ASZ];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2 * C::BSZ];
   const int x = blockIdx.x % kXcds, qx = blockIdx.x / kXcds;
@@ -267,12 +282,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void tiles_bf16x3(TileArgs a) {
   const Item it = uni(a.items[idx]);
   const ProductArgs pa = uni(a.prods ? a.prods[it.product] : a.single);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wr = wave / C::WC, wc = wave % C::WC;
-  const int nr = min(max(((it.h + 15) >> 4) - 2 * wr, 0), 2);
-  const int nc = min(max(((it.w + 15) >> 4) - C::MC * wc, 0), C::MC);
-  if (nr == 0) dispatch_nc<TM, TN, NW, RESUME, 0>(nc, a, it, pa, wr, wc, As, Bs);
-  else if (nr == 1) dispatch_nc<TM, TN, NW, RESUME, 1>(nc, a, it, pa, wr, wc, As, Bs);
-  else dispatch_nc<TM, TN, NW, RESUME, 2>(nc, a, it, pa, wr, wc, As, Bs);
+  // this wave's rectangle of the sub-tile's output blocks (1 <= h <= TM, 1 <= w <= TN)
+  const uint32_t rect = WaveRects<TM / 16, TN / 16, NW>::get((it.h + 15) >> 4, (it.w + 15) >> 4, wave);
+  const int rb0 = int(rect & 0xFF), cb0 = int((rect >> 8) & 0xFF);
+  const int na = int((rect >> 16) & 0xFF), nb = int(rect >> 24);
+  dispatch_b3<TM, TN, NW, RESUME, 0, 0>(na, nb, rb0, cb0, a, it, pa, As, Bs);
   if (a.stamps) {
     __syncthreads();
     if (threadIdx.x == 0) a.stamps[2 * idx + 1] = wall_clock64();
