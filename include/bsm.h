@@ -81,7 +81,10 @@ typedef enum {
   BSM_ORDER_DEFAULT = 0,    /* = BSM_ORDER_INTERLEAVE */
   BSM_ORDER_INTERLEAVE = 1, /* whole C blocks, in C-block order, each to the least-loaded XCD */
   BSM_ORDER_LOCALITY = 2,   /* C-block order cut into 8 runs of equal cost */
-  BSM_ORDER_LPT = 3         /* largest cost first, each task to the least-loaded XCD */
+  BSM_ORDER_LPT = 3,        /* largest cost first, each task to the least-loaded XCD */
+  BSM_ORDER_PATCH = 4       /* rectangles of patch_rows x patch_cols C blocks, each whole to the
+                               least-loaded XCD, so that the tasks an XCD runs at the same time
+                               share few A block rows and B block columns in its L2 */
 } bsm_order;
 
 typedef struct {
@@ -94,6 +97,8 @@ typedef struct {
                              while the operands, alpha and accumulate stay the same */
   int32_t out;            /* bsm_out: element type of C */
   int32_t order;          /* bsm_order */
+  int32_t patch_rows;     /* BSM_ORDER_PATCH: C-block rows per patch, 0 = 4 */
+  int32_t patch_cols;     /* BSM_ORDER_PATCH: C-block columns per patch, 0 = 8 */
   const char* tune_cache; /* NULL, or a file where bsm_autotune looks up and records its choices
                              (lines "signature variant"); the string is copied */
 } bsm_options;
@@ -323,10 +328,13 @@ bsm_status bsm_adam_step(float* d_params, const float* d_grad, float* d_m, float
  * min(P_row, P_col). */
 int64_t bsm_concurrent_iterations(int64_t p_row, int64_t p_col, int64_t K);
 
-/* The tile variants this build provides: variant v (option tile = v + 1) computes C sub-tiles of
- * at most tm[v] x tn[v] elements per workgroup.  Writes up to `cap` entries (either array may be
+/* The tile variants of the FP64 and FP32 forms: variant v (option tile = v + 1) computes C
+ * sub-tiles of at most tm[v] x tn[v] elements per workgroup.  Writes up to `cap` entries (either array may be
  * NULL) and returns the number of variants. */
 int32_t bsm_tile_variants(int32_t* tm, int32_t* tn, int32_t cap);
+
+/* The same for the split-bf16 form's tile variants. */
+int32_t bsm_bf16_tile_variants(int32_t* tm, int32_t* tn, int32_t cap);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char* bsm_last_error(void);

@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "bsm.h")
 FP64, FP32, BF16X3 = 0, 1, 2
 SCHED_FLOPS, SCHED_MLP = 0, 1
 OUT_F64, OUT_F32 = 0, 1
-ORDER_DEFAULT, ORDER_INTERLEAVE, ORDER_LOCALITY, ORDER_LPT = 0, 1, 2, 3
+ORDER_DEFAULT, ORDER_INTERLEAVE, ORDER_LOCALITY, ORDER_LPT, ORDER_PATCH = 0, 1, 2, 3, 4
 
 OK, E_INVALID, E_MISMATCH, E_NOMEM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "OK", -1: "E_INVALID", -2: "E_MISMATCH", -3: "E_NOMEM", -4: "E_HIP",
@@ -36,6 +36,7 @@ class Options(ctypes.Structure):
                 ("k_window", ctypes.c_int64), ("record_timings", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("out", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("patch_rows", ctypes.c_int32), ("patch_cols", ctypes.c_int32),
                 ("tune_cache", ctypes.c_char_p)]
 
 
@@ -69,6 +70,8 @@ def load() -> ctypes.CDLL:
     L.bsm_concurrent_iterations.argtypes = [_i64, _i64, _i64]
     L.bsm_tile_variants.restype = ctypes.c_int32
     L.bsm_tile_variants.argtypes = [_p, _p, ctypes.c_int32]
+    L.bsm_bf16_tile_variants.restype = ctypes.c_int32
+    L.bsm_bf16_tile_variants.argtypes = [_p, _p, ctypes.c_int32]
     L.bsm_plan_create.argtypes = [ctypes.POINTER(_p), _i64, _p, _i64, _p, _i64, _p, _p, _p,
                                   ctypes.POINTER(Options)]
     L.bsm_plan_query.argtypes = [_p, ctypes.POINTER(PlanInfo)]
@@ -144,11 +147,12 @@ def _arr(a, dtype):
 
 
 def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, tile=0,
-            use_graph=0, out=OUT_F64, order=ORDER_DEFAULT, tune_cache=None) -> Options:
+            use_graph=0, out=OUT_F64, order=ORDER_DEFAULT, patch=(0, 0), tune_cache=None) -> Options:
     o = Options()
     load().bsm_options_default(ctypes.byref(o))
     o.precision, o.sched, o.k_window, o.record_timings, o.tile = precision, sched, k_window, record_timings, tile
     o.use_graph, o.out, o.order = use_graph, out, order
+    o.patch_rows, o.patch_cols = int(patch[0]), int(patch[1])
     o.tune_cache = tune_cache.encode() if tune_cache else None
     return o
 
@@ -157,13 +161,14 @@ def concurrent_iterations(p_row: int, p_col: int, K: int) -> int:
     return int(load().bsm_concurrent_iterations(p_row, p_col, K))
 
 
-def tile_variants():
-    """[(tm, tn)] of every tile variant (option tile = index + 1)."""
+def tile_variants(precision=FP64):
+    """[(tm, tn)] of every tile variant of a precision form (option tile = index + 1)."""
     L = load()
-    n = int(L.bsm_tile_variants(None, None, 0))
+    fn = L.bsm_bf16_tile_variants if precision == BF16X3 else L.bsm_tile_variants
+    n = int(fn(None, None, 0))
     tm = np.zeros(n, np.int32)
     tn = np.zeros(n, np.int32)
-    L.bsm_tile_variants(tm.ctypes.data, tn.ctypes.data, n)
+    fn(tm.ctypes.data, tn.ctypes.data, n)
     return list(zip(tm.tolist(), tn.tolist()))
 
 

@@ -30,12 +30,13 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-para
 
 
 TILE_UNIT = "kernels_tile.hip"
+B3_UNIT = "kernels_bf16x3.hip"
 
 
-def tile_variant_ids():
-    """Variant ids of the BSM_TILE_VARIANTS table in csrc/types.hpp."""
+def tile_variant_ids(table="BSM_TILE_VARIANTS"):
+    """Variant ids of a tile-variant table (BSM_TILE_VARIANTS, BSM_BF16_VARIANTS) in csrc/types.hpp."""
     text = open(os.path.join(CSRC, "types.hpp")).read()
-    body = text[text.index("#define BSM_TILE_VARIANTS(X)"):]
+    body = text[text.index(f"#define {table}(X)"):]
     body = body[:body.index("\n\n")]
     return [int(m) for m in re.findall(r"X\((\d+),", body)]
 
@@ -58,7 +59,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         jobs.append((["g++"] + CXX_FLAGS + ["-c", src, "-o", obj], obj))
     for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
-        if os.path.basename(src) == TILE_UNIT:
+        if os.path.basename(src) in (TILE_UNIT, B3_UNIT):
             continue
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         jobs.append(([HIPCC] + HIP_FLAGS + ["-c", src, "-o", obj], obj))
@@ -70,6 +71,12 @@ def build(verbose: bool = False) -> str:
                 obj = os.path.join(BUILD, f"tile_{form}_{vid}_{resume}.o")
                 defs = [f"-DBSM_UNIT_FORM={form}", f"-DBSM_UNIT_ID={vid}", f"-DBSM_UNIT_RESUME={resume}"]
                 jobs.append(([HIPCC] + HIP_FLAGS + defs + ["-c", unit, "-o", obj], obj))
+    unit = os.path.join(CSRC, B3_UNIT)
+    for vid in tile_variant_ids("BSM_BF16_VARIANTS"):
+        for resume in (0, 1):
+            obj = os.path.join(BUILD, f"tile_b3_{vid}_{resume}.o")
+            defs = [f"-DBSM_B3_UNIT_ID={vid}", f"-DBSM_B3_UNIT_RESUME={resume}"]
+            jobs.append(([HIPCC] + HIP_FLAGS + defs + ["-c", unit, "-o", obj], obj))
     # longest first: the tile units dominate
     jobs.sort(key=lambda j: 0 if os.path.basename(j[1]).startswith("tile_") else 1)
     # translation units compile independently (the tile kernels dominate; one per form)

@@ -680,6 +680,8 @@ void bsm_options_default(bsm_options* opt) {
   opt->use_graph = 0;
   opt->out = BSM_OUT_F64;
   opt->order = BSM_ORDER_DEFAULT;
+  opt->patch_rows = 0;
+  opt->patch_cols = 0;
   opt->tune_cache = nullptr;
 }
 
@@ -689,6 +691,14 @@ int32_t bsm_tile_variants(int32_t* tm, int32_t* tn, int32_t cap) {
     if (tn) tn[v] = kVariants[v].tn;
   }
   return kNumVariants;
+}
+
+int32_t bsm_bf16_tile_variants(int32_t* tm, int32_t* tn, int32_t cap) {
+  for (int v = 0; v < kNumBf16Variants && v < cap; ++v) {
+    if (tm) tm[v] = kBf16Variants[v].tm;
+    if (tn) tn[v] = kBf16Variants[v].tn;
+  }
+  return kNumBf16Variants;
 }
 
 int64_t bsm_concurrent_iterations(int64_t p_row, int64_t p_col, int64_t K) {
@@ -720,8 +730,12 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
     case BSM_ORDER_INTERLEAVE: cfg.order = ORDER_INTERLEAVE; break;
     case BSM_ORDER_LOCALITY: cfg.order = ORDER_LOCALITY; break;
     case BSM_ORDER_LPT: cfg.order = ORDER_LPT; break;
+    case BSM_ORDER_PATCH: cfg.order = ORDER_PATCH; break;
     default: return fail(BSM_E_INVALID, "unknown task order");
   }
+  if (o.patch_rows < 0 || o.patch_cols < 0) return fail(BSM_E_INVALID, "patch sizes must be >= 0");
+  if (o.patch_rows > 0) cfg.patch_r = o.patch_rows;
+  if (o.patch_cols > 0) cfg.patch_c = o.patch_cols;
   if (o.tune_cache) cfg.tune_cache = o.tune_cache;
   bsm_plan* p = new (std::nothrow) bsm_plan;
   if (!p) return fail(BSM_E_NOMEM, "host allocation failed");

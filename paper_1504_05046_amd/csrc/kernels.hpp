@@ -43,6 +43,12 @@ hipError_t launch_tiles_f32(int variant, int64_t grid, const TileArgs& args, hip
   hipError_t launch_tile_unit_1_##ID##_1(int64_t, const TileArgs&, hipStream_t);
 BSM_TILE_VARIANTS(BSM_DECLARE_TILE_UNITS)
 #undef BSM_DECLARE_TILE_UNITS
+// The split-bf16 tile kernel likewise (kernels_bf16x3.hip, once per variant ID and window kind R).
+#define BSM_DECLARE_B3_UNITS(ID, TM, TN, KC, NW, OCC)                                  \
+  hipError_t launch_b3_unit_##ID##_0(int64_t, const TileArgs&, hipStream_t);          \
+  hipError_t launch_b3_unit_##ID##_1(int64_t, const TileArgs&, hipStream_t);
+BSM_BF16_VARIANTS(BSM_DECLARE_B3_UNITS)
+#undef BSM_DECLARE_B3_UNITS
 
 // dst[i] = src[i] rounded to FP32 for i < n.
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t stream);

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <tuple>
 
 #include "../../include/bsm.h"
 
@@ -101,6 +102,25 @@ static std::vector<std::vector<size_t>> deal(const HostPlan& p, const std::vecto
       bins[size_t(x)].push_back(q);
       load[size_t(x)] += cost[q];
     }
+  } else if (p.cfg.order == ORDER_PATCH) {
+    // patches of patch_r x patch_c C blocks, in row-major patch order per product; each whole
+    // patch to the least-loaded XCD; inside a patch the canonical C-block order (stable sort)
+    const int pr = std::max(1, p.cfg.patch_r), pc = std::max(1, p.cfg.patch_c);
+    auto key = [&](size_t q) {
+      return std::make_tuple(p.items[q].product, p.meta[q].ci / pr, p.meta[q].cj / pc);
+    };
+    std::vector<size_t> o(idx);
+    std::stable_sort(o.begin(), o.end(), [&](size_t a, size_t b) { return key(a) < key(b); });
+    size_t u = 0;
+    while (u < o.size()) {
+      size_t e = u + 1;
+      double c = cost[o[u]];
+      while (e < o.size() && key(o[e]) == key(o[u])) c += cost[o[e++]];
+      int x = int(std::min_element(load.begin(), load.end()) - load.begin());
+      for (size_t r = u; r < e; ++r) bins[size_t(x)].push_back(o[r]);
+      load[size_t(x)] += c;
+      u = e;
+    }
   } else if (p.cfg.order == ORDER_INTERLEAVE) {
     // whole C blocks (consecutive tasks with the same C offset) dealt to the least-loaded XCD in
     // C-block order
@@ -151,34 +171,34 @@ void schedule(HostPlan& p, const std::vector<double>& cost_in) {
       return x.c0 < y.c0;
     });
     std::vector<Item> it2(n);
-    std::vector<uint8_t> v2(n);
+    std::vector<ItemMeta> v2(n);
     std::vector<double> c2(n);
     std::vector<float> f2(p.features.size());
     for (size_t q = 0; q < n; ++q) {
       it2[q] = p.items[perm[q]];
-      v2[q] = p.ivar[perm[q]];
+      v2[q] = p.meta[perm[q]];
       c2[q] = cost_in[perm[q]];
       for (int f = 0; f < 5; ++f) f2[q * 5 + size_t(f)] = p.features[perm[q] * 5 + size_t(f)];
     }
     p.items.swap(it2);
-    p.ivar.swap(v2);
+    p.meta.swap(v2);
     p.features.swap(f2);
     cost.swap(c2);
   }
   // one segment per tile variant in use, each dealt to the XCDs on its own
   std::vector<Item> items;
-  std::vector<uint8_t> vars;
+  std::vector<ItemMeta> metas;
   std::vector<double> c2;
   std::vector<float> f2;
   items.reserve(n);
-  vars.reserve(n);
+  metas.reserve(n);
   c2.reserve(n);
   f2.reserve(p.features.size());
   p.segs.clear();
   for (int v = 0; v < 256; ++v) {
     std::vector<size_t> idx;
     for (size_t q = 0; q < n; ++q)
-      if (p.ivar[q] == v) idx.push_back(q);
+      if (p.meta[q].var == v) idx.push_back(q);
     if (idx.empty()) continue;
     Segment g;
     g.variant = v;
@@ -189,7 +209,7 @@ void schedule(HostPlan& p, const std::vector<double>& cost_in) {
       g.xcd_begin[x] = int32_t(items.size()) - g.begin;
       for (size_t q : bins[size_t(x)]) {
         items.push_back(p.items[q]);
-        vars.push_back(p.ivar[q]);
+        metas.push_back(p.meta[q]);
         c2.push_back(cost[q]);
         for (int f = 0; f < 5; ++f) f2.push_back(p.features[q * 5 + size_t(f)]);
       }
@@ -201,7 +221,7 @@ void schedule(HostPlan& p, const std::vector<double>& cost_in) {
     p.segs.push_back(g);
   }
   p.items.swap(items);
-  p.ivar.swap(vars);
+  p.meta.swap(metas);
   p.cost.swap(c2);
   p.features.swap(f2);
 }
@@ -216,7 +236,7 @@ void cut_items(HostPlan& p, const int class_var[kSizeClasses]) {
   const bool bf16 = p.cfg.precision == 2;
   std::vector<std::pair<int, int>> rs, cs;
   p.items.clear();
-  p.ivar.clear();
+  p.meta.clear();
   p.features.clear();
   for (int c = 0; c < kSizeClasses; ++c) p.class_var[c] = class_var[c];
   for (const CBlock& cb : p.cblocks) {
@@ -238,7 +258,7 @@ void cut_items(HostPlan& p, const int class_var[kSizeClasses]) {
         it.ldm = uint16_t(cb.m);
         it.product = 0;
         p.items.push_back(it);
-        p.ivar.push_back(uint8_t(variant));
+        p.meta.push_back(ItemMeta{cb.ci, cb.cj, variant});
         p.features.push_back(std::log(float(it.h)));
         p.features.push_back(std::log(float(it.w)));
         p.features.push_back(std::log(float(std::max(1.0, cb.sk))));
@@ -264,7 +284,8 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   if (cfg.k_window < 0) return "negative k_window";
   if (cfg.tile < 0 || cfg.tile > (cfg.precision == 2 ? kNumBf16Variants : kNumVariants))
     return "unknown tile variant";
-  if (cfg.order < ORDER_LOCALITY || cfg.order > ORDER_INTERLEAVE) return "unknown task order";
+  if (cfg.order < ORDER_LOCALITY || cfg.order > ORDER_PATCH) return "unknown task order";
+  if (cfg.patch_r < 1 || cfg.patch_c < 1) return "patch sizes must be >= 1";
 
   p.cfg = cfg;
   p.M = M; p.K = K; p.N = N;
@@ -370,12 +391,12 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
       }
       int m = int(p.rows[size_t(i)]), n = int(p.cols[size_t(j)]);
       p.useful_flops += 2.0 * m * n * sk;
-      p.cblocks.push_back(CBlock{co, uint32_t(tb), uint32_t(tc), m, n, sk});
+      p.cblocks.push_back(CBlock{co, uint32_t(tb), uint32_t(tc), m, n, int32_t(i), int32_t(j), sk});
     }
   }
   p.k_total = 0;
   for (int64_t k = 0; k < K; ++k) p.k_total += double(p.inner[size_t(k)]);
-  cut_items(p, bf16 ? 0 : (cfg.tile > 0 ? cfg.tile - 1 : kDefaultVariant));
+  cut_items(p, cfg.tile > 0 ? cfg.tile - 1 : (bf16 ? kDefaultBf16Variant : kDefaultVariant));
   // S5: k-windows (0 = all K inner blocks in flight at once)
   p.k_window_eff = (cfg.k_window == 0 || cfg.k_window >= K) ? std::max<int64_t>(K, 1) : cfg.k_window;
   p.windows = K > 0 ? (K + p.k_window_eff - 1) / p.k_window_eff : 1;
@@ -413,7 +434,7 @@ std::string merge_plans(HostPlan& out, const std::vector<const HostPlan*>& parts
       it.product = uint32_t(q);
       out.items.push_back(it);
     }
-    out.ivar.insert(out.ivar.end(), p.ivar.begin(), p.ivar.end());
+    out.meta.insert(out.meta.end(), p.meta.begin(), p.meta.end());
     out.features.insert(out.features.end(), p.features.begin(), p.features.end());
     out.useful_flops += p.useful_flops;
     out.c_blocks += p.c_blocks;

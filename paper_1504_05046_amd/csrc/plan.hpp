@@ -19,12 +19,15 @@ constexpr int kNumVariants = int(sizeof(kVariants) / sizeof(kVariants[0]));
 constexpr int kDefaultVariant = 0;  // 128 x 128, 8 waves
 constexpr Variant kBf16Variants[] = {BSM_BF16_VARIANTS(BSM_VARIANT_ROW)};
 constexpr int kNumBf16Variants = int(sizeof(kBf16Variants) / sizeof(kBf16Variants[0]));
+constexpr int kDefaultBf16Variant = 0;
 #undef BSM_VARIANT_ROW
 
 // Task order: LOCALITY keeps C-block order and cuts it into one contiguous run per XCD; LPT sorts
 // by cost and bins greedily; INTERLEAVE deals whole C blocks, in C-block order, each to the
-// least-loaded XCD, so that all XCDs work on the same region of C at the same time.
-enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1, ORDER_INTERLEAVE = 2 };
+// least-loaded XCD, so that all XCDs work on the same region of C at the same time; PATCH deals
+// whole rectangles of patch_r x patch_c C blocks, so that the tasks an XCD runs together share
+// few A block rows and B block columns in its L2.
+enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1, ORDER_INTERLEAVE = 2, ORDER_PATCH = 3 };
 
 struct PlanConfig {
   int precision = 0;
@@ -34,6 +37,7 @@ struct PlanConfig {
   int tile = 0;       // 0 = auto, else variant id + 1
   int order = ORDER_INTERLEAVE;
   int out_f32 = 0;    // C holds FP32 elements
+  int patch_r = 4, patch_c = 8;  // C blocks per patch (ORDER_PATCH)
   std::string tune_cache;  // autotuner choices file ("" = none)
 };
 
@@ -59,7 +63,15 @@ struct CBlock {
   int64_t c_off;
   uint32_t tri_begin, tri_count;
   int32_t m, n;
+  int32_t ci, cj;  // block row and column of C
   double sk;  // summed inner size of the k-list
+};
+
+// Host-side facts about a task the device does not need: its C block's position and its tile
+// variant.
+struct ItemMeta {
+  int32_t ci, cj;
+  int32_t var;
 };
 
 struct HostPlan {
@@ -77,7 +89,7 @@ struct HostPlan {
   double k_total = 0;            // summed inner size of all K blocks
   int class_var[kSizeClasses] = {0, 0, 0, 0};  // tile variant of each size class
   std::vector<Item> items;       // tasks in execution order: segment by segment, XCD by XCD
-  std::vector<uint8_t> ivar;     // tile variant of items[q]
+  std::vector<ItemMeta> meta;    // position and tile variant of items[q]
   std::vector<double> cost;      // scheduler cost of items[q]
   std::vector<float> features;   // 5 per item: log h, log w, log sum_k, log #k, density
   std::vector<Segment> segs;     // one per tile variant in use, in variant order
@@ -104,7 +116,7 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
                        const uint64_t* a_bits, const uint64_t* b_bits, const PlanConfig& cfg,
                        int* code);
 
-// Cut every C block into tasks with the tile variant of its size class (replaces items, ivar and
+// Cut every C block into tasks with the tile variant of its size class (replaces items, meta and
 // features; sets p.class_var).
 void cut_items(HostPlan& p, const int class_var[kSizeClasses]);
 // The same variant for every size class.

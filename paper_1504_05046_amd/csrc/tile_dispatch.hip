@@ -1,5 +1,5 @@
-// Launch of the FP64/FP32 tile kernel: picks the instantiation of a variant and window kind (the
-// instantiations live in separate translation units, see kernels_tile.hip).
+// Launch of the tile kernels: picks the instantiation of a variant and window kind (the
+// instantiations live in separate translation units, see kernels_tile.hip and kernels_bf16x3.hip).
 #include "kernels.hpp"
 
 namespace bsm {
@@ -26,6 +26,20 @@ hipError_t launch_tiles_f32(int variant, int64_t grid, const TileArgs& args, hip
   if (grid <= 0) return hipSuccess;
   switch (variant) {
     BSM_TILE_VARIANTS(BSM_CASE_F32)
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+#define BSM_CASE_B3(ID, TM, TN, KC, NW, OCC)                                         \
+  case ID:                                                                         \
+    return args.win_first ? launch_b3_unit_##ID##_0(grid, args, stream)            \
+                          : launch_b3_unit_##ID##_1(grid, args, stream);
+
+hipError_t launch_tiles_bf16x3(int variant, int64_t grid, const TileArgs& args, hipStream_t stream) {
+  if (grid <= 0) return hipSuccess;
+  switch (variant) {
+    BSM_BF16_VARIANTS(BSM_CASE_B3)
     default:
       return hipErrorInvalidValue;
   }

@@ -25,9 +25,13 @@ constexpr int kXcds = 8;                       // MI355X: 8 accelerator dies, ea
   X(2, 64, 64, 16, 4, 3)        \
   X(3, 32, 32, 16, 4, 4)
 
-// Split-bf16 tile variants (same fields; the k-chunk is one 32-deep bf16 MFMA step).
+// Split-bf16 tile variants (same fields; the k-chunk is one 32-deep bf16 MFMA step): 128 x 128
+// with 8 waves (two per SIMD) or 4 waves (one per SIMD, 4 x 4 blocks per wave), both with 144 KB
+// of LDS, and 64 x 64 with two workgroups per CU.
 #define BSM_BF16_VARIANTS(X) \
-  X(0, 128, 128, 32, 8, 2)
+  X(0, 128, 128, 32, 8, 2)   \
+  X(1, 128, 128, 32, 4, 1)   \
+  X(2, 64, 64, 32, 4, 2)
 
 // Slice planes of the split-bf16 form: each block with its inner size padded to a multiple of 32
 // (zeros), A blocks as rows x s32 and B blocks transposed (cols x s32), so that both MFMA operands

@@ -231,8 +231,11 @@ def test_options_validated():
     ok_bits = gen.pack_bits(np.ones((1, 1), bool))
     _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], ok_bits, ok_bits, out=2))
     _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], ok_bits, ok_bits, order=9))
-    for order in (bsm.ORDER_DEFAULT, bsm.ORDER_INTERLEAVE, bsm.ORDER_LOCALITY, bsm.ORDER_LPT):
+    for order in (bsm.ORDER_DEFAULT, bsm.ORDER_INTERLEAVE, bsm.ORDER_LOCALITY, bsm.ORDER_LPT,
+                  bsm.ORDER_PATCH):
         bsm.Plan([1], [1], [1], ok_bits, ok_bits, order=order).close()
+    bsm.Plan([1], [1], [1], ok_bits, ok_bits, order=bsm.ORDER_PATCH, patch=(2, 16)).close()
+    _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], ok_bits, ok_bits, order=bsm.ORDER_PATCH, patch=(-1, 2)))
     plan = bsm.Plan([1], [1], [1], ok_bits, ok_bits, out=bsm.OUT_F32, tune_cache="/tmp/x")
     assert plan.info().out == bsm.OUT_F32
     # the binding wants an FP32 C for such a plan
@@ -288,3 +291,12 @@ def test_size_classes_and_segments():
     assert plan.info().tile == 0
     _expect(bsm.E_INVALID, lambda: plan.set_tile_classes([0, 1, 1, 1]))
     _expect(bsm.E_INVALID, lambda: plan.set_tile_classes([1, 1, 1, 5]))
+
+
+def test_patch_order_keeps_the_task_set():
+    """The patch order deals whole rectangles of C blocks; it reorders tasks, never changes them."""
+    p = gen.random_problem(47, 9, 6, 11, 8, 200, 0.6, 0.6)
+    base = bsm.Plan.from_problem(p).features()
+    pat = bsm.Plan.from_problem(p, order=bsm.ORDER_PATCH, patch=(2, 3)).features()
+    assert not np.array_equal(base, pat)
+    assert np.array_equal(np.sort(base.view(np.int32), axis=0), np.sort(pat.view(np.int32), axis=0))

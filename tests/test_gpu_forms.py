@@ -153,3 +153,21 @@ def test_timings_recorded():
     with pytest.raises(bsm.BsmError) as ei:
         plan2.timings()
     assert ei.value.code == bsm.E_STATE
+
+
+@pytest.mark.parametrize("tile", range(1, len(bsm.tile_variants(bsm.BF16X3)) + 1))
+def test_bf16x3_every_tile_variant(tile):
+    """Every split-bf16 tile variant: integers bit-exact, random values within the gate, also with
+    k-windows (resumed partial sums) and ragged sizes."""
+    _say(f"[bf16x3 variant] tile={tile}")
+    q = gen.integer_problem(1800 + tile, 6, 7, 5, 1, 200, 0.6, 0.6)
+    got, plan = run(q, precision=bsm.BF16X3, tile=tile)
+    assert plan.info().tile == tile
+    assert np.array_equal(got, ref(q))
+    p = gen.random_problem(1810 + tile, 8, 9, 7, 1, 260, 0.5, 0.5)
+    got, plan = run(p, precision=bsm.BF16X3, tile=tile)
+    plan.verify()
+    assert rel_fro(got, ref(p)) <= 1e-6
+    got2, plan2 = run(p, precision=bsm.BF16X3, tile=tile, k_window=3)
+    plan2.verify()
+    assert np.array_equal(got, got2)

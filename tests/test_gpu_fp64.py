@@ -91,11 +91,14 @@ def test_every_tile_variant(tile):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("order", [bsm.ORDER_LOCALITY, bsm.ORDER_LPT, bsm.ORDER_INTERLEAVE])
-def test_task_orders_bitwise_identical(order):
+@pytest.mark.parametrize("order,patch", [(bsm.ORDER_LOCALITY, (0, 0)), (bsm.ORDER_LPT, (0, 0)),
+                                         (bsm.ORDER_INTERLEAVE, (0, 0)), (bsm.ORDER_PATCH, (0, 0)),
+                                         (bsm.ORDER_PATCH, (3, 2))])
+def test_task_orders_bitwise_identical(order, patch):
     p = gen.random_problem(300, 8, 8, 8, 20, 200, 0.5, 0.5)
     a, _ = run_gpu(p)
-    b, _ = run_gpu(p, order=order)
+    b, plan = run_gpu(p, order=order, patch=patch)
+    plan.verify()
     assert np.array_equal(a, b)
 
 
