@@ -99,6 +99,11 @@ typedef struct {
   int32_t order;          /* bsm_order */
   int32_t patch_rows;     /* BSM_ORDER_PATCH: C-block rows per patch, 0 = 4 */
   int32_t patch_cols;     /* BSM_ORDER_PATCH: C-block columns per patch, 0 = 8 */
+  int32_t device_klists;  /* where C blocks' k-lists (their block triples) are built:
+                              0 = on the host while they fit a host list of 2^28 triples, else on
+                              the device; -1 = always on the host; 1 = always on the device; n >= 2
+                              = always on the device, in batches of at most n triples (the device
+                              buffer for them; the default batch is 2^27 triples, 2 GiB) */
   const char* tune_cache; /* NULL, or a file where bsm_autotune looks up and records its choices
                              (lines "signature variant"); the string is copied */
 } bsm_options;
@@ -115,6 +120,7 @@ typedef struct {
   int32_t tile;            /* tile variant every task uses (variant id + 1), or 0 when the size
                               classes use different variants (bsm_plan_tile_classes) */
   int32_t out;             /* bsm_out: element type of C */
+  int32_t device_klists;   /* 1: the k-lists are built on the device, batch by batch */
 } bsm_plan_info;
 
 typedef struct bsm_batch bsm_batch;
@@ -130,7 +136,11 @@ void bsm_options_default(bsm_options* opt);
  * process's part of C).  Host-only work: validates the tilings and shapes, forms the C-shape (the
  * boolean product of the two shapes), the packed offsets, the task list (each present C block,
  * cut into sub-tiles; its k-list = the k with A_ik and B_kj present, in ascending order) and the
- * task order.  Device memory is allocated at the first execute.  All arguments are host memory
+ * task order.  When the k-lists are built on the device (option device_klists), the host keeps
+ * only each C block's k-list length and summed inner size, counted from the shape words, plus
+ * the offset tables, and the tasks are cut into batches whose triples fit the device buffer; each
+ * execute then builds a batch's triples on the device right before the batch's tile launch.
+ * Device memory is allocated at the first execute.  All arguments are host memory
  * and are copied; opt may be NULL (defaults).  Errors: BSM_E_INVALID for a null pointer, a
  * negative count, a block size outside [1, 65535], a padding bit set or an unknown option;
  * BSM_E_NOMEM if the host runs out or a buffer exceeds 2^48 elements. */
@@ -173,7 +183,8 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
  * calls that overlap on different streams of one GPU race and give wrong results.  Execution
  * counters and per-task clocks are not kept (bsm_plan_verify does not cover these calls), and the
  * plan's graph option is ignored.  Errors: as bsm_execute; BSM_E_NOMEM (checked before any device
- * work) if the plan needs more than the 64 MiB, with the size in bsm_last_error(). */
+ * work) if the plan needs more than the 64 MiB, with the size in bsm_last_error();
+ * BSM_E_UNSUPPORTED for a plan whose k-lists are built on the device. */
 bsm_status bsm_execute_static(const bsm_plan* plan, double alpha, const double* dA,
                               const double* dB, void* dC, int accumulate, void* stream);
 

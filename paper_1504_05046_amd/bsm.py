@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("out", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("patch_rows", ctypes.c_int32), ("patch_cols", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p)]
+                ("device_klists", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -48,7 +48,7 @@ class PlanInfo(ctypes.Structure):
                 ("triples", ctypes.c_int64), ("tasks", ctypes.c_int64),
                 ("useful_flops", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
                 ("k_windows", ctypes.c_int64), ("tile", ctypes.c_int32),
-                ("out", ctypes.c_int32)]
+                ("out", ctypes.c_int32), ("device_klists", ctypes.c_int32)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -147,12 +147,14 @@ def _arr(a, dtype):
 
 
 def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, tile=0,
-            use_graph=0, out=OUT_F64, order=ORDER_DEFAULT, patch=(0, 0), tune_cache=None) -> Options:
+            use_graph=0, out=OUT_F64, order=ORDER_DEFAULT, patch=(0, 0), device_klists=0,
+            tune_cache=None) -> Options:
     o = Options()
     load().bsm_options_default(ctypes.byref(o))
     o.precision, o.sched, o.k_window, o.record_timings, o.tile = precision, sched, k_window, record_timings, tile
     o.use_graph, o.out, o.order = use_graph, out, order
     o.patch_rows, o.patch_cols = int(patch[0]), int(patch[1])
+    o.device_klists = int(device_klists)
     o.tune_cache = tune_cache.encode() if tune_cache else None
     return o
 

@@ -40,7 +40,9 @@ static bsm_status hip_fail(hipError_t e, const char* what) {
 // clocks.
 struct TaskSet {
   Item* items = nullptr;
-  Triple* tri = nullptr;
+  Triple* tri = nullptr;     // the host list, or the buffer device-built k-lists go into
+  KJob* jobs = nullptr;      // device-built k-lists: the C blocks of every segment
+  size_t n_jobs = 0;
   uint64_t* stamps = nullptr;
   uint32_t* done = nullptr;  // executions of each task since the last upload
   size_t n_items = 0, n_tri = 0;
@@ -49,14 +51,15 @@ struct TaskSet {
   bool used = false;         // work that reads these buffers may be queued
 
   void release() {
-    for (void* ptr : {static_cast<void*>(items), static_cast<void*>(tri),
+    for (void* ptr : {static_cast<void*>(items), static_cast<void*>(tri), static_cast<void*>(jobs),
                       static_cast<void*>(stamps), static_cast<void*>(done)})
       if (ptr) (void)hipFree(ptr);
     items = nullptr;
     tri = nullptr;
+    jobs = nullptr;
     stamps = nullptr;
     done = nullptr;
-    n_items = n_tri = 0;
+    n_items = n_tri = n_jobs = 0;
   }
 
   // (Re-)upload tasks (always) and triples (when their count changed); clocks if asked for.
@@ -79,15 +82,25 @@ struct TaskSet {
     if (n_items)
       BSM_HIP(hipMemcpy(items, h.items.data(), n_items * sizeof(Item), hipMemcpyHostToDevice),
               "hipMemcpy(tasks)");
-    if (h.tri.size() != n_tri) {
+    const size_t want_tri = h.dev_klists ? size_t(h.tri_capacity) : h.tri.size();
+    if (want_tri != n_tri) {
       if (tri) (void)hipFree(tri);
       tri = nullptr;
-      n_tri = h.tri.size();
+      n_tri = want_tri;
       if (n_tri) BSM_HIP(hipMalloc(&tri, n_tri * sizeof(Triple)), "hipMalloc(triples)");
     }
-    if (n_tri)
+    if (n_tri && !h.dev_klists)
       BSM_HIP(hipMemcpy(tri, h.tri.data(), n_tri * sizeof(Triple), hipMemcpyHostToDevice),
               "hipMemcpy(triples)");
+    if (h.jobs.size() != n_jobs) {
+      if (jobs) (void)hipFree(jobs);
+      jobs = nullptr;
+      n_jobs = h.jobs.size();
+      if (n_jobs) BSM_HIP(hipMalloc(&jobs, n_jobs * sizeof(KJob)), "hipMalloc(k-list jobs)");
+    }
+    if (n_jobs)
+      BSM_HIP(hipMemcpy(jobs, h.jobs.data(), n_jobs * sizeof(KJob), hipMemcpyHostToDevice),
+              "hipMemcpy(k-list jobs)");
     if (with_stamps && !stamps && n_items)
       BSM_HIP(hipMalloc(&stamps, n_items * 16), "hipMalloc(clocks)");
     timed = false;
@@ -171,6 +184,13 @@ struct bsm_plan {
   SplitBlock* d_split_a = nullptr;  // split-bf16 form: block tables of the split pass
   SplitBlock* d_split_b = nullptr;
   double* d_partial = nullptr;      // raw sums between k-windows (laid out like C)
+  // device-built k-lists: shapes, offset tables and inner sizes
+  uint64_t* d_abits = nullptr;
+  uint64_t* d_btbits = nullptr;
+  int64_t* d_atab = nullptr;
+  int64_t* d_bttab = nullptr;
+  int64_t* d_inner = nullptr;
+  DevKlists dk{};
   GraphCache gc;
   int device = -1;
   bool ready = false;               // device buffers allocated
@@ -227,6 +247,22 @@ static bsm_status prepare(bsm_plan* p) {
   }
   if (h.windows > 1 && h.c_elems > 0)
     BSM_HIP(hipMalloc(&p->d_partial, size_t(h.c_elems) * 8), "hipMalloc(partial)");
+  if (h.dev_klists) {
+    auto up = [&](auto** dst, const auto& v, const char* what) -> bsm_status {
+      const size_t bytes = v.size() * sizeof(v[0]);
+      if (!bytes) return BSM_OK;
+      BSM_HIP(hipMalloc(dst, bytes), what);
+      BSM_HIP(hipMemcpy(*dst, v.data(), bytes, hipMemcpyHostToDevice), what);
+      return BSM_OK;
+    };
+    bsm_status s2;
+    if ((s2 = up(&p->d_abits, h.a_bits, "k-list tables")) != BSM_OK) return s2;
+    if ((s2 = up(&p->d_btbits, h.bt_bits, "k-list tables")) != BSM_OK) return s2;
+    if ((s2 = up(&p->d_atab, h.a_tab, "k-list tables")) != BSM_OK) return s2;
+    if ((s2 = up(&p->d_bttab, h.bt_tab, "k-list tables")) != BSM_OK) return s2;
+    if ((s2 = up(&p->d_inner, h.inner, "k-list tables")) != BSM_OK) return s2;
+    p->dk = DevKlists{p->d_abits, p->d_btbits, h.wk, p->d_atab, p->d_bttab, h.K, p->d_inner};
+  }
   p->device = dev;
   p->ready = true;
   return BSM_OK;
@@ -286,7 +322,7 @@ static hipError_t launch_form(int precision, int variant, int64_t grid, const Ti
 // S7/S8 (and S5): the tile kernel over a task list, once per k-window.
 static bsm_status enqueue_tiles(const HostPlan& h, TaskSet& ts, const ProductArgs* prods,
                                 const ProductArgs& single, int accumulate, int skip_task,
-                                hipStream_t s) {
+                                hipStream_t s, const DevKlists* dk = nullptr) {
   if (h.items.empty()) return BSM_OK;
   // k-windows of I consecutive inner blocks, issued in order on the stream; each window resumes
   // from the raw FP64 sums of the previous one, so C does not depend on I.  Within a window, one
@@ -294,6 +330,11 @@ static bsm_status enqueue_tiles(const HostPlan& h, TaskSet& ts, const ProductArg
   const int64_t I = h.k_window_eff;
   for (int64_t wdx = 0; wdx < h.windows; ++wdx) {
     for (const Segment& g : h.segs) {
+      if (h.dev_klists) {
+        // this batch's k-lists into the triple buffer (after the previous batch's tiles)
+        if (!dk) return fail(BSM_E_STATE, "device k-lists without their tables");
+        BSM_HIP(launch_fill_klists(ts.jobs + g.job_begin, g.job_count, *dk, ts.tri, s), "k-list fill");
+      }
       TileArgs a{};
       a.items = ts.items + g.begin;
       a.tri = ts.tri;
@@ -626,6 +667,8 @@ bsm_status bsm_execute_static(const bsm_plan* plan, double alpha, const double* 
   const HostPlan& h = plan->hp;
   bsm_status st = check_operands(h, dA, dB, dC, accumulate);
   if (st != BSM_OK) return st;
+  if (h.dev_klists)
+    return fail(BSM_E_UNSUPPORTED, "bsm_execute_static needs the k-lists in the plan's host list");
   const StaticLayout L = static_layout(h);
   if (L.total > kStaticScratchBytes)
     return fail(BSM_E_NOMEM, "the plan needs " + std::to_string(L.total) +
@@ -682,6 +725,7 @@ void bsm_options_default(bsm_options* opt) {
   opt->order = BSM_ORDER_DEFAULT;
   opt->patch_rows = 0;
   opt->patch_cols = 0;
+  opt->device_klists = 0;
   opt->tune_cache = nullptr;
 }
 
@@ -736,6 +780,7 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
   if (o.patch_rows < 0 || o.patch_cols < 0) return fail(BSM_E_INVALID, "patch sizes must be >= 0");
   if (o.patch_rows > 0) cfg.patch_r = o.patch_rows;
   if (o.patch_cols > 0) cfg.patch_c = o.patch_cols;
+  cfg.device_klists = o.device_klists;
   if (o.tune_cache) cfg.tune_cache = o.tune_cache;
   bsm_plan* p = new (std::nothrow) bsm_plan;
   if (!p) return fail(BSM_E_NOMEM, "host allocation failed");
@@ -768,10 +813,13 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   info->a_elems = h.a_elems;
   info->b_elems = h.b_elems;
   info->c_elems = h.c_elems;
-  info->triples = int64_t(h.tri.size());
+  info->triples = h.triples_total;
   info->tasks = int64_t(h.items.size());
   info->useful_flops = h.useful_flops;
   int64_t ws = int64_t(h.items.size() * sizeof(Item) + h.tri.size() * sizeof(Triple));
+  if (h.dev_klists)
+    ws += h.tri_capacity * int64_t(sizeof(Triple)) + int64_t(h.jobs.size() * sizeof(KJob)) +
+          int64_t((h.a_bits.size() + h.bt_bits.size()) * 8 + (h.a_tab.size() + h.bt_tab.size() + h.inner.size()) * 8);
   if (h.cfg.precision == BSM_FP32) ws += (h.a_elems + h.b_elems) * 4;
   if (h.cfg.precision == BSM_BF16X3)
     ws += (h.a_elems32 + h.b_elems32) * 6 + int64_t((h.split_a.size() + h.split_b.size()) * sizeof(SplitBlock));
@@ -781,6 +829,7 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   info->k_windows = h.windows;
   info->tile = reported_tile(h);
   info->out = h.cfg.out_f32 ? BSM_OUT_F32 : BSM_OUT_F64;
+  info->device_klists = h.dev_klists ? 1 : 0;
   return BSM_OK;
 }
 
@@ -816,7 +865,7 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
     pa.c_f32 = h.cfg.out_f32;
     pa.P = plan->d_partial;
     pa.alpha = alpha;
-    return enqueue_tiles(h, plan->ts, nullptr, pa, accumulate, plan->skip_task, q);
+    return enqueue_tiles(h, plan->ts, nullptr, pa, accumulate, plan->skip_task, q, &plan->dk);
   };
   if (!plan->use_graph) {
     st = body(s);
@@ -895,7 +944,7 @@ bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, void
       pa.c_f32 = h.cfg.out_f32;
       pa.P = plan->d_partial;
       pa.alpha = 1.0;
-      return enqueue_tiles(h, plan->ts, nullptr, pa, 0, -1, q);
+      return enqueue_tiles(h, plan->ts, nullptr, pa, 0, -1, q, &plan->dk);
     };
     auto timeit = [&](float* ms) {
       plan->ts.used = true;
@@ -940,7 +989,10 @@ bsm_status bsm_plan_destroy(bsm_plan* plan) {
     plan->gc.release();
     plan->ts.release();
     for (void* ptr : {plan->d_opA, plan->d_opB, static_cast<void*>(plan->d_split_a),
-                      static_cast<void*>(plan->d_split_b), static_cast<void*>(plan->d_partial)})
+                      static_cast<void*>(plan->d_split_b), static_cast<void*>(plan->d_partial),
+                      static_cast<void*>(plan->d_abits), static_cast<void*>(plan->d_btbits),
+                      static_cast<void*>(plan->d_atab), static_cast<void*>(plan->d_bttab),
+                      static_cast<void*>(plan->d_inner)})
       if (ptr) (void)hipFree(ptr);
   }
   delete plan;

@@ -50,6 +50,21 @@ BSM_TILE_VARIANTS(BSM_DECLARE_TILE_UNITS)
 BSM_BF16_VARIANTS(BSM_DECLARE_B3_UNITS)
 #undef BSM_DECLARE_B3_UNITS
 
+// Device tables from which device-built k-lists are made (see klist.hip).
+struct DevKlists {
+  const uint64_t* a_bits;   // A's shape, M x wk words
+  const uint64_t* bt_bits;  // B's shape transposed, N x wk words
+  int64_t wk;
+  const int64_t* a_tab;     // M x K packed offsets of A_ik (form's layout)
+  const int64_t* bt_tab;    // N x K packed offsets of B_kj, at [j K + k]
+  int64_t K;
+  const int64_t* inner;     // inner block sizes
+};
+
+// Writes the k-list triples of njobs C blocks (KJob) into tri.
+hipError_t launch_fill_klists(const KJob* jobs, int64_t njobs, const DevKlists& d, Triple* tri,
+                              hipStream_t stream);
+
 // dst[i] = src[i] rounded to FP32 for i < n.
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t stream);
 

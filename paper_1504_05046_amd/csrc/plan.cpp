@@ -7,7 +7,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <numeric>
+#include <thread>
 #include <tuple>
 
 #include "../../include/bsm.h"
@@ -77,13 +79,106 @@ static void cut_dim(int m, int per, std::vector<std::pair<int, int>>& out) {
 
 std::vector<double> flop_costs(const HostPlan& p) {
   std::vector<double> c(p.items.size());
-  for (size_t q = 0; q < p.items.size(); ++q) {
-    const Item& it = p.items[q];
-    double sk = 0;
-    for (uint32_t t = 0; t < it.tri_count; ++t) sk += tri_ks(p.tri[it.tri_begin + t]);
-    c[q] = 2.0 * it.h * it.w * sk;
-  }
+  for (size_t q = 0; q < p.items.size(); ++q) c[q] = 2.0 * p.items[q].h * p.items[q].w * p.meta[q].sk;
   return c;
+}
+
+// Device-built k-lists: every segment is cut into batches whose C blocks' triples fit the
+// device's triple buffer.  A batch takes C blocks (with all their tasks) from the fronts of the
+// segment's XCD runs until the next one would overflow the buffer, so that every batch takes at
+// least one block; it becomes a segment of its own.
+// Each batch gets one job per distinct C block, and its tasks point into the job's range of the
+// buffer.
+static void batch_device_klists(HostPlan& p) {
+  const int64_t budget = p.cfg.device_klists >= 2 ? p.cfg.device_klists : kDeviceTriples;
+  std::vector<Item> items;
+  std::vector<ItemMeta> metas;
+  std::vector<double> costs;
+  std::vector<float> feats;
+  std::vector<Segment> segs;
+  p.jobs.clear();
+  p.tri_capacity = 0;
+  items.reserve(p.items.size());
+  metas.reserve(p.items.size());
+  costs.reserve(p.items.size());
+  feats.reserve(p.features.size());
+  for (const Segment& g : p.segs) {
+    int32_t pos[kXcds], end[kXcds];
+    for (int x = 0; x < kXcds; ++x) {
+      pos[x] = g.begin + g.xcd_begin[x];
+      end[x] = g.begin + g.xcd_begin[x + 1];
+    }
+    // tasks [q, run_end(q)) belong to one C block
+    auto run_end = [&](int32_t q, int32_t e) {
+      int32_t r = q + 1;
+      while (r < e && p.items[size_t(r)].c_off == p.items[size_t(q)].c_off &&
+             p.items[size_t(r)].product == p.items[size_t(q)].product)
+        ++r;
+      return r;
+    };
+    for (;;) {
+      bool left = false;
+      for (int x = 0; x < kXcds; ++x) left = left || pos[x] < end[x];
+      if (!left) break;
+      // this batch's share of every run: [pos[x], stop[x])
+      int32_t stop[kXcds];
+      for (int x = 0; x < kXcds; ++x) stop[x] = pos[x];
+      // the next C block comes from the run whose share of this batch costs least so far (the
+      // scheduler's costs), so that every batch keeps the XCDs balanced
+      int64_t tri = 0;
+      double load[kXcds] = {0};
+      for (;;) {
+        int best = -1;
+        for (int x = 0; x < kXcds; ++x)
+          if (stop[x] < end[x] && (best < 0 || load[x] < load[best])) best = x;
+        if (best < 0) break;
+        const int64_t c = p.items[size_t(stop[best])].tri_count;
+        if (tri > 0 && tri + c > budget) break;
+        tri += c;
+        const int32_t e = run_end(stop[best], end[best]);
+        for (int32_t q = stop[best]; q < e; ++q) load[best] += p.cost[size_t(q)];
+        stop[best] = e;
+      }
+      Segment b;
+      b.variant = g.variant;
+      b.begin = int32_t(items.size());
+      b.job_begin = int64_t(p.jobs.size());
+      std::map<std::pair<uint32_t, int64_t>, size_t> job_of;  // (product, C offset) -> job
+      uint32_t used = 0;
+      int64_t maxc = 0;
+      for (int x = 0; x < kXcds; ++x) {
+        b.xcd_begin[x] = int32_t(items.size()) - b.begin;
+        for (int32_t q = pos[x]; q < stop[x]; ++q) {
+          Item it = p.items[size_t(q)];
+          const auto key = std::make_pair(it.product, it.c_off);
+          auto f = job_of.find(key);
+          if (f == job_of.end()) {
+            f = job_of.emplace(key, p.jobs.size()).first;
+            p.jobs.push_back(KJob{p.meta[size_t(q)].ci, p.meta[size_t(q)].cj, used, it.tri_count});
+            used += it.tri_count;
+          }
+          it.tri_begin = p.jobs[f->second].tri_begin;
+          items.push_back(it);
+          metas.push_back(p.meta[size_t(q)]);
+          costs.push_back(p.cost[size_t(q)]);
+          for (int f5 = 0; f5 < 5; ++f5) feats.push_back(p.features[size_t(q) * 5 + size_t(f5)]);
+        }
+        maxc = std::max<int64_t>(maxc, stop[x] - pos[x]);
+        pos[x] = stop[x];
+      }
+      b.xcd_begin[kXcds] = int32_t(items.size()) - b.begin;
+      b.end = int32_t(items.size());
+      b.grid = maxc * kXcds;
+      b.job_count = int64_t(p.jobs.size()) - b.job_begin;
+      p.tri_capacity = std::max<int64_t>(p.tri_capacity, used);
+      segs.push_back(b);
+    }
+  }
+  p.items.swap(items);
+  p.meta.swap(metas);
+  p.cost.swap(costs);
+  p.features.swap(feats);
+  p.segs.swap(segs);
 }
 
 // Deals the tasks of one segment (indices `idx` into the canonically ordered task list) to the
@@ -224,6 +319,7 @@ void schedule(HostPlan& p, const std::vector<double>& cost_in) {
   p.meta.swap(metas);
   p.cost.swap(c2);
   p.features.swap(f2);
+  if (p.dev_klists) batch_device_klists(p);
 }
 
 void cut_items(HostPlan& p, int variant) {
@@ -258,7 +354,7 @@ void cut_items(HostPlan& p, const int class_var[kSizeClasses]) {
         it.ldm = uint16_t(cb.m);
         it.product = 0;
         p.items.push_back(it);
-        p.meta.push_back(ItemMeta{cb.ci, cb.cj, variant});
+        p.meta.push_back(ItemMeta{cb.ci, cb.cj, variant, cb.sk});
         p.features.push_back(std::log(float(it.h)));
         p.features.push_back(std::log(float(it.w)));
         p.features.push_back(std::log(float(std::max(1.0, cb.sk))));
@@ -285,6 +381,7 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   if (cfg.tile < 0 || cfg.tile > (cfg.precision == 2 ? kNumBf16Variants : kNumVariants))
     return "unknown tile variant";
   if (cfg.order < ORDER_LOCALITY || cfg.order > ORDER_PATCH) return "unknown task order";
+  if (cfg.device_klists < -1) return "device_klists must be -1, 0, 1 or a batch size >= 2";
   if (cfg.patch_r < 1 || cfg.patch_c < 1) return "patch sizes must be >= 1";
 
   p.cfg = cfg;
@@ -354,45 +451,128 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
     }
   }
 
-  // S3: k-lists (A row AND B column) and tasks
+  // S3: k-lists (A row AND B column) and tasks.  First, per present C block, the k-list's length
+  // and summed inner size, counted from the bitmap words (block rows in parallel); then either
+  // the triples themselves in a host list, or, when they would not fit it, the tables from which
+  // the device builds them batch by batch.
   std::vector<uint64_t> bt(size_t(N * wk), 0);  // B's shape transposed: column j's k bits
   for (int64_t k = 0; k < K; ++k)
     for (int64_t j = 0; j < N; ++j)
       if (test_bit(p.b_bits.data(), wn, k, j)) bt[size_t(j * wk + (k >> 6))] |= uint64_t(1) << (k & 63);
+  std::vector<int64_t> crow(size_t(M) + 1, 0);  // present C blocks before block row i
+  for (int64_t i = 0; i < M; ++i) {
+    int64_t c = 0;
+    for (int64_t v = 0; v < wn; ++v) c += __builtin_popcountll(p.c_bits[size_t(i * wn + v)]);
+    crow[size_t(i) + 1] = crow[size_t(i)] + c;
+  }
+  std::vector<uint32_t> cnt(size_t(crow[size_t(M)]));
+  std::vector<double> sks(size_t(crow[size_t(M)]));
+  // inner sizes grouped into per-size k masks when there are few distinct sizes (the summed
+  // inner size is then a handful of masked popcounts instead of a walk over the bits)
+  std::map<int64_t, std::vector<uint64_t>> size_mask;
+  for (int64_t k = 0; k < K && size_mask.size() <= 16; ++k) {
+    auto& m = size_mask[p.inner[size_t(k)]];
+    if (m.empty()) m.assign(size_t(wk), 0);
+    m[size_t(k >> 6)] |= uint64_t(1) << (k & 63);
+  }
+  const bool by_mask = size_mask.size() <= 16;
+  auto count_rows = [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int64_t q = crow[size_t(i)];
+      for (int64_t j = 0; j < N; ++j) {
+        if (!test_bit(p.c_bits.data(), wn, i, j)) continue;
+        const uint64_t* ar = p.a_bits.data() + i * wk;
+        const uint64_t* br = bt.data() + j * wk;
+        uint32_t c = 0;
+        double sk = 0;
+        if (by_mask) {
+          for (int64_t w = 0; w < wk; ++w) c += uint32_t(__builtin_popcountll(ar[w] & br[w]));
+          for (const auto& sm : size_mask) {
+            int64_t n = 0;
+            for (int64_t w = 0; w < wk; ++w) n += __builtin_popcountll(ar[w] & br[w] & sm.second[size_t(w)]);
+            sk += double(sm.first) * double(n);
+          }
+        } else {
+          for (int64_t w = 0; w < wk; ++w) {
+            uint64_t x = ar[w] & br[w];
+            while (x) {
+              const int64_t k = w * 64 + __builtin_ctzll(x);
+              x &= x - 1;
+              ++c;
+              sk += double(p.inner[size_t(k)]);
+            }
+          }
+        }
+        cnt[size_t(q)] = c;
+        sks[size_t(q)] = sk;
+        ++q;
+      }
+    }
+  };
+  {
+    const int64_t nthreads = std::max<int64_t>(1, std::min<int64_t>(
+        std::min<int64_t>(16, int64_t(std::thread::hardware_concurrency())), (M * N) / 4096 + 1));
+    std::vector<std::thread> pool;
+    for (int64_t t = 0; t < nthreads; ++t)
+      pool.emplace_back(count_rows, M * t / nthreads, M * (t + 1) / nthreads);
+    for (auto& th : pool) th.join();
+  }
+  int64_t total = 0;
+  for (uint32_t c : cnt) total += c;
+  p.triples_total = total;
+  p.dev_klists = cfg.device_klists > 0 || (cfg.device_klists == 0 && total > kHostTriples);
+  if (!p.dev_klists && total >= (int64_t(1) << 32)) {
+    *code = BSM_E_NOMEM;
+    return "more than 2^32 block triples for a host list (device k-lists were turned off)";
+  }
   p.tri.clear();
   p.items.clear();
   p.features.clear();
   p.useful_flops = 0;
   p.cblocks.clear();
+  p.cblocks.reserve(cnt.size());
+  if (!p.dev_klists) p.tri.reserve(size_t(total));
   for (int64_t i = 0; i < M; ++i) {
+    int64_t q = crow[size_t(i)];
     for (int64_t j = 0; j < N; ++j) {
       int64_t co = p.c_off[size_t(i * N + j)];
       if (co < 0) continue;
-      size_t tb = p.tri.size();
-      double sk = 0;
-      for (int64_t w = 0; w < wk; ++w) {
-        uint64_t x = p.a_bits[size_t(i * wk + w)] & bt[size_t(j * wk + w)];
-        while (x) {
-          int64_t k = w * 64 + __builtin_ctzll(x);
-          x &= x - 1;
-          Triple t;
-          const int64_t ao = bf16 ? a_off32[size_t(i * K + k)] : p.a_off[size_t(i * K + k)];
-          const int64_t bo = bf16 ? b_off32[size_t(k * N + j)] : p.b_off[size_t(k * N + j)];
-          t.a = uint64_t(ao) | (uint64_t(p.inner[size_t(k)]) << 48);
-          t.b = uint64_t(bo) | (uint64_t(k) << 48);
-          p.tri.push_back(t);
-          sk += double(p.inner[size_t(k)]);
+      const size_t tb = p.dev_klists ? 0 : p.tri.size();
+      if (!p.dev_klists) {
+        for (int64_t w = 0; w < wk; ++w) {
+          uint64_t x = p.a_bits[size_t(i * wk + w)] & bt[size_t(j * wk + w)];
+          while (x) {
+            int64_t k = w * 64 + __builtin_ctzll(x);
+            x &= x - 1;
+            Triple t;
+            const int64_t ao = bf16 ? a_off32[size_t(i * K + k)] : p.a_off[size_t(i * K + k)];
+            const int64_t bo = bf16 ? b_off32[size_t(k * N + j)] : p.b_off[size_t(k * N + j)];
+            t.a = uint64_t(ao) | (uint64_t(p.inner[size_t(k)]) << 48);
+            t.b = uint64_t(bo) | (uint64_t(k) << 48);
+            p.tri.push_back(t);
+          }
         }
       }
-      size_t tc = p.tri.size() - tb;
-      if (p.tri.size() >= (size_t(1) << 32)) {
-        *code = BSM_E_NOMEM;
-        return "more than 2^32 block triples";
-      }
+      const double sk = sks[size_t(q)];
+      const uint32_t tc = cnt[size_t(q)];
+      ++q;
       int m = int(p.rows[size_t(i)]), n = int(p.cols[size_t(j)]);
       p.useful_flops += 2.0 * m * n * sk;
-      p.cblocks.push_back(CBlock{co, uint32_t(tb), uint32_t(tc), m, n, int32_t(i), int32_t(j), sk});
+      p.cblocks.push_back(CBlock{co, uint32_t(tb), tc, m, n, int32_t(i), int32_t(j), sk});
     }
+  }
+  if (p.dev_klists) {
+    // the device's tables: A offsets by (i, k), B offsets by (j, k), both in the form's layout
+    p.wk = wk;
+    p.bt_bits.swap(bt);
+    p.a_tab.assign(size_t(M * K), -1);
+    p.bt_tab.assign(size_t(N * K), -1);
+    for (int64_t i = 0; i < M; ++i)
+      for (int64_t k = 0; k < K; ++k)
+        p.a_tab[size_t(i * K + k)] = bf16 ? a_off32[size_t(i * K + k)] : p.a_off[size_t(i * K + k)];
+    for (int64_t k = 0; k < K; ++k)
+      for (int64_t j = 0; j < N; ++j)
+        p.bt_tab[size_t(j * K + k)] = bf16 ? b_off32[size_t(k * N + j)] : p.b_off[size_t(k * N + j)];
   }
   p.k_total = 0;
   for (int64_t k = 0; k < K; ++k) p.k_total += double(p.inner[size_t(k)]);
@@ -422,6 +602,10 @@ std::string merge_plans(HostPlan& out, const std::vector<const HostPlan*>& parts
     const HostPlan& p = *parts[q];
     if (p.cfg.precision != p0.cfg.precision) return "batch members differ in precision";
     if (p.windows != 1) return "batch members must issue all k-iterations at once (k_window 0)";
+    if (p.dev_klists) {
+      *code = BSM_E_UNSUPPORTED;
+      return "batch members must keep their k-lists on the host (device k-lists are per plan)";
+    }
     const uint64_t tb = out.tri.size();
     if (tb + p.tri.size() >= (uint64_t(1) << 32)) {
       *code = BSM_E_NOMEM;

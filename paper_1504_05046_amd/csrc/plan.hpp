@@ -38,6 +38,7 @@ struct PlanConfig {
   int order = ORDER_INTERLEAVE;
   int out_f32 = 0;    // C holds FP32 elements
   int patch_r = 4, patch_c = 8;  // C blocks per patch (ORDER_PATCH)
+  int device_klists = 0;  // 0: when the triples would not fit the host list, 1: always, -1: never
   std::string tune_cache;  // autotuner choices file ("" = none)
 };
 
@@ -56,7 +57,13 @@ struct Segment {
   int32_t begin = 0, end = 0;
   int32_t xcd_begin[kXcds + 1] = {0};
   int64_t grid = 0;  // workgroups of the launch
+  int64_t job_begin = 0, job_count = 0;  // device-built k-lists of the segment's C blocks
 };
+
+// Block triples the host list holds at most; beyond it (or on request) k-lists are built on the
+// device, batch by batch, into a buffer of at most kDeviceTriples triples.
+constexpr int64_t kHostTriples = int64_t(1) << 28;
+constexpr int64_t kDeviceTriples = int64_t(1) << 27;
 
 // A present C block and its k-list (the unit tasks are cut from).
 struct CBlock {
@@ -72,6 +79,7 @@ struct CBlock {
 struct ItemMeta {
   int32_t ci, cj;
   int32_t var;
+  double sk;  // summed inner size of the C block's k-list
 };
 
 struct HostPlan {
@@ -84,7 +92,16 @@ struct HostPlan {
   int64_t a_elems = 0, b_elems = 0, c_elems = 0;
   double useful_flops = 0.0;
 
-  std::vector<Triple> tri;       // k-lists of all C blocks, C blocks in row-major order
+  std::vector<Triple> tri;       // k-lists of all C blocks, C blocks in row-major order (host mode)
+  // device-built k-lists: bitmaps, offset tables and the jobs of every segment
+  bool dev_klists = false;
+  int64_t wk = 0;                // 64-bit words per bitmap row of the inner dimension
+  std::vector<uint64_t> bt_bits; // B's shape transposed: column j's k bits (N x wk)
+  std::vector<int64_t> a_tab;    // M x K: packed offset of A_ik in the form's layout, -1 absent
+  std::vector<int64_t> bt_tab;   // N x K: packed offset of B_kj at [j K + k], -1 absent
+  std::vector<KJob> jobs;        // per segment (Segment::job_begin), C blocks of the segment
+  int64_t tri_capacity = 0;      // triple buffer the device needs (largest segment)
+  int64_t triples_total = 0;     // triples of the whole product
   std::vector<CBlock> cblocks;   // present C blocks, row-major
   double k_total = 0;            // summed inner size of all K blocks
   int class_var[kSizeClasses] = {0, 0, 0, 0};  // tile variant of each size class

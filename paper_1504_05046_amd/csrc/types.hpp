@@ -77,6 +77,13 @@ struct Item {
 };
 static_assert(sizeof(Item) == 32, "Item layout");
 
+// Device-built k-list of one C block (i, j): the triples of its k-list, ascending k, are written
+// at tri[tri_begin .. tri_begin + count) before the tile kernel of the batch runs.
+struct KJob {
+  int32_t i, j;
+  uint32_t tri_begin, count;
+};
+
 // Operands of one product: A and B in the element type of the precision form (FP64 tiles, or
 // their FP32 / bf16-slice copies), C in FP64 or FP32 (c_f32) and the k-window partial sums P in
 // FP64.

@@ -300,3 +300,30 @@ def test_patch_order_keeps_the_task_set():
     pat = bsm.Plan.from_problem(p, order=bsm.ORDER_PATCH, patch=(2, 3)).features()
     assert not np.array_equal(base, pat)
     assert np.array_equal(np.sort(base.view(np.int32), axis=0), np.sort(pat.view(np.int32), axis=0))
+
+
+@pytest.mark.parametrize("dk", [1, 5, 64])
+def test_device_klists_plan_matches_host_lists(dk):
+    """Planning with k-lists built on the device keeps the C-shape, layout, counts, useful flops and
+    the task set of the host-list plan; only the task order (batches) and the triples' home differ."""
+    p = gen.random_problem(48, 7, 9, 8, 4, 150, 0.5, 0.5)
+    host = bsm.Plan.from_problem(p)
+    dev = bsm.Plan.from_problem(p, device_klists=dk)
+    hi, di = host.info(), dev.info()
+    assert hi.device_klists == 0 and di.device_klists == 1
+    for f in ("c_blocks", "c_elems", "triples", "tasks"):
+        assert getattr(hi, f) == getattr(di, f), f
+    assert hi.useful_flops == di.useful_flops
+    assert np.array_equal(host.c_shape(), dev.c_shape())
+    assert np.array_equal(host.c_offsets(), dev.c_offsets())
+    fh, fd = host.features(), dev.features()
+    assert np.array_equal(np.sort(fh.view(np.int32), axis=0), np.sort(fd.view(np.int32), axis=0))
+    _expect(bsm.E_INVALID, lambda: bsm.Plan.from_problem(p, device_klists=-2))
+
+
+def test_device_klists_limits_on_host():
+    p = gen.random_problem(49, 3, 3, 3, 1, 30, 0.8, 0.8)
+    dev = bsm.Plan.from_problem(p, device_klists=1)
+    _expect(bsm.E_UNSUPPORTED, lambda: bsm.Batch([dev]))
+    L = bsm.load()
+    assert L.bsm_execute_static(dev.handle, 1.0, 1 << 32, 1 << 36, 1 << 40, 0, None) == bsm.E_UNSUPPORTED

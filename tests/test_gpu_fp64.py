@@ -284,3 +284,30 @@ def test_mixed_tile_classes_single_plan(precision):
     got2, _ = run_gpu(p, plan=win)
     win.verify()
     assert np.array_equal(got, got2)
+
+
+@pytest.mark.parametrize("precision", [bsm.FP64, bsm.FP32, bsm.BF16X3])
+def test_device_built_klists_match_host_lists(precision):
+    """k-lists built on the device, batch by batch (also in batches of a few triples), give the
+    same bits as the host-built lists, with and without k-windows."""
+    _say(f"[device k-lists] precision={precision}")
+    p = gen.random_problem(2400 + precision, 9, 12, 8, 4, 180, 0.5, 0.5)
+    base, _ = run_gpu(p, precision=precision)
+    for dk in (1, 7, 64):
+        got, plan = run_gpu(p, precision=precision, device_klists=dk)
+        assert plan.info().device_klists == 1
+        plan.verify()
+        assert np.array_equal(got, base), dk
+    got, plan = run_gpu(p, precision=precision, device_klists=7, k_window=3)
+    plan.verify()
+    assert np.array_equal(got, base)
+
+
+def test_device_built_klists_decay_cloud_against_oracle():
+    """C = A A on a small distance-decay cloud with device-built k-lists and small tiles."""
+    p = gen.decay_cloud(seed=5001, npts=300, box=15.0)
+    got, plan = run_gpu(p, device_klists=1, tile=4)
+    plan.verify()
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    assert rel_fro(got, ref) <= 1e-12
+    assert np.all(np.abs(got - ref) <= _abs_bound(p) + 1e-300)
