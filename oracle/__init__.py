@@ -49,9 +49,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_useful_flops.restype = ctypes.c_double
         L.oracle_useful_flops.argtypes = [_i64, _i64, _i64, _p, _p, _p, _p, _p]
         L.oracle_bsmm.argtypes = [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p, _p, ctypes.c_double,
-                                  ctypes.c_int, _p, ctypes.c_int]
+                                  ctypes.c_int, _p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.oracle_bsmm_blocks.argtypes = [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p, _p,
-                                         ctypes.c_double, _i64, _p, _p, _p, _p, ctypes.c_int]
+                                         ctypes.c_double, _i64, _p, _p, _p, _p, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int]
         L.oracle_concurrent_iterations.restype = _i64
         L.oracle_concurrent_iterations.argtypes = [_i64, _i64, _i64]
         L.oracle_memory_overhead.restype = ctypes.c_double
@@ -105,15 +106,43 @@ def useful_flops(rows, inner, cols, a_bits, b_bits) -> float:
     return lib().oracle_useful_flops(r.size, s.size, t.size, _ptr(r), _ptr(s), _ptr(t), _ptr(a), _ptr(b))
 
 
+def product_shape(M: int, K: int, N: int, a_bits, b_bits, trans_a: bool = False,
+                  trans_b: bool = False) -> np.ndarray:
+    """C-shape of op(A) op(B) from the stored shapes (a transposed operand's bitmap is stored
+    transposed: K x M for A, N x K for B)."""
+    if not trans_a and not trans_b:
+        return shape_product(M, K, N, a_bits, b_bits)
+    from itertools import product as _prod
+    wa = lib().oracle_words(M if trans_a else K)
+    wb = lib().oracle_words(K if trans_b else N)
+    a = _c64(a_bits, np.uint64)
+    b = _c64(b_bits, np.uint64)
+    bit = lambda w, words, x, y: bool((int(w[x * words + y // 64]) >> (y % 64)) & 1)
+    la = np.zeros((M, K), bool)
+    lb = np.zeros((K, N), bool)
+    for i, k in _prod(range(M), range(K)):
+        la[i, k] = bit(a, wa, k, i) if trans_a else bit(a, wa, i, k)
+    for k, j in _prod(range(K), range(N)):
+        lb[k, j] = bit(b, wb, j, k) if trans_b else bit(b, wb, k, j)
+    wn = lib().oracle_words(N)
+    out = np.zeros(M * wn, dtype=np.uint64)
+    for i in range(M):
+        for j in range(N):
+            if np.any(la[i] & lb[:, j]):
+                out[i * wn + j // 64] |= np.uint64(1) << np.uint64(j % 64)
+    return out
+
+
 def bsmm(rows, inner, cols, a_bits, b_bits, A, B, alpha: float = 1.0,
-         C: Optional[np.ndarray] = None, extended: bool = False) -> np.ndarray:
-    """Packed C = alpha*A*B (+ C when C is given).  Returns a new array."""
+         C: Optional[np.ndarray] = None, extended: bool = False, trans_a: bool = False,
+         trans_b: bool = False) -> np.ndarray:
+    """Packed C = alpha*op(A)*op(B) (+ C when C is given).  Returns a new array."""
     r, s, t = (_c64(x, np.int64) for x in (rows, inner, cols))
     a = _c64(a_bits, np.uint64)
     b = _c64(b_bits, np.uint64)
     Ad = _c64(A, np.float64)
     Bd = Ad if B is A else _c64(B, np.float64)
-    c_bits = shape_product(r.size, s.size, t.size, a, b)
+    c_bits = product_shape(r.size, s.size, t.size, a, b, trans_a, trans_b)
     _, total = block_offsets(r, t, c_bits)
     if C is None:
         out = np.zeros(total, dtype=np.float64)
@@ -124,14 +153,16 @@ def bsmm(rows, inner, cols, a_bits, b_bits, A, B, alpha: float = 1.0,
             raise ValueError("C has the wrong size")
         acc = 1
     st = lib().oracle_bsmm(r.size, s.size, t.size, _ptr(r), _ptr(s), _ptr(t), _ptr(a), _ptr(b),
-                           _ptr(Ad), _ptr(Bd), float(alpha), acc, _ptr(out), int(extended))
+                           _ptr(Ad), _ptr(Bd), float(alpha), acc, _ptr(out), int(extended),
+                           int(bool(trans_a)), int(bool(trans_b)))
     if st != 0:
         raise MemoryError("oracle_bsmm failed")
     return out
 
 
 def bsmm_blocks(rows, inner, cols, a_bits, b_bits, A, B, sel: Sequence[Tuple[int, int]],
-                alpha: float = 1.0, extended: bool = False):
+                alpha: float = 1.0, extended: bool = False, trans_a: bool = False,
+                trans_b: bool = False):
     """Selected C blocks: returns (list of 2-D arrays, list of presence flags)."""
     r, s, t = (_c64(x, np.int64) for x in (rows, inner, cols))
     a = _c64(a_bits, np.uint64)
@@ -145,7 +176,8 @@ def bsmm_blocks(rows, inner, cols, a_bits, b_bits, A, B, sel: Sequence[Tuple[int
     present = np.zeros(max(1, len(sel)), dtype=np.int32)
     st = lib().oracle_bsmm_blocks(r.size, s.size, t.size, _ptr(r), _ptr(s), _ptr(t), _ptr(a),
                                   _ptr(b), _ptr(Ad), _ptr(Bd), float(alpha), len(sel), _ptr(si),
-                                  _ptr(sj), _ptr(out), _ptr(present), int(extended))
+                                  _ptr(sj), _ptr(out), _ptr(present), int(extended),
+                                  int(bool(trans_a)), int(bool(trans_b)))
     if st != 0:
         raise ValueError("oracle_bsmm_blocks failed")
     blocks, pos = [], 0

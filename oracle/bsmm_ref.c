@@ -23,6 +23,14 @@
  * i-k-j order, k blocks ascending, one OpenMP thread per whole C block, so the result does not
  * depend on the thread count.  An optional long-double accumulator gives a tighter reference.
  *
+ * Transposed operands (the SUMMA variants of Sec. 2.1 that multiply by a transpose):
+ * C = alpha op(A) op(B) (+ C), op(X) = X or X^T.  The tilings always describe the product
+ * (r: rows of C and of op(A), s: the inner dimension, t: columns of C and of op(B)).  A transposed
+ * operand is stored as the transposed block matrix: for op(A) = A^T the stored matrix has K x M
+ * blocks, its shape bit (k, i) and its block (k, i) of s_k x r_i elements, row-major, packed in
+ * the stored matrix's row-major block order; likewise op(B) = B^T is stored as N x K blocks of
+ * t_j x s_k elements.  op(A)_ik is then the transpose of the stored block (k, i).
+ *
  * Also here: the paper's two closed forms, the concurrent-iteration limit (Eq. 1) and the
  * per-node memory overhead of one SUMMA iteration (Eq. 2).
  */
@@ -99,20 +107,45 @@ double oracle_useful_flops(int64_t M, int64_t K, int64_t N, const int64_t* r, co
 typedef struct {
   int64_t M, K, N;
   const int64_t *r, *s, *t;
-  const uint64_t *a_bits, *b_bits;
-  int64_t *a_off, *b_off; /* M*K and K*N, -1 = absent */
+  const uint64_t *a_bits, *b_bits; /* as stored (transposed shapes when ta / tb) */
+  int ta, tb;                      /* op(A) = A^T, op(B) = B^T */
+  int64_t *a_off, *b_off; /* stored packed offsets: M*K (or K*M) and K*N (or N*K), -1 = absent */
 } problem;
 
 static int setup(problem* p, int64_t M, int64_t K, int64_t N, const int64_t* r, const int64_t* s,
-                 const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits) {
+                 const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits, int ta, int tb) {
   p->M = M; p->K = K; p->N = N; p->r = r; p->s = s; p->t = t;
   p->a_bits = a_bits; p->b_bits = b_bits;
+  p->ta = ta; p->tb = tb;
   p->a_off = (int64_t*)malloc((size_t)(M * K > 0 ? M * K : 1) * sizeof(int64_t));
   p->b_off = (int64_t*)malloc((size_t)(K * N > 0 ? K * N : 1) * sizeof(int64_t));
   if (!p->a_off || !p->b_off) return -1;
-  oracle_block_offsets(M, K, r, s, a_bits, p->a_off);
-  oracle_block_offsets(K, N, s, t, b_bits, p->b_off);
+  if (ta) oracle_block_offsets(K, M, s, r, a_bits, p->a_off);
+  else oracle_block_offsets(M, K, r, s, a_bits, p->a_off);
+  if (tb) oracle_block_offsets(N, K, t, s, b_bits, p->b_off);
+  else oracle_block_offsets(K, N, s, t, b_bits, p->b_off);
   return 0;
+}
+
+/* stored offset of op(A)_ik and op(B)_kj (-1 when absent) */
+static int64_t a_at(const problem* p, int64_t i, int64_t k) {
+  return p->ta ? p->a_off[k * p->M + i] : p->a_off[i * p->K + k];
+}
+static int64_t b_at(const problem* p, int64_t k, int64_t j) {
+  return p->tb ? p->b_off[j * p->K + k] : p->b_off[k * p->N + j];
+}
+
+/* The C-shape of op(A) op(B), from the stored shapes. */
+static void shape_of_product(const problem* p, uint64_t* c_bits) {
+  int64_t wn = words_of(p->N);
+  memset(c_bits, 0, (size_t)(p->M * wn) * sizeof(uint64_t));
+  for (int64_t i = 0; i < p->M; ++i)
+    for (int64_t j = 0; j < p->N; ++j)
+      for (int64_t k = 0; k < p->K; ++k)
+        if (a_at(p, i, k) >= 0 && b_at(p, k, j) >= 0) {
+          c_bits[i * wn + j / 64] |= (uint64_t)1 << (j % 64);
+          break;
+        }
 }
 
 static void teardown(problem* p) { free(p->a_off); free(p->b_off); }
@@ -127,18 +160,19 @@ static int block_product(const problem* p, const double* A, const double* B, int
   if (extended) acc = (long double*)calloc((size_t)(h * w > 0 ? h * w : 1), sizeof(long double));
   for (int64_t e = 0; e < h * w; ++e) out[e] = 0.0;
   for (int64_t k = 0; k < p->K; ++k) {
-    int64_t ao = p->a_off[i * p->K + k], bo = p->b_off[k * p->N + j];
+    int64_t ao = a_at(p, i, k), bo = b_at(p, k, j);
     if (ao < 0 || bo < 0) continue;
     present = 1;
     int64_t d = p->s[k];
-    const double* a = A + ao; /* h x d */
-    const double* b = B + bo; /* d x w */
+    const double* a = A + ao; /* op(A)_ik: h x d; stored d x h when transposed */
+    const double* b = B + bo; /* op(B)_kj: d x w; stored w x d when transposed */
     for (int64_t x = 0; x < h; ++x)
       for (int64_t y = 0; y < d; ++y) {
-        double av = a[x * d + y];
+        double av = p->ta ? a[y * h + x] : a[x * d + y];
         for (int64_t z = 0; z < w; ++z) {
-          if (extended) acc[x * w + z] += (long double)av * (long double)b[y * w + z];
-          else out[x * w + z] += av * b[y * w + z];
+          double bv = p->tb ? b[z * d + y] : b[y * w + z];
+          if (extended) acc[x * w + z] += (long double)av * (long double)bv;
+          else out[x * w + z] += av * bv;
         }
       }
   }
@@ -153,14 +187,15 @@ static int block_product(const problem* p, const double* A, const double* B, int
  * overwritten, with accumulate = 1 it must hold the previous C and receives alpha*AB + C. */
 int oracle_bsmm(int64_t M, int64_t K, int64_t N, const int64_t* r, const int64_t* s,
                 const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits, const double* A,
-                const double* B, double alpha, int accumulate, double* C, int extended) {
+                const double* B, double alpha, int accumulate, double* C, int extended, int ta,
+                int tb) {
   problem p;
-  if (setup(&p, M, K, N, r, s, t, a_bits, b_bits)) { teardown(&p); return -1; }
+  if (setup(&p, M, K, N, r, s, t, a_bits, b_bits, ta, tb)) { teardown(&p); return -1; }
   int64_t wn = words_of(N);
   uint64_t* c_bits = (uint64_t*)calloc((size_t)(M * wn > 0 ? M * wn : 1), sizeof(uint64_t));
   int64_t* c_off = (int64_t*)malloc((size_t)(M * N > 0 ? M * N : 1) * sizeof(int64_t));
   if (!c_bits || !c_off) { free(c_bits); free(c_off); teardown(&p); return -1; }
-  oracle_shape_product(M, K, N, a_bits, b_bits, c_bits);
+  shape_of_product(&p, c_bits);
   oracle_block_offsets(M, N, r, t, c_bits, c_off);
   int status = 0;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -189,9 +224,9 @@ int oracle_bsmm_blocks(int64_t M, int64_t K, int64_t N, const int64_t* r, const 
                        const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits,
                        const double* A, const double* B, double alpha, int64_t nsel,
                        const int64_t* sel_i, const int64_t* sel_j, double* out, int32_t* present,
-                       int extended) {
+                       int extended, int ta, int tb) {
   problem p;
-  if (setup(&p, M, K, N, r, s, t, a_bits, b_bits)) { teardown(&p); return -1; }
+  if (setup(&p, M, K, N, r, s, t, a_bits, b_bits, ta, tb)) { teardown(&p); return -1; }
   int64_t* pos = (int64_t*)malloc((size_t)(nsel + 1) * sizeof(int64_t));
   if (!pos) { teardown(&p); return -1; }
   pos[0] = 0;

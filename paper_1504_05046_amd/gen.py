@@ -34,7 +34,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -134,6 +134,27 @@ def unpack_bits(words: np.ndarray, r: int, c: int) -> np.ndarray:
     b = np.asarray(words, dtype="<u8").reshape(r, w).view(np.uint8).reshape(r, w, 8)
     bits = np.unpackbits(b, axis=-1).reshape(r, w, 8, 8)[:, :, :, ::-1].reshape(r, w * 64)
     return bits[:, :c].astype(bool)
+
+
+def stored_transpose(rsz, csz, mask, data) -> Tuple[np.ndarray, np.ndarray]:
+    """Storage of X^T for a packed block matrix X (rsz x csz tiling): bitmap of mask^T and each
+    present block transposed, packed in the transposed matrix's row-major block order.  Used to
+    hand a product an operand that it reads as op(X) = X^T."""
+    rsz = np.asarray(rsz, dtype=np.int64)
+    csz = np.asarray(csz, dtype=np.int64)
+    mask = np.asarray(mask, dtype=bool)
+    data = np.asarray(data, dtype=np.float64)
+    offs = np.concatenate([[0], np.cumsum(rsz[np.nonzero(mask)[0]] * csz[np.nonzero(mask)[1]])])
+    where = {(int(i), int(j)): int(offs[n]) for n, (i, j) in enumerate(zip(*np.nonzero(mask)))}
+    out = np.empty(int(offs[-1]), dtype=np.float64)
+    pos = 0
+    mt = mask.T
+    for j, i in zip(*np.nonzero(mt)):
+        h, w = int(rsz[i]), int(csz[j])
+        o = where[(int(i), int(j))]
+        out[pos:pos + h * w] = data[o:o + h * w].reshape(h, w).T.reshape(-1)
+        pos += h * w
+    return pack_bits(mt), out
 
 
 def _fill_blocks(seed: int, mat: int, mask: np.ndarray, rsz: np.ndarray, csz: np.ndarray,

@@ -50,6 +50,67 @@ def test_matches_numpy_dense_ragged_sizes():
     _dense_product_check(p)
 
 
+def _stored(rsz, csz, mask, D, trans):
+    """Packed storage of an operand whose product-side view is the dense D (rsz x csz blocks):
+    as is, or as the transposed block matrix when trans."""
+    if trans:
+        return gen.pack_bits(mask.T), from_dense(csz, rsz, mask.T, D.T)
+    return gen.pack_bits(mask), from_dense(rsz, csz, mask, D)
+
+
+@pytest.mark.parametrize("ta,tb", [(False, True), (True, False), (True, True)])
+@pytest.mark.parametrize("seed", range(4))
+def test_transposed_operands_match_numpy(seed, ta, tb):
+    """C = op(A) op(B) with an operand stored as the transposed block matrix: numpy's product of
+    the dense transposes, elementwise within Higham's bound, and C's shape is the boolean product
+    of the logical shapes."""
+    p = gen.random_problem(100 + seed, 4, 5, 3, 1, 9, 0.6, 0.6)
+    A = to_dense(p.rows, p.inner, p.a_mask, p.a_data)
+    B = to_dense(p.inner, p.cols, p.b_mask, p.b_data)
+    a_bits, a_st = _stored(p.rows, p.inner, p.a_mask, A, ta)
+    b_bits, b_st = _stored(p.inner, p.cols, p.b_mask, B, tb)
+    c_mask = (p.a_mask.astype(np.int64) @ p.b_mask.astype(np.int64)) > 0
+    got = oracle.bsmm(p.rows, p.inner, p.cols, a_bits, b_bits, a_st, b_st, -1.5, trans_a=ta,
+                      trans_b=tb)
+    c_bits = oracle.product_shape(p.M, p.K, p.N, a_bits, b_bits, ta, tb)
+    assert np.array_equal(gen.unpack_bits(c_bits, p.M, p.N), c_mask)
+    ref = -1.5 * (A @ B)
+    bound = 2 * higham_gamma(int(p.inner.sum())) * 1.5 * (np.abs(A) @ np.abs(B)) + 1e-300
+    assert got.size == packed_offsets(p.rows, p.cols, c_mask)[1]
+    assert np.all(np.abs(to_dense(p.rows, p.cols, c_mask, got) - ref) <= bound)
+    # selected blocks follow the same reading
+    sel = [(i, j) for i in range(p.M) for j in range(p.N)][::3]
+    out, present = oracle.bsmm_blocks(p.rows, p.inner, p.cols, a_bits, b_bits, a_st, b_st, sel,
+                                      -1.5, trans_a=ta, trans_b=tb)
+    ro = np.concatenate([[0], np.cumsum(p.rows)])
+    co = np.concatenate([[0], np.cumsum(p.cols)])
+    for n, (i, j) in enumerate(sel):
+        assert bool(present[n]) == bool(c_mask[i, j])
+        blk = ref[ro[i]:ro[i + 1], co[j]:co[j + 1]]
+        assert np.allclose(out[n].reshape(blk.shape), blk, rtol=1e-13, atol=1e-13)
+
+
+def test_transposed_product_identity_bitwise():
+    """(AB)^T = B^T A^T: the oracle multiplying the stored B and A as transposed operands gives the
+    transpose of C = AB bit for bit (same products, same summation order)."""
+    p = gen.random_problem(7, 4, 6, 5, 1, 12, 0.5, 0.7)
+    c = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    ct = oracle.bsmm(p.cols, p.inner, p.rows, p.b_bits(), p.a_bits(), p.b_data, p.a_data,
+                     trans_a=True, trans_b=True)
+    c_mask = (p.a_mask.astype(np.int64) @ p.b_mask.astype(np.int64)) > 0
+    D = to_dense(p.rows, p.cols, c_mask, c)
+    Dt = to_dense(p.cols, p.rows, c_mask.T, ct)
+    assert np.array_equal(D.T, Dt)
+
+
+def test_gen_stored_transpose_matches_dense_transpose():
+    p = gen.random_problem(9, 3, 4, 2, 1, 7, 0.7, 0.7)
+    bits, data = gen.stored_transpose(p.rows, p.inner, p.a_mask, p.a_data)
+    A = to_dense(p.rows, p.inner, p.a_mask, p.a_data)
+    assert np.array_equal(bits, gen.pack_bits(p.a_mask.T))
+    assert np.array_equal(data, from_dense(p.inner, p.rows, p.a_mask.T, A.T))
+
+
 def test_shape_product_exhaustive_2x2x2():
     """All 2^4 x 2^4 pairs of 2x2 block shapes: C-shape is the boolean product (numpy), bit-exact,
     and the values agree with the dense product."""
