@@ -10,6 +10,8 @@
  * library executes that local multiply for block-sparse operands: for every (i, j) in the
  * C-shape  Chat_ij = OR_k (Ahat_ik AND Bhat_kj)
  *     C_ij = alpha * sum_{k : Ahat_ik and Bhat_kj} A_ik B_kj   (+ C_ij when accumulating).
+ * Either operand may be read transposed (Sec. 2.1's SUMMA variants for products with A^T or B^T):
+ * options trans_a / trans_b replace A by A^T and B by B^T in the formulas above; see Transposes.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -21,6 +23,14 @@
  *           row-major with leading dimension equal to its own column count.  A block's offset is
  *           the number of elements of the present blocks before it.  The same layout holds for
  *           C, whose shape is Chat.
+ * Transposes with trans_a, the caller's A is the K x M block matrix whose transpose is the
+ *           product's left operand: its shape is given as stored (K x M bits), its tiles are its
+ *           own present blocks packed in its own row-major block order, block (k, i) of s_k x r_i
+ *           elements, and the product reads block (k, i) transposed as op(A)_ik.  Likewise with
+ *           trans_b the caller's B is N x K, block (j, k) of t_j x s_k elements.  The tilings
+ *           always describe the product (r, s, t as above).  A transposed operand is copied into
+ *           the product's layout by a transposition pass on the stream before the tile kernels
+ *           (in the FP32 and split-bf16 forms, inside the conversion pass they run anyway).
  * Memory    host arguments are copied before the call returns.  Device buffers (dA, dB, dC) are
  *           owned by the caller and must stay valid until the work queued on the stream is done.
  *           dA and dB may be the same buffer (C = A A); dC must not overlap either.
@@ -104,6 +114,9 @@ typedef struct {
                               the device; -1 = always on the host; 1 = always on the device; n >= 2
                               = always on the device, in batches of at most n triples (the device
                               buffer for them; the default batch is 2^27 triples, 2 GiB) */
+  int32_t trans_a;        /* 1 = the product reads A^T: A is stored as the K x M block matrix
+                             (see Transposes); 0 = as is */
+  int32_t trans_b;        /* 1 = the product reads B^T: B is stored as the N x K block matrix */
   const char* tune_cache; /* NULL, or a file where bsm_autotune looks up and records its choices
                              (lines "signature variant"); the string is copied */
 } bsm_options;
@@ -140,7 +153,8 @@ void bsm_options_default(bsm_options* opt);
  * only each C block's k-list length and summed inner size, counted from the shape words, plus
  * the offset tables, and the tasks are cut into batches whose triples fit the device buffer; each
  * execute then builds a batch's triples on the device right before the batch's tile launch.
- * Device memory is allocated at the first execute.  All arguments are host memory
+ * Device memory is allocated at the first execute.  a_bits and b_bits are the shapes as stored:
+ * M x K and K x N, or K x M with trans_a and N x K with trans_b.  All arguments are host memory
  * and are copied; opt may be NULL (defaults).  Errors: BSM_E_INVALID for a null pointer, a
  * negative count, a block size outside [1, 65535], a padding bit set or an unknown option;
  * BSM_E_NOMEM if the host runs out or a buffer exceeds 2^48 elements. */

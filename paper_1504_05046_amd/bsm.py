@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("out", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("patch_rows", ctypes.c_int32), ("patch_cols", ctypes.c_int32),
-                ("device_klists", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+                ("device_klists", ctypes.c_int32), ("trans_a", ctypes.c_int32),
+                ("trans_b", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -148,13 +149,14 @@ def _arr(a, dtype):
 
 def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, tile=0,
             use_graph=0, out=OUT_F64, order=ORDER_DEFAULT, patch=(0, 0), device_klists=0,
-            tune_cache=None) -> Options:
+            tune_cache=None, trans_a=0, trans_b=0) -> Options:
     o = Options()
     load().bsm_options_default(ctypes.byref(o))
     o.precision, o.sched, o.k_window, o.record_timings, o.tile = precision, sched, k_window, record_timings, tile
     o.use_graph, o.out, o.order = use_graph, out, order
     o.patch_rows, o.patch_cols = int(patch[0]), int(patch[1])
     o.device_klists = int(device_klists)
+    o.trans_a, o.trans_b = int(trans_a), int(trans_b)
     o.tune_cache = tune_cache.encode() if tune_cache else None
     return o
 
@@ -224,6 +226,14 @@ class Plan:
         self._b = _arr(b_bits, np.uint64)
         o = opts if opts is not None else options(**kw)
         self._opts = o  # keeps the tune-cache string alive for the call
+        # shapes as stored: op(A) = A^T is given as K x M, op(B) = B^T as N x K
+        M, K, N = self._rows.size, self._inner.size, self._cols.size
+        ar, ac = (K, M) if o.trans_a else (M, K)
+        br, bc = (N, K) if o.trans_b else (K, N)
+        for name, bits, r, c in (("a_bits", self._a, ar, ac), ("b_bits", self._b, br, bc)):
+            if bits.size < r * ((c + 63) // 64):
+                raise ValueError(f"{name}: {bits.size} words, the {r} x {c} shape needs "
+                                 f"{r * ((c + 63) // 64)}")
         h = _p()
         _check(L.bsm_plan_create(ctypes.byref(h), self._rows.size, self._rows.ctypes.data,
                                  self._inner.size, self._inner.ctypes.data, self._cols.size,

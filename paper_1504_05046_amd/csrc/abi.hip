@@ -176,13 +176,42 @@ static uint64_t bits_of(double d) {
 }
 
 // ------------------------------------------------------------------------------------------------
+// Operands as the tile kernels read them when not in place (staged_bytes > 0): the buffers and
+// the block tables of the passes that fill them.
+struct Staging {
+  void* opA = nullptr;
+  void* opB = nullptr;
+  const SplitBlock* sa = nullptr;  // split-bf16 form: block tables of the split pass
+  const SplitBlock* sb = nullptr;
+  const XposeBlock* xa = nullptr;  // transposed operands: block tables of the transposition pass
+  const XposeBlock* xb = nullptr;
+};
+
+// Bytes of the staged copy of A (or B): the FP32 copy, the bf16 slice planes, or op(X) of a
+// transposed FP64 operand; 0 = the tile kernels read the caller's buffer.
+static int64_t staged_bytes(const HostPlan& h, bool b) {
+  switch (h.cfg.precision) {
+    case BSM_FP32: return (b ? h.b_elems : h.a_elems) * 4;
+    case BSM_BF16X3: return (b ? h.b_elems32 : h.a_elems32) * 6;
+    default: return (b ? h.cfg.trans_b : h.cfg.trans_a) ? (b ? h.b_elems : h.a_elems) * 8 : 0;
+  }
+}
+
+// Bytes of the block tables of the staging passes.
+static int64_t staging_table_bytes(const HostPlan& h) {
+  return int64_t((h.split_a.size() + h.split_b.size()) * sizeof(SplitBlock) +
+                 (h.xpose_a.size() + h.xpose_b.size()) * sizeof(XposeBlock));
+}
+
 struct bsm_plan {
   HostPlan hp;
   TaskSet ts;
-  void* d_opA = nullptr;            // converted operands of the reduced-precision forms
+  void* d_opA = nullptr;            // staged operands (staged_bytes)
   void* d_opB = nullptr;
   SplitBlock* d_split_a = nullptr;  // split-bf16 form: block tables of the split pass
   SplitBlock* d_split_b = nullptr;
+  XposeBlock* d_xpose_a = nullptr;  // transposed operands: block tables of the transposition pass
+  XposeBlock* d_xpose_b = nullptr;
   double* d_partial = nullptr;      // raw sums between k-windows (laid out like C)
   // device-built k-lists: shapes, offset tables and inner sizes
   uint64_t* d_abits = nullptr;
@@ -228,23 +257,21 @@ static bsm_status prepare(bsm_plan* p) {
   bsm_status st = check_device(&dev);
   if (st != BSM_OK) return st;
   const HostPlan& h = p->hp;
-  if (h.cfg.precision == BSM_FP32) {
-    if (h.a_elems > 0) BSM_HIP(hipMalloc(&p->d_opA, size_t(h.a_elems) * 4), "hipMalloc(A fp32)");
-    if (h.b_elems > 0) BSM_HIP(hipMalloc(&p->d_opB, size_t(h.b_elems) * 4), "hipMalloc(B fp32)");
-  }
-  if (h.cfg.precision == BSM_BF16X3) {
-    if (h.a_elems32 > 0) BSM_HIP(hipMalloc(&p->d_opA, size_t(h.a_elems32) * 6), "hipMalloc(A slices)");
-    if (h.b_elems32 > 0) BSM_HIP(hipMalloc(&p->d_opB, size_t(h.b_elems32) * 6), "hipMalloc(B slices)");
-    const size_t na = h.split_a.size() * sizeof(SplitBlock), nb = h.split_b.size() * sizeof(SplitBlock);
-    if (na) {
-      BSM_HIP(hipMalloc(&p->d_split_a, na), "hipMalloc(split table)");
-      BSM_HIP(hipMemcpy(p->d_split_a, h.split_a.data(), na, hipMemcpyHostToDevice), "hipMemcpy(split table)");
-    }
-    if (nb) {
-      BSM_HIP(hipMalloc(&p->d_split_b, nb), "hipMalloc(split table)");
-      BSM_HIP(hipMemcpy(p->d_split_b, h.split_b.data(), nb, hipMemcpyHostToDevice), "hipMemcpy(split table)");
-    }
-  }
+  const int64_t sa = staged_bytes(h, false), sb = staged_bytes(h, true);
+  if (sa > 0) BSM_HIP(hipMalloc(&p->d_opA, size_t(sa)), "hipMalloc(staged A)");
+  if (sb > 0) BSM_HIP(hipMalloc(&p->d_opB, size_t(sb)), "hipMalloc(staged B)");
+  auto table = [&](auto** dst, const auto& v) -> bsm_status {
+    const size_t bytes = v.size() * sizeof(v[0]);
+    if (!bytes) return BSM_OK;
+    BSM_HIP(hipMalloc(dst, bytes), "hipMalloc(staging table)");
+    BSM_HIP(hipMemcpy(*dst, v.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy(staging table)");
+    return BSM_OK;
+  };
+  bsm_status s1;
+  if ((s1 = table(&p->d_split_a, h.split_a)) != BSM_OK) return s1;
+  if ((s1 = table(&p->d_split_b, h.split_b)) != BSM_OK) return s1;
+  if ((s1 = table(&p->d_xpose_a, h.xpose_a)) != BSM_OK) return s1;
+  if ((s1 = table(&p->d_xpose_b, h.xpose_b)) != BSM_OK) return s1;
   if (h.windows > 1 && h.c_elems > 0)
     BSM_HIP(hipMalloc(&p->d_partial, size_t(h.c_elems) * 8), "hipMalloc(partial)");
   if (h.dev_klists) {
@@ -277,39 +304,63 @@ static bsm_status sync_tasks(bsm_plan* p, hipStream_t stream) {
   return BSM_OK;
 }
 
-// S6: operands in the precision form's element type and layout (queued on s), written into opA
-// and opB (FP32 copies, or bf16 slice planes built with the split tables sa and sb).
-static bsm_status convert_into(const HostPlan& h, const double* dA, const double* dB, void* opA,
-                               void* opB, const SplitBlock* sa, const SplitBlock* sb, hipStream_t s,
-                               ProductArgs& pa) {
-  pa.A = dA;
-  pa.B = dB;
-  pa.a_plane = pa.b_plane = 0;
+// C = A A in the FP32 form with neither operand transposed: one FP32 copy serves both.
+static bool shares_f32_copy(const HostPlan& h, const double* dA, const double* dB) {
+  return h.cfg.precision == BSM_FP32 && !h.cfg.trans_a && !h.cfg.trans_b && dB == dA &&
+         h.b_elems == h.a_elems;
+}
+
+// Where the tile kernels read op(A) and op(B): the caller's buffers or the staged copies.
+static void bind_operands(const HostPlan& h, const double* dA, const double* dB, const Staging& g,
+                          ProductArgs& pa) {
+  pa.A = staged_bytes(h, false) > 0 ? g.opA : dA;
+  pa.B = staged_bytes(h, true) > 0 ? (shares_f32_copy(h, dA, dB) ? g.opA : g.opB) : dB;
+  pa.a_plane = h.cfg.precision == BSM_BF16X3 ? h.a_elems32 : 0;
+  pa.b_plane = h.cfg.precision == BSM_BF16X3 ? h.b_elems32 : 0;
+}
+
+// S6: operands in the precision form's element type and the product's layout (queued on s),
+// written into the staged copies: FP32 copies (transposed block by block for a transposed
+// operand), bf16 slice planes built with the split tables, or op(X) of a transposed FP64 operand.
+static bsm_status convert_into(const HostPlan& h, const double* dA, const double* dB,
+                               const Staging& g, hipStream_t s, ProductArgs& pa) {
+  bind_operands(h, dA, dB, g, pa);
+  const bool ta = h.cfg.trans_a != 0, tb = h.cfg.trans_b != 0;
   if (h.cfg.precision == BSM_FP32) {
-    BSM_HIP(launch_to_f32(dA, static_cast<float*>(opA), h.a_elems, s), "convert A");
-    pa.A = opA;
-    if (dB == dA && h.b_elems == h.a_elems) {
-      pa.B = opA;  // C = A A: one conversion
-    } else {
-      BSM_HIP(launch_to_f32(dB, static_cast<float*>(opB), h.b_elems, s), "convert B");
-      pa.B = opB;
-    }
+    if (ta)
+      BSM_HIP(launch_transpose_f32(g.xa, int64_t(h.xpose_a.size()), dA, static_cast<float*>(g.opA), s),
+              "transpose A");
+    else
+      BSM_HIP(launch_to_f32(dA, static_cast<float*>(g.opA), h.a_elems, s), "convert A");
+    if (shares_f32_copy(h, dA, dB)) return BSM_OK;
+    if (tb)
+      BSM_HIP(launch_transpose_f32(g.xb, int64_t(h.xpose_b.size()), dB, static_cast<float*>(g.opB), s),
+              "transpose B");
+    else
+      BSM_HIP(launch_to_f32(dB, static_cast<float*>(g.opB), h.b_elems, s), "convert B");
   } else if (h.cfg.precision == BSM_BF16X3) {
-    pa.a_plane = h.a_elems32;
-    pa.b_plane = h.b_elems32;
-    BSM_HIP(launch_split_bf16x3(sa, int64_t(h.split_a.size()), dA, static_cast<uint16_t*>(opA),
+    BSM_HIP(launch_split_bf16x3(g.sa, int64_t(h.split_a.size()), dA, static_cast<uint16_t*>(g.opA),
                                 pa.a_plane, s), "split A");
-    BSM_HIP(launch_split_bf16x3(sb, int64_t(h.split_b.size()), dB, static_cast<uint16_t*>(opB),
+    BSM_HIP(launch_split_bf16x3(g.sb, int64_t(h.split_b.size()), dB, static_cast<uint16_t*>(g.opB),
                                 pa.b_plane, s), "split B");
-    pa.A = opA;
-    pa.B = opB;
+  } else {
+    if (ta)
+      BSM_HIP(launch_transpose_f64(g.xa, int64_t(h.xpose_a.size()), dA, static_cast<double*>(g.opA), s),
+              "transpose A");
+    if (tb)
+      BSM_HIP(launch_transpose_f64(g.xb, int64_t(h.xpose_b.size()), dB, static_cast<double*>(g.opB), s),
+              "transpose B");
   }
   return BSM_OK;
 }
 
+static Staging staging_of(const bsm_plan* p) {
+  return Staging{p->d_opA, p->d_opB, p->d_split_a, p->d_split_b, p->d_xpose_a, p->d_xpose_b};
+}
+
 static bsm_status enqueue_convert(bsm_plan* p, const double* dA, const double* dB, hipStream_t s,
                                   ProductArgs& pa) {
-  return convert_into(p->hp, dA, dB, p->d_opA, p->d_opB, p->d_split_a, p->d_split_b, s, pa);
+  return convert_into(p->hp, dA, dB, staging_of(p), s, pa);
 }
 
 static hipError_t launch_form(int precision, int variant, int64_t grid, const TileArgs& a,
@@ -630,7 +681,8 @@ static bsm_status scratch_of(int dev, unsigned char** out) {
 
 // Byte offsets of each buffer inside the static scratch (256-byte aligned); total = bytes used.
 struct StaticLayout {
-  int64_t items = 0, tri = 0, split_a = 0, split_b = 0, opA = 0, opB = 0, partial = 0, total = 0;
+  int64_t items = 0, tri = 0, split_a = 0, split_b = 0, xpose_a = 0, xpose_b = 0, opA = 0, opB = 0,
+          partial = 0, total = 0;
 };
 
 static StaticLayout static_layout(const HostPlan& h) {
@@ -643,15 +695,12 @@ static StaticLayout static_layout(const HostPlan& h) {
   };
   L.items = take(int64_t(h.items.size() * sizeof(Item)));
   L.tri = take(int64_t(h.tri.size() * sizeof(Triple)));
-  if (h.cfg.precision == BSM_FP32) {
-    L.opA = take(h.a_elems * 4);
-    L.opB = take(h.b_elems * 4);
-  } else if (h.cfg.precision == BSM_BF16X3) {
-    L.split_a = take(int64_t(h.split_a.size() * sizeof(SplitBlock)));
-    L.split_b = take(int64_t(h.split_b.size() * sizeof(SplitBlock)));
-    L.opA = take(h.a_elems32 * 6);
-    L.opB = take(h.b_elems32 * 6);
-  }
+  L.split_a = take(int64_t(h.split_a.size() * sizeof(SplitBlock)));
+  L.split_b = take(int64_t(h.split_b.size() * sizeof(SplitBlock)));
+  L.xpose_a = take(int64_t(h.xpose_a.size() * sizeof(XposeBlock)));
+  L.xpose_b = take(int64_t(h.xpose_b.size() * sizeof(XposeBlock)));
+  L.opA = take(staged_bytes(h, false));
+  L.opB = take(staged_bytes(h, true));
   if (h.windows > 1) L.partial = take(h.c_elems * 8);
   L.total = pos;
   return L;
@@ -688,18 +737,22 @@ bsm_status bsm_execute_static(const bsm_plan* plan, double alpha, const double* 
   if (!h.tri.empty())
     BSM_HIP(hipMemcpyAsync(tri, h.tri.data(), h.tri.size() * sizeof(Triple), hipMemcpyHostToDevice, s),
             "hipMemcpyAsync(triples)");
-  SplitBlock* sa = reinterpret_cast<SplitBlock*>(base + L.split_a);
-  SplitBlock* sb = reinterpret_cast<SplitBlock*>(base + L.split_b);
-  if (h.cfg.precision == BSM_BF16X3) {
-    if (!h.split_a.empty())
-      BSM_HIP(hipMemcpyAsync(sa, h.split_a.data(), h.split_a.size() * sizeof(SplitBlock),
-                             hipMemcpyHostToDevice, s), "hipMemcpyAsync(split table)");
-    if (!h.split_b.empty())
-      BSM_HIP(hipMemcpyAsync(sb, h.split_b.data(), h.split_b.size() * sizeof(SplitBlock),
-                             hipMemcpyHostToDevice, s), "hipMemcpyAsync(split table)");
-  }
+  auto table = [&](int64_t at, const auto& v) -> bsm_status {
+    if (!v.empty())
+      BSM_HIP(hipMemcpyAsync(base + at, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice, s),
+              "hipMemcpyAsync(staging table)");
+    return BSM_OK;
+  };
+  if ((st = table(L.split_a, h.split_a)) != BSM_OK) return st;
+  if ((st = table(L.split_b, h.split_b)) != BSM_OK) return st;
+  if ((st = table(L.xpose_a, h.xpose_a)) != BSM_OK) return st;
+  if ((st = table(L.xpose_b, h.xpose_b)) != BSM_OK) return st;
+  const Staging g{base + L.opA, base + L.opB, reinterpret_cast<const SplitBlock*>(base + L.split_a),
+                  reinterpret_cast<const SplitBlock*>(base + L.split_b),
+                  reinterpret_cast<const XposeBlock*>(base + L.xpose_a),
+                  reinterpret_cast<const XposeBlock*>(base + L.xpose_b)};
   ProductArgs pa{};
-  if ((st = convert_into(h, dA, dB, base + L.opA, base + L.opB, sa, sb, s, pa)) != BSM_OK) return st;
+  if ((st = convert_into(h, dA, dB, g, s, pa)) != BSM_OK) return st;
   pa.C = dC;
   pa.c_f32 = h.cfg.out_f32;
   pa.P = h.windows > 1 ? reinterpret_cast<double*>(base + L.partial) : nullptr;
@@ -726,6 +779,8 @@ void bsm_options_default(bsm_options* opt) {
   opt->patch_rows = 0;
   opt->patch_cols = 0;
   opt->device_klists = 0;
+  opt->trans_a = 0;
+  opt->trans_b = 0;
   opt->tune_cache = nullptr;
 }
 
@@ -781,6 +836,8 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
   if (o.patch_rows > 0) cfg.patch_r = o.patch_rows;
   if (o.patch_cols > 0) cfg.patch_c = o.patch_cols;
   cfg.device_klists = o.device_klists;
+  cfg.trans_a = o.trans_a;
+  cfg.trans_b = o.trans_b;
   if (o.tune_cache) cfg.tune_cache = o.tune_cache;
   bsm_plan* p = new (std::nothrow) bsm_plan;
   if (!p) return fail(BSM_E_NOMEM, "host allocation failed");
@@ -820,9 +877,7 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   if (h.dev_klists)
     ws += h.tri_capacity * int64_t(sizeof(Triple)) + int64_t(h.jobs.size() * sizeof(KJob)) +
           int64_t((h.a_bits.size() + h.bt_bits.size()) * 8 + (h.a_tab.size() + h.bt_tab.size() + h.inner.size()) * 8);
-  if (h.cfg.precision == BSM_FP32) ws += (h.a_elems + h.b_elems) * 4;
-  if (h.cfg.precision == BSM_BF16X3)
-    ws += (h.a_elems32 + h.b_elems32) * 6 + int64_t((h.split_a.size() + h.split_b.size()) * sizeof(SplitBlock));
+  ws += staged_bytes(h, false) + staged_bytes(h, true) + staging_table_bytes(h);
   if (h.windows > 1) ws += h.c_elems * 8;
   if (h.cfg.record_timings) ws += int64_t(h.items.size()) * 16;
   info->workspace_bytes = ws;
@@ -989,7 +1044,8 @@ bsm_status bsm_plan_destroy(bsm_plan* plan) {
     plan->gc.release();
     plan->ts.release();
     for (void* ptr : {plan->d_opA, plan->d_opB, static_cast<void*>(plan->d_split_a),
-                      static_cast<void*>(plan->d_split_b), static_cast<void*>(plan->d_partial),
+                      static_cast<void*>(plan->d_split_b), static_cast<void*>(plan->d_xpose_a),
+                      static_cast<void*>(plan->d_xpose_b), static_cast<void*>(plan->d_partial),
                       static_cast<void*>(plan->d_abits), static_cast<void*>(plan->d_btbits),
                       static_cast<void*>(plan->d_atab), static_cast<void*>(plan->d_bttab),
                       static_cast<void*>(plan->d_inner)})
@@ -1074,17 +1130,7 @@ static bsm_status batch_table(bsm_batch* b, const double* alphas, const double* 
     const HostPlan& h = p->hp;
     ProductArgs& pa = t[q];
     std::memset(&pa, 0, sizeof pa);
-    pa.A = dA[q];
-    pa.B = dB[q];
-    if (h.cfg.precision == BSM_FP32) {
-      pa.A = p->d_opA;
-      pa.B = (dB[q] == dA[q] && h.b_elems == h.a_elems) ? p->d_opA : p->d_opB;
-    } else if (h.cfg.precision == BSM_BF16X3) {
-      pa.A = p->d_opA;
-      pa.B = p->d_opB;
-      pa.a_plane = h.a_elems32;
-      pa.b_plane = h.b_elems32;
-    }
+    bind_operands(h, dA[q], dB[q], staging_of(p), pa);
     pa.C = dC[q];
     pa.c_f32 = h.cfg.out_f32;
     pa.P = nullptr;

@@ -69,6 +69,11 @@ hipError_t launch_fill_klists(const KJob* jobs, int64_t njobs, const DevKlists& 
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t stream);
 
 // Three bf16 slices of every block of one operand (see SplitBlock), planes `plane` elements apart.
+// stored blocks of a transposed operand -> the product's packed layout (FP64, or rounded to FP32)
+hipError_t launch_transpose_f64(const XposeBlock* blocks, int64_t nblocks, const double* src,
+                                double* dst, hipStream_t stream);
+hipError_t launch_transpose_f32(const XposeBlock* blocks, int64_t nblocks, const double* src,
+                                float* dst, hipStream_t stream);
 hipError_t launch_split_bf16x3(const SplitBlock* blocks, int64_t nblocks, const double* src,
                                uint16_t* dst, int64_t plane, hipStream_t stream);
 

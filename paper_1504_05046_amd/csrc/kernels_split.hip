@@ -1,5 +1,7 @@
-// Operand conversion for the reduced-precision forms (HBM-bound elementwise pass over the packed
-// tiles; the packed layout is kept, only the element type changes).
+// Operand preparation passes (HBM-bound, ahead of the tile kernels): conversion for the
+// reduced-precision forms (the packed layout is kept, only the element type changes), and the
+// transposition of an operand that the product reads as X^T (Sec. 2.1's transposed variants) into
+// the product's packed layout.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -99,6 +101,53 @@ __global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict
       __syncthreads();
     }
   }
+}
+
+// One workgroup per block: the stored rows x cols block goes through LDS in 64 x 64 tiles (reads
+// coalesced along the stored rows, writes along the transposed rows) and is written cols x rows,
+// rounded to T.  The 65-element row pitch spreads both phases over the LDS banks.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_blocks(const XposeBlock* __restrict__ blocks,
+                                                        const double* __restrict__ src,
+                                                        T* __restrict__ dst) {
+  __shared__ double tile[64][65];
+  const XposeBlock b = blocks[blockIdx.x];
+  const double* sb = src + b.src_off;
+  T* db = dst + b.dst_off;
+  for (int r0 = 0; r0 < b.rows; r0 += 64)
+    for (int c0 = 0; c0 < b.cols; c0 += 64) {
+      const int th = b.rows - r0 < 64 ? b.rows - r0 : 64;
+      const int tw = b.cols - c0 < 64 ? b.cols - c0 : 64;
+      for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int rr = e >> 6, cc = e & 63;
+        if (rr < th && cc < tw) tile[rr][cc] = sb[int64_t(r0 + rr) * b.cols + c0 + cc];
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int cc = e >> 6, rr = e & 63;
+        if (rr < th && cc < tw) db[int64_t(c0 + cc) * b.rows + r0 + rr] = T(tile[rr][cc]);
+      }
+      __syncthreads();
+    }
+}
+
+template <typename T>
+static hipError_t launch_transpose(const XposeBlock* blocks, int64_t nblocks, const double* src,
+                                   T* dst, hipStream_t stream) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_blocks<T>, dim3(uint32_t(nblocks)), dim3(256), 0, stream, blocks,
+                     src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_f64(const XposeBlock* blocks, int64_t nblocks, const double* src,
+                                double* dst, hipStream_t stream) {
+  return launch_transpose(blocks, nblocks, src, dst, stream);
+}
+
+hipError_t launch_transpose_f32(const XposeBlock* blocks, int64_t nblocks, const double* src,
+                                float* dst, hipStream_t stream) {
+  return launch_transpose(blocks, nblocks, src, dst, stream);
 }
 
 hipError_t launch_split_bf16x3(const SplitBlock* blocks, int64_t nblocks, const double* src,

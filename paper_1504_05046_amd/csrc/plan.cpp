@@ -62,6 +62,22 @@ static int64_t pack_offsets(int64_t R, int64_t C, const std::vector<int64_t>& rs
   return pos;
 }
 
+// The R x C shape `bits` transposed (C x R, same word layout).
+static std::vector<uint64_t> transpose_bits(const uint64_t* bits, int64_t R, int64_t C) {
+  const int64_t wc = words_for(C), wr = words_for(R);
+  std::vector<uint64_t> out(size_t(C * wr), 0);
+  for (int64_t i = 0; i < R; ++i)
+    for (int64_t w = 0; w < wc; ++w) {
+      uint64_t x = bits[i * wc + w];
+      while (x) {
+        const int64_t j = w * 64 + __builtin_ctzll(x);
+        x &= x - 1;
+        out[size_t(j * wr + (i >> 6))] |= uint64_t(1) << (i & 63);
+      }
+    }
+  return out;
+}
+
 // Sub-tile cuts of one C block: a dimension of nb16 16-row blocks is cut into the fewest pieces
 // of at most `per` blocks, as equal as the 16-row granule allows (larger pieces first).
 static void cut_dim(int m, int per, std::vector<std::pair<int, int>>& out) {
@@ -373,8 +389,12 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   if (!(e = check_tiling("row_sizes", M, rows)).empty()) return e;
   if (!(e = check_tiling("inner_sizes", K, inner)).empty()) return e;
   if (!(e = check_tiling("col_sizes", N, cols)).empty()) return e;
-  if (!(e = check_bits("a_bits", M, K, a_bits)).empty()) return e;
-  if (!(e = check_bits("b_bits", K, N, b_bits)).empty()) return e;
+  if (cfg.trans_a < 0 || cfg.trans_a > 1 || cfg.trans_b < 0 || cfg.trans_b > 1)
+    return "trans_a and trans_b must be 0 or 1";
+  const bool ta = cfg.trans_a != 0, tb = cfg.trans_b != 0;
+  // a transposed operand's shape is given as stored: K x M for A, N x K for B
+  if (!(e = check_bits("a_bits", ta ? K : M, ta ? M : K, a_bits)).empty()) return e;
+  if (!(e = check_bits("b_bits", tb ? N : K, tb ? K : N, b_bits)).empty()) return e;
   if (cfg.precision < 0 || cfg.precision > 2) return "unknown precision";
   if (cfg.sched < 0 || cfg.sched > 1) return "unknown scheduler";
   if (cfg.k_window < 0) return "negative k_window";
@@ -390,12 +410,27 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   p.inner.assign(inner, inner + K);
   p.cols.assign(cols, cols + N);
   int64_t wk = words_for(K), wn = words_for(N);
-  p.a_bits.assign(a_bits, a_bits + M * wk);
-  p.b_bits.assign(b_bits, b_bits + K * wn);
+  // the shapes of op(A) and op(B), which everything below works on
+  if (ta) p.a_bits = transpose_bits(a_bits, K, M);
+  else p.a_bits.assign(a_bits, a_bits + M * wk);
+  if (tb) p.b_bits = transpose_bits(b_bits, N, K);
+  else p.b_bits.assign(b_bits, b_bits + K * wn);
 
-  // S1: packed offsets of A and B
+  // S1: packed offsets of op(A) and op(B) in the product's layout, and for a transposed operand
+  // the offsets of its blocks as stored (st_a[k M + i] of A_ki = op(A)_ik, st_b[j K + k])
   p.a_elems = pack_offsets(M, K, p.rows, p.inner, p.a_bits, p.a_off, p.a_blocks);
   p.b_elems = pack_offsets(K, N, p.inner, p.cols, p.b_bits, p.b_off, p.b_blocks);
+  std::vector<int64_t> st_a, st_b;
+  if (ta) {
+    int64_t nb;
+    std::vector<uint64_t> sb(a_bits, a_bits + K * words_for(M));
+    pack_offsets(K, M, p.inner, p.rows, sb, st_a, nb);
+  }
+  if (tb) {
+    int64_t nb;
+    std::vector<uint64_t> sb(b_bits, b_bits + N * wk);
+    pack_offsets(N, K, p.cols, p.inner, sb, st_b, nb);
+  }
 
   // S2: C-shape, row i = OR of B's rows k over A's present (i, k)
   p.c_bits.assign(size_t(M * wn), 0);
@@ -429,8 +464,13 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
         int64_t o = p.a_off[size_t(i * K + k)];
         if (o < 0) continue;
         a_off32[size_t(i * K + k)] = pos;
-        p.split_a.push_back(SplitBlock{o, pos, int32_t(p.rows[size_t(i)]), int32_t(p.inner[size_t(k)]),
-                                       int32_t(p.inner[size_t(k)]), 0});
+        // stored as r_i x s_k, or (transposed) as s_k x r_i
+        if (ta)
+          p.split_a.push_back(SplitBlock{st_a[size_t(k * M + i)], pos, int32_t(p.rows[size_t(i)]),
+                                         int32_t(p.inner[size_t(k)]), int32_t(p.rows[size_t(i)]), 1});
+        else
+          p.split_a.push_back(SplitBlock{o, pos, int32_t(p.rows[size_t(i)]), int32_t(p.inner[size_t(k)]),
+                                         int32_t(p.inner[size_t(k)]), 0});
         pos += p.rows[size_t(i)] * pad_k(p.inner[size_t(k)]);
       }
     p.a_elems32 = pos;
@@ -440,8 +480,13 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
         int64_t o = p.b_off[size_t(k * N + j)];
         if (o < 0) continue;
         b_off32[size_t(k * N + j)] = pos;
-        p.split_b.push_back(SplitBlock{o, pos, int32_t(p.cols[size_t(j)]), int32_t(p.inner[size_t(k)]),
-                                       int32_t(p.cols[size_t(j)]), 1});
+        // stored as s_k x t_j (written transposed), or (transposed) as t_j x s_k
+        if (tb)
+          p.split_b.push_back(SplitBlock{st_b[size_t(j * K + k)], pos, int32_t(p.cols[size_t(j)]),
+                                         int32_t(p.inner[size_t(k)]), int32_t(p.inner[size_t(k)]), 0});
+        else
+          p.split_b.push_back(SplitBlock{o, pos, int32_t(p.cols[size_t(j)]), int32_t(p.inner[size_t(k)]),
+                                         int32_t(p.cols[size_t(j)]), 1});
         pos += p.cols[size_t(j)] * pad_k(p.inner[size_t(k)]);
       }
     p.b_elems32 = pos;
@@ -449,6 +494,25 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
       *code = BSM_E_NOMEM;
       return "slice planes exceed the descriptor range";
     }
+  } else {
+    // FP64 / FP32 forms: a transposed operand is written into the product's layout by a
+    // transposition pass (stored block rows x cols -> cols x rows), block by block
+    if (ta)
+      for (int64_t i = 0; i < M; ++i)
+        for (int64_t k = 0; k < K; ++k) {
+          const int64_t o = p.a_off[size_t(i * K + k)];
+          if (o >= 0)
+            p.xpose_a.push_back(XposeBlock{st_a[size_t(k * M + i)], o, int32_t(p.inner[size_t(k)]),
+                                           int32_t(p.rows[size_t(i)])});
+        }
+    if (tb)
+      for (int64_t k = 0; k < K; ++k)
+        for (int64_t j = 0; j < N; ++j) {
+          const int64_t o = p.b_off[size_t(k * N + j)];
+          if (o >= 0)
+            p.xpose_b.push_back(XposeBlock{st_b[size_t(j * K + k)], o, int32_t(p.cols[size_t(j)]),
+                                           int32_t(p.inner[size_t(k)])});
+        }
   }
 
   // S3: k-lists (A row AND B column) and tasks.  First, per present C block, the k-list's length

@@ -39,6 +39,7 @@ struct PlanConfig {
   int out_f32 = 0;    // C holds FP32 elements
   int patch_r = 4, patch_c = 8;  // C blocks per patch (ORDER_PATCH)
   int device_klists = 0;  // 0: when the triples would not fit the host list, 1: always, -1: never
+  int trans_a = 0, trans_b = 0;  // the product reads A^T (B^T): the operand is stored transposed
   std::string tune_cache;  // autotuner choices file ("" = none)
 };
 
@@ -113,6 +114,9 @@ struct HostPlan {
   // split-bf16 form: slice-plane layout of A and B and the split pass's block table
   int64_t a_elems32 = 0, b_elems32 = 0;
   std::vector<SplitBlock> split_a, split_b;
+  // FP64 and FP32 forms with a transposed operand: the transposition pass's block tables (stored
+  // blocks -> op(A), op(B) in the product's packed layout)
+  std::vector<XposeBlock> xpose_a, xpose_b;
   int64_t k_window_eff = 0;      // inner blocks per k-window
   int64_t windows = 1;           // number of k-windows
 

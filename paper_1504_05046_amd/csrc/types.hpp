@@ -52,6 +52,16 @@ struct SplitBlock {
   int32_t transpose;  // 1: the source is ks x rows (B) and is written transposed
 };
 
+// One block of a transposed operand as the transposition pass sees it: the stored block at
+// src_off is rows x cols (row-major); it is written transposed (cols x rows, row-major) at dst_off
+// of the operand in the product's own layout.
+struct XposeBlock {
+  int64_t src_off;
+  int64_t dst_off;
+  int32_t rows;
+  int32_t cols;
+};
+
 // One (i,k,j) block triple of a C block's k-list: where A_ik and B_kj start and the inner block
 // size.  a = A offset | (s_k << 48);  b = B offset | (k << 48).
 struct Triple {

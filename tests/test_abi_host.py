@@ -327,3 +327,48 @@ def test_device_klists_limits_on_host():
     _expect(bsm.E_UNSUPPORTED, lambda: bsm.Batch([dev]))
     L = bsm.load()
     assert L.bsm_execute_static(dev.handle, 1.0, 1 << 32, 1 << 36, 1 << 40, 0, None) == bsm.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("ta,tb", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("precision", [bsm.FP64, bsm.FP32, bsm.BF16X3])
+def test_transposed_operand_plans(precision, ta, tb):
+    """With an operand stored transposed the plan reads its shape as stored: C's shape, offsets,
+    flop count and triples are those of op(A) op(B) (oracle), and the staged copy of a transposed
+    FP64 operand shows in the workspace."""
+    p = gen.random_problem(60 + 2 * ta + tb, 5, 7, 4, 1, 90, 0.5, 0.6)
+    a_bits = gen.pack_bits(p.a_mask.T) if ta else p.a_bits()
+    b_bits = gen.pack_bits(p.b_mask.T) if tb else p.b_bits()
+    plan = bsm.Plan(p.rows, p.inner, p.cols, a_bits, b_bits, precision=precision, trans_a=ta,
+                    trans_b=tb)
+    plain = bsm.Plan.from_problem(p, precision=precision)
+    c_bits = oracle.product_shape(p.M, p.K, p.N, a_bits, b_bits, bool(ta), bool(tb))
+    assert np.array_equal(plan.c_shape(), c_bits)
+    assert np.array_equal(plan.c_offsets(), oracle.block_offsets(p.rows, p.cols, c_bits)[0])
+    i, j = plan.info(), plain.info()
+    assert (i.a_elems, i.b_elems, i.c_elems, i.triples, i.tasks) == \
+        (j.a_elems, j.b_elems, j.c_elems, j.triples, j.tasks)
+    assert i.useful_flops == j.useful_flops
+    extra = (ta * i.a_elems + tb * i.b_elems) * 8 if precision == bsm.FP64 else 0
+    assert i.workspace_bytes >= j.workspace_bytes + extra
+
+
+def test_transposed_shapes_validated():
+    """A transposed operand's bitmap has the stored dimensions: its padding is checked against
+    them, the binding checks its length, and trans flags other than 0/1 are rejected."""
+    M, K, N = 70, 3, 2
+    rows, inner, cols = [4] * M, [5] * K, [6] * N
+    a_st = gen.pack_bits(np.ones((K, M), bool))      # K x M: 3 rows of 2 words
+    b = gen.pack_bits(np.ones((K, N), bool))
+    bsm.Plan(rows, inner, cols, a_st, b, trans_a=1).close()
+    with pytest.raises(ValueError):                   # M x K layout: 70 rows of 1 word
+        bsm.Plan(rows, inner, cols, a_st, b)
+    bad = a_st.copy()
+    bad[1] |= np.uint64(1) << np.uint64(6)            # column 70 of a 70-column row: padding
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Plan(rows, inner, cols, bad, b, trans_a=1)
+    assert e.value.code == bsm.E_INVALID
+    for flag in ({"trans_a": 2}, {"trans_b": -1}):
+        with pytest.raises(bsm.BsmError) as e:
+            bsm.Plan(rows, inner, cols, a_st, b, **flag) if "trans_a" in flag else \
+                bsm.Plan(rows, inner, cols, gen.pack_bits(np.ones((M, K), bool)), b, **flag)
+        assert e.value.code == bsm.E_INVALID
