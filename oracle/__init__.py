@@ -53,6 +53,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_bsmm_blocks.argtypes = [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p, _p,
                                          ctypes.c_double, _i64, _p, _p, _p, _p, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int]
+        L.oracle_zbsmm.argtypes = [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p, _p, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int, _p, ctypes.c_int, ctypes.c_int]
+        L.oracle_zbsmm_blocks.argtypes = [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p, _p, _i64, _p,
+                                          _p, _p, _p, ctypes.c_int, ctypes.c_int]
         L.oracle_concurrent_iterations.restype = _i64
         L.oracle_concurrent_iterations.argtypes = [_i64, _i64, _i64]
         L.oracle_memory_overhead.restype = ctypes.c_double
@@ -180,6 +184,60 @@ def bsmm_blocks(rows, inner, cols, a_bits, b_bits, A, B, sel: Sequence[Tuple[int
                                   int(bool(trans_a)), int(bool(trans_b)))
     if st != 0:
         raise ValueError("oracle_bsmm_blocks failed")
+    blocks, pos = [], 0
+    for (i, j), n in zip(sel, sizes):
+        blocks.append(out[pos:pos + n].reshape(int(r[i]), int(t[j])).copy())
+        pos += n
+    return blocks, [bool(x) for x in present[:len(sel)]]
+
+
+def _ops(op):
+    """'N' / 'T' / 'C' (or 0 / 1 / 2, or a bool for the transpose) -> 0 / 1 / 2."""
+    return {"N": 0, "T": 1, "C": 2}[op] if isinstance(op, str) else int(op)
+
+
+def zbsmm(rows, inner, cols, a_bits, b_bits, A, B, alpha: complex = 1.0,
+          C: Optional[np.ndarray] = None, op_a="N", op_b="N") -> np.ndarray:
+    """Packed complex C = alpha*op(A)*op(B) (+ C when C is given); op is 'N', 'T' (transpose) or
+    'C' (adjoint); A, B, C are complex128 arrays of the packed blocks.  Returns a new array."""
+    r, s, t = (_c64(x, np.int64) for x in (rows, inner, cols))
+    a = _c64(a_bits, np.uint64)
+    b = _c64(b_bits, np.uint64)
+    oa, ob = _ops(op_a), _ops(op_b)
+    Ad = _c64(A, np.complex128)
+    Bd = Ad if B is A else _c64(B, np.complex128)
+    c_bits = product_shape(r.size, s.size, t.size, a, b, oa != 0, ob != 0)
+    _, total = block_offsets(r, t, c_bits)
+    out = np.zeros(total, np.complex128) if C is None else _c64(C, np.complex128).copy()
+    if out.size != total:
+        raise ValueError("C has the wrong size")
+    al = complex(alpha)
+    st = lib().oracle_zbsmm(r.size, s.size, t.size, _ptr(r), _ptr(s), _ptr(t), _ptr(a), _ptr(b),
+                            _ptr(Ad), _ptr(Bd), al.real, al.imag, int(C is not None), _ptr(out),
+                            oa, ob)
+    if st != 0:
+        raise MemoryError("oracle_zbsmm failed")
+    return out
+
+
+def zbsmm_blocks(rows, inner, cols, a_bits, b_bits, A, B, sel: Sequence[Tuple[int, int]],
+                 op_a="N", op_b="N"):
+    """Selected complex C blocks (alpha = 1): (list of 2-D complex arrays, presence flags)."""
+    r, s, t = (_c64(x, np.int64) for x in (rows, inner, cols))
+    a = _c64(a_bits, np.uint64)
+    b = _c64(b_bits, np.uint64)
+    Ad = _c64(A, np.complex128)
+    Bd = Ad if B is A else _c64(B, np.complex128)
+    si = _c64([q[0] for q in sel], np.int64)
+    sj = _c64([q[1] for q in sel], np.int64)
+    sizes = [int(r[i]) * int(t[j]) for i, j in sel]
+    out = np.zeros(max(1, sum(sizes)), dtype=np.complex128)
+    present = np.zeros(max(1, len(sel)), dtype=np.int32)
+    st = lib().oracle_zbsmm_blocks(r.size, s.size, t.size, _ptr(r), _ptr(s), _ptr(t), _ptr(a),
+                                   _ptr(b), _ptr(Ad), _ptr(Bd), len(sel), _ptr(si), _ptr(sj),
+                                   _ptr(out), _ptr(present), _ops(op_a), _ops(op_b))
+    if st != 0:
+        raise ValueError("oracle_zbsmm_blocks failed")
     blocks, pos = [], 0
     for (i, j), n in zip(sel, sizes):
         blocks.append(out[pos:pos + n].reshape(int(r[i]), int(t[j])).copy())

@@ -31,6 +31,12 @@
  * the stored matrix's row-major block order; likewise op(B) = B^T is stored as N x K blocks of
  * t_j x s_k elements.  op(A)_ik is then the transpose of the stored block (k, i).
  *
+ * Complex elements (Sec. 4.3 names real and complex element types as both supported): the same
+ * product over complex blocks, each element stored as two doubles (real part, then imaginary
+ * part), offsets counted in complex elements.  Here op(X) may also be the adjoint X^H (transpose
+ * and conjugate), and alpha is complex.  Every complex multiply-add is written out in real
+ * arithmetic: (ar + i ai)(br + i bi) = (ar br - ai bi) + i (ar bi + ai br).
+ *
  * Also here: the paper's two closed forms, the concurrent-iteration limit (Eq. 1) and the
  * per-node memory overhead of one SUMMA iteration (Eq. 2).
  */
@@ -241,6 +247,93 @@ int oracle_bsmm_blocks(int64_t M, int64_t K, int64_t N, const int64_t* r, const 
     int64_t hw = r[sel_i[q]] * t[sel_j[q]];
     for (int64_t e = 0; e < hw; ++e) o[e] = alpha * o[e];
   }
+  free(pos); teardown(&p);
+  return 0;
+}
+
+/* One complex C block (interleaved, r_i x t_j) = sum over present k of op(A)_ik op(B)_kj, k
+ * ascending, elements in i-k-j order; ca / cb conjugate the operand.  Returns presence. */
+static int zblock_product(const problem* p, const double* A, const double* B, int ca, int cb,
+                          int64_t i, int64_t j, double* out) {
+  int64_t h = p->r[i], w = p->t[j];
+  int present = 0;
+  for (int64_t e = 0; e < 2 * h * w; ++e) out[e] = 0.0;
+  for (int64_t k = 0; k < p->K; ++k) {
+    int64_t ao = a_at(p, i, k), bo = b_at(p, k, j);
+    if (ao < 0 || bo < 0) continue;
+    present = 1;
+    int64_t d = p->s[k];
+    const double* a = A + 2 * ao;
+    const double* b = B + 2 * bo;
+    for (int64_t x = 0; x < h; ++x)
+      for (int64_t y = 0; y < d; ++y) {
+        int64_t ea = p->ta ? y * h + x : x * d + y;
+        double ar = a[2 * ea], ai = ca ? -a[2 * ea + 1] : a[2 * ea + 1];
+        for (int64_t z = 0; z < w; ++z) {
+          int64_t eb = p->tb ? z * d + y : y * w + z;
+          double br = b[2 * eb], bi = cb ? -b[2 * eb + 1] : b[2 * eb + 1];
+          out[2 * (x * w + z)] += ar * br - ai * bi;
+          out[2 * (x * w + z) + 1] += ar * bi + ai * br;
+        }
+      }
+  }
+  return present;
+}
+
+/* Complex product: C = alpha op(A) op(B) (+ C), A, B, C interleaved complex; op_a, op_b: 0 = as
+ * is, 1 = transpose, 2 = adjoint (stored as for the transpose). */
+int oracle_zbsmm(int64_t M, int64_t K, int64_t N, const int64_t* r, const int64_t* s,
+                 const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits, const double* A,
+                 const double* B, double alpha_re, double alpha_im, int accumulate, double* C,
+                 int op_a, int op_b) {
+  problem p;
+  if (setup(&p, M, K, N, r, s, t, a_bits, b_bits, op_a != 0, op_b != 0)) { teardown(&p); return -1; }
+  int64_t wn = words_of(N);
+  uint64_t* c_bits = (uint64_t*)calloc((size_t)(M * wn > 0 ? M * wn : 1), sizeof(uint64_t));
+  int64_t* c_off = (int64_t*)malloc((size_t)(M * N > 0 ? M * N : 1) * sizeof(int64_t));
+  if (!c_bits || !c_off) { free(c_bits); free(c_off); teardown(&p); return -1; }
+  shape_of_product(&p, c_bits);
+  oracle_block_offsets(M, N, r, t, c_bits, c_off);
+  int status = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < M * N; ++q) {
+    int64_t i = q / N, j = q % N;
+    int64_t co = c_off[q];
+    if (co < 0) continue;
+    int64_t hw = r[i] * t[j];
+    double* tmp = (double*)malloc((size_t)(hw > 0 ? 2 * hw : 1) * sizeof(double));
+    if (!tmp) { status = -1; continue; }
+    zblock_product(&p, A, B, op_a == 2, op_b == 2, i, j, tmp);
+    for (int64_t e = 0; e < hw; ++e) {
+      double xr = tmp[2 * e], xi = tmp[2 * e + 1];
+      double vr = alpha_re * xr - alpha_im * xi, vi = alpha_re * xi + alpha_im * xr;
+      double* c = C + 2 * (co + e);
+      c[0] = accumulate ? vr + c[0] : vr;
+      c[1] = accumulate ? vi + c[1] : vi;
+    }
+    free(tmp);
+  }
+  free(c_bits); free(c_off); teardown(&p);
+  return status;
+}
+
+/* Selected complex C blocks (alpha = 1, no accumulation), as oracle_bsmm_blocks. */
+int oracle_zbsmm_blocks(int64_t M, int64_t K, int64_t N, const int64_t* r, const int64_t* s,
+                        const int64_t* t, const uint64_t* a_bits, const uint64_t* b_bits,
+                        const double* A, const double* B, int64_t nsel, const int64_t* sel_i,
+                        const int64_t* sel_j, double* out, int32_t* present, int op_a, int op_b) {
+  problem p;
+  if (setup(&p, M, K, N, r, s, t, a_bits, b_bits, op_a != 0, op_b != 0)) { teardown(&p); return -1; }
+  int64_t* pos = (int64_t*)malloc((size_t)(nsel + 1) * sizeof(int64_t));
+  if (!pos) { teardown(&p); return -1; }
+  pos[0] = 0;
+  for (int64_t q = 0; q < nsel; ++q) {
+    if (sel_i[q] < 0 || sel_i[q] >= M || sel_j[q] < 0 || sel_j[q] >= N) { free(pos); teardown(&p); return -2; }
+    pos[q + 1] = pos[q] + 2 * r[sel_i[q]] * t[sel_j[q]];
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < nsel; ++q)
+    present[q] = zblock_product(&p, A, B, op_a == 2, op_b == 2, sel_i[q], sel_j[q], out + pos[q]);
   free(pos); teardown(&p);
   return 0;
 }

@@ -41,6 +41,7 @@ import numpy as np
 # spawn-key tags, so that the streams for tilings, shapes and values never coincide
 _TILING, _SHAPE, _VALUES, _SCALE, _POINTS = 1, 2, 3, 4, 5
 MAT_A, MAT_B = 0, 1
+_IMAG_A, _IMAG_B = 2, 3  # streams of the imaginary parts of complex operands
 
 
 def _rng(seed: int, *key: int) -> np.random.Generator:
@@ -143,10 +144,10 @@ def stored_transpose(rsz, csz, mask, data) -> Tuple[np.ndarray, np.ndarray]:
     rsz = np.asarray(rsz, dtype=np.int64)
     csz = np.asarray(csz, dtype=np.int64)
     mask = np.asarray(mask, dtype=bool)
-    data = np.asarray(data, dtype=np.float64)
+    data = np.asarray(data)
     offs = np.concatenate([[0], np.cumsum(rsz[np.nonzero(mask)[0]] * csz[np.nonzero(mask)[1]])])
     where = {(int(i), int(j)): int(offs[n]) for n, (i, j) in enumerate(zip(*np.nonzero(mask)))}
-    out = np.empty(int(offs[-1]), dtype=np.float64)
+    out = np.empty(int(offs[-1]), dtype=data.dtype if data.size else np.float64)
     pos = 0
     mt = mask.T
     for j, i in zip(*np.nonzero(mt)):
@@ -155,6 +156,18 @@ def stored_transpose(rsz, csz, mask, data) -> Tuple[np.ndarray, np.ndarray]:
         out[pos:pos + h * w] = data[o:o + h * w].reshape(h, w).T.reshape(-1)
         pos += h * w
     return pack_bits(mt), out
+
+
+def imag_parts(p: Problem, seed: int, draw=None) -> Tuple[np.ndarray, np.ndarray]:
+    """Complex operands of the same block structure: A and B with p's values as real parts and
+    independent seeded draws (same shapes, same distribution as `draw`, N(0,1) by default) as
+    imaginary parts, packed like p's buffers (complex128)."""
+    draw = draw or _normal
+    ia = _fill_blocks(seed, _IMAG_A, p.a_mask, p.rows, p.inner, draw)
+    ib = ia if p.b_is_a else _fill_blocks(seed, _IMAG_B, p.b_mask, p.inner, p.cols, draw)
+    za = p.a_data + 1j * ia
+    zb = za if p.b_is_a else p.b_data + 1j * ib
+    return za, zb
 
 
 def _fill_blocks(seed: int, mat: int, mask: np.ndarray, rsz: np.ndarray, csz: np.ndarray,

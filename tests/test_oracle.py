@@ -449,3 +449,97 @@ def test_adam_decreases_loss():
         loss, g = oracle.mlp_loss_grad(F, H1, H2, params, X, T)
         oracle.adam_step(params, g, m, v, step, lr=3e-3)
     assert loss < 0.2 * first
+
+
+# ---- complex elements ------------------------------------------------------------------------
+def _zdense(rsz, csz, mask, z):
+    return to_dense(rsz, csz, mask, z.real) + 1j * to_dense(rsz, csz, mask, z.imag)
+
+
+def _zstored(rsz, csz, mask, D, op):
+    """Packed storage of an operand whose product-side view is D under op ('N', 'T', 'C')."""
+    if op == "N":
+        return gen.pack_bits(mask), from_dense(rsz, csz, mask, D.real) + 1j * from_dense(rsz, csz, mask, D.imag)
+    S = D.T if op == "T" else D.conj().T
+    return gen.pack_bits(mask.T), from_dense(csz, rsz, mask.T, S.real) + 1j * from_dense(csz, rsz, mask.T, S.imag)
+
+
+@pytest.mark.parametrize("op_a,op_b", [("N", "N"), ("T", "N"), ("N", "C"), ("C", "T"), ("C", "C")])
+def test_complex_matches_numpy_dense(op_a, op_b):
+    """Complex C = alpha op(A) op(B) + C against numpy's complex product of the dense matrices,
+    elementwise within a Higham-type bound (each real output is a real dot product of length 2n
+    over the real and imaginary parts)."""
+    p = gen.random_problem(410, 4, 5, 3, 1, 11, 0.6, 0.6)
+    za, zb = gen.imag_parts(p, 411)
+    A, B = _zdense(p.rows, p.inner, p.a_mask, za), _zdense(p.inner, p.cols, p.b_mask, zb)
+    a_bits, a_st = _zstored(p.rows, p.inner, p.a_mask, A, op_a)
+    b_bits, b_st = _zstored(p.inner, p.cols, p.b_mask, B, op_b)
+    c_mask = (p.a_mask.astype(np.int64) @ p.b_mask.astype(np.int64)) > 0
+    C0 = np.random.default_rng(4).standard_normal((2, packed_offsets(p.rows, p.cols, c_mask)[1]))
+    C0 = C0[0] + 1j * C0[1]
+    alpha = 0.75 - 1.5j
+    got = oracle.zbsmm(p.rows, p.inner, p.cols, a_bits, b_bits, a_st, b_st, alpha, C=C0,
+                       op_a=op_a, op_b=op_b)
+    ref = alpha * (A @ B) + _zdense(p.rows, p.cols, c_mask, C0)
+    n = int(p.inner.sum())
+    mag = lambda X: np.abs(X.real) + np.abs(X.imag)
+    bound = 4 * higham_gamma(2 * n + 4) * (mag(np.array([alpha]))[0] * (mag(A) @ mag(B)) +
+                                           mag(_zdense(p.rows, p.cols, c_mask, C0))) + 1e-300
+    diff = _zdense(p.rows, p.cols, c_mask, got) - ref
+    assert np.all(np.abs(diff.real) <= bound) and np.all(np.abs(diff.imag) <= bound)
+
+
+def test_complex_real_inputs_reduce_to_the_real_product():
+    """Zero imaginary parts: the real part is the real oracle's product bit for bit (every
+    dropped term is an exact zero) and the imaginary part is zero."""
+    p = gen.random_problem(420, 5, 4, 6, 1, 20, 0.6, 0.6)
+    got = oracle.zbsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data + 0j,
+                       p.b_data + 0j, 2.0)
+    real = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data, 2.0)
+    assert np.array_equal(got.real, real) and np.all(got.imag == 0)
+
+
+def test_complex_gaussian_integers_exact():
+    """Gaussian-integer blocks: every partial sum is an integer below 2^53, so the product equals
+    numpy's exactly."""
+    p = gen.integer_problem(430, 4, 6, 5, 1, 30, 0.6, 0.6)
+    rng = np.random.default_rng(431)
+    za = p.a_data + 1j * rng.integers(-8, 9, p.a_data.size)
+    zb = p.b_data + 1j * rng.integers(-8, 9, p.b_data.size)
+    got = oracle.zbsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), za, zb, 1j)
+    A, B = _zdense(p.rows, p.inner, p.a_mask, za), _zdense(p.inner, p.cols, p.b_mask, zb)
+    c_mask = (p.a_mask.astype(np.int64) @ p.b_mask.astype(np.int64)) > 0
+    assert np.array_equal(_zdense(p.rows, p.cols, c_mask, got), 1j * (A @ B))
+
+
+def test_complex_adjoint_identity_bitwise():
+    """(AB)^H = B^H A^H: multiplying the stored B and A as adjoint operands gives the conjugate
+    transpose of C = AB bit for bit (the same products, negated, summed in the same order)."""
+    p = gen.random_problem(440, 4, 5, 3, 1, 12, 0.6, 0.7)
+    za, zb = gen.imag_parts(p, 441)
+    c = oracle.zbsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), za, zb)
+    ch = oracle.zbsmm(p.cols, p.inner, p.rows, p.b_bits(), p.a_bits(), zb, za, op_a="C", op_b="C")
+    c_mask = (p.a_mask.astype(np.int64) @ p.b_mask.astype(np.int64)) > 0
+    D = _zdense(p.rows, p.cols, c_mask, c)
+    Dh = _zdense(p.cols, p.rows, c_mask.T, ch)
+    assert np.array_equal(D.conj().T, Dh)
+
+
+def test_complex_selected_blocks_match_full_product():
+    p = gen.random_problem(450, 5, 4, 5, 1, 16, 0.6, 0.6)
+    za, zb = gen.imag_parts(p, 451)
+    zt_bits, zt = gen.stored_transpose(p.inner, p.cols, p.b_mask, zb.conj())
+    full = oracle.zbsmm(p.rows, p.inner, p.cols, p.a_bits(), zt_bits, za, zt, op_b="C")
+    c_mask = (p.a_mask.astype(np.int64) @ p.b_mask.astype(np.int64)) > 0
+    off, _ = packed_offsets(p.rows, p.cols, c_mask)
+    sel = [(i, j) for i in range(p.M) for j in range(p.N)]
+    blocks, pres = oracle.zbsmm_blocks(p.rows, p.inner, p.cols, p.a_bits(), zt_bits, za, zt, sel,
+                                       op_b="C")
+    for (i, j), blk, pr in zip(sel, blocks, pres):
+        assert pr == bool(c_mask[i, j])
+        if pr:
+            o = off[(i, j)]
+            assert np.array_equal(full[o:o + blk.size], blk.reshape(-1))
+    # adjoint of the stored conj-transpose is B itself: same result as the plain product
+    plain = oracle.zbsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), za, zb)
+    assert np.array_equal(full, plain)
