@@ -80,6 +80,19 @@ typedef enum {
   BSM_OUT_F32 = 1  /* C holds FP32 elements: alpha * sum (+ C) is formed in FP64, rounded once */
 } bsm_out;
 
+/* Element type of A, B and C.  Complex elements (Sec. 4.3 lists real and complex types as both
+ * supported) are stored as two doubles each, real part first, offsets and sizes counted in complex
+ * elements.  A complex product runs as the real product of embeddings: op(A)_ik becomes the real
+ * block [[Re, -Im], [Im, Re]] (2 r_i x 2 s_k) and op(B)_kj the block [Re; Im] (2 s_k x t_j), so
+ * that the real C block is [Re C_ij; Im C_ij]; an embedding pass before the tile kernels and a
+ * complex epilogue (alpha, accumulation, interleaving) after them run on the same stream.  Every
+ * precision form applies to the real product.  Complex block sizes are at most 32767 rows and
+ * inner columns. */
+typedef enum {
+  BSM_REAL = 0,
+  BSM_COMPLEX = 1
+} bsm_elem;
+
 /* How tasks are ordered (never changes the numbers). */
 typedef enum {
   BSM_SCHED_FLOPS = 0, /* cost = flop count */
@@ -115,8 +128,10 @@ typedef struct {
                               = always on the device, in batches of at most n triples (the device
                               buffer for them; the default batch is 2^27 triples, 2 GiB) */
   int32_t trans_a;        /* 1 = the product reads A^T: A is stored as the K x M block matrix
-                             (see Transposes); 0 = as is */
-  int32_t trans_b;        /* 1 = the product reads B^T: B is stored as the N x K block matrix */
+                             (see Transposes); 2 = the adjoint A^H (stored as for 1; the same as
+                             1 for real elements); 0 = as is */
+  int32_t trans_b;        /* the same for B: 1 = B^T, 2 = B^H, stored as the N x K block matrix */
+  int32_t elem;           /* bsm_elem: element type of A, B and C */
   const char* tune_cache; /* NULL, or a file where bsm_autotune looks up and records its choices
                              (lines "signature variant"); the string is copied */
 } bsm_options;
@@ -134,6 +149,7 @@ typedef struct {
                               classes use different variants (bsm_plan_tile_classes) */
   int32_t out;             /* bsm_out: element type of C */
   int32_t device_klists;   /* 1: the k-lists are built on the device, batch by batch */
+  int32_t elem;            /* bsm_elem; a_elems, b_elems, c_elems count elements of this type */
 } bsm_plan_info;
 
 typedef struct bsm_batch bsm_batch;
@@ -182,9 +198,20 @@ bsm_status bsm_plan_c_offsets(const bsm_plan* plan, int64_t* c_offsets);
  * (c_elems elements of the plan's output type).  With accumulate = 0 every element of C is
  * written (present blocks only); with accumulate = 1 C must hold the previous values.  dA may
  * equal dB.  Errors: BSM_E_INVALID for null pointers or overlapping C; BSM_E_UNSUPPORTED without
- * a gfx950 device; BSM_E_HIP if a launch fails. */
+ * a gfx950 device; BSM_E_HIP if a launch fails.  On a complex plan alpha is real (see
+ * bsm_execute_complex). */
 bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
                        void* dC, int accumulate, void* stream);
+
+/* C = alpha op(A) op(B) (+ C) with complex alpha = alpha_re + i alpha_im, for a plan with complex
+ * elements (Sec. 4.3's complex type); the same call as bsm_execute otherwise.  dA, dB: device
+ * pointers to the packed complex tiles (a_elems, b_elems complex elements, two doubles each,
+ * 16-byte aligned); dC: c_elems complex elements of the output type (complex FP64, or complex
+ * FP32 with BSM_OUT_F32), aligned to its element.  The embedded operands and the real product's
+ * C live in device memory the plan owns.  Errors: as bsm_execute; BSM_E_INVALID for misaligned
+ * buffers; BSM_E_MISMATCH for a nonzero alpha_im on a real plan. */
+bsm_status bsm_execute_complex(bsm_plan* plan, double alpha_re, double alpha_im, const double* dA,
+                               const double* dB, void* dC, int accumulate, void* stream);
 
 /* For callers that cannot allocate device memory (code under hipGraph capture, tight serving
  * loops, harnesses that forbid hipMalloc): the same product as bsm_execute, with the same kernels
@@ -198,7 +225,8 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
  * counters and per-task clocks are not kept (bsm_plan_verify does not cover these calls), and the
  * plan's graph option is ignored.  Errors: as bsm_execute; BSM_E_NOMEM (checked before any device
  * work) if the plan needs more than the 64 MiB, with the size in bsm_last_error();
- * BSM_E_UNSUPPORTED for a plan whose k-lists are built on the device. */
+ * BSM_E_UNSUPPORTED for a plan whose k-lists are built on the device or a plan with complex
+ * elements. */
 bsm_status bsm_execute_static(const bsm_plan* plan, double alpha, const double* dA,
                               const double* dB, void* dC, int accumulate, void* stream);
 
@@ -264,7 +292,8 @@ bsm_status bsm_plan_destroy(bsm_plan* plan);
  * while the operand pointers, alphas and accumulate stay the same.  The plans must outlive the batch and must not run
  * elsewhere while the batch executes.  An FP64 plan may appear more than once (each entry is a
  * product with its own operands); an FP32 or split-bf16 plan only once, since it converts its
- * operands into buffers it owns (BSM_E_INVALID otherwise). */
+ * operands into buffers it owns (BSM_E_INVALID otherwise).  Members have real elements
+ * (BSM_E_UNSUPPORTED for a complex plan). */
 bsm_status bsm_batch_create(bsm_batch** out, bsm_plan* const* plans, int64_t n);
 
 /* Task count, total useful flops and tile variant (id + 1, or 0 when the tasks mix variants) of a

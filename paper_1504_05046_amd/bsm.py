@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "bsm.h")
 FP64, FP32, BF16X3 = 0, 1, 2
 SCHED_FLOPS, SCHED_MLP = 0, 1
 OUT_F64, OUT_F32 = 0, 1
+REAL, COMPLEX = 0, 1
 ORDER_DEFAULT, ORDER_INTERLEAVE, ORDER_LOCALITY, ORDER_LPT, ORDER_PATCH = 0, 1, 2, 3, 4
 
 OK, E_INVALID, E_MISMATCH, E_NOMEM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
@@ -38,7 +39,8 @@ class Options(ctypes.Structure):
                 ("out", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("patch_rows", ctypes.c_int32), ("patch_cols", ctypes.c_int32),
                 ("device_klists", ctypes.c_int32), ("trans_a", ctypes.c_int32),
-                ("trans_b", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
+                ("trans_b", ctypes.c_int32), ("elem", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -49,7 +51,8 @@ class PlanInfo(ctypes.Structure):
                 ("triples", ctypes.c_int64), ("tasks", ctypes.c_int64),
                 ("useful_flops", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
                 ("k_windows", ctypes.c_int64), ("tile", ctypes.c_int32),
-                ("out", ctypes.c_int32), ("device_klists", ctypes.c_int32)]
+                ("out", ctypes.c_int32), ("device_klists", ctypes.c_int32),
+                ("elem", ctypes.c_int32)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -79,6 +82,8 @@ def load() -> ctypes.CDLL:
     L.bsm_plan_c_shape.argtypes = [_p, _p]
     L.bsm_plan_c_offsets.argtypes = [_p, _p]
     L.bsm_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
+    L.bsm_execute_complex.argtypes = [_p, ctypes.c_double, ctypes.c_double, _p, _p, _p,
+                                      ctypes.c_int, _p]
     L.bsm_execute_static.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
     L.bsm_plan_verify.argtypes = [_p, _p]
     L.bsm_plan_tile_classes.argtypes = [_p, _p, ctypes.c_int32]
@@ -149,14 +154,14 @@ def _arr(a, dtype):
 
 def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, tile=0,
             use_graph=0, out=OUT_F64, order=ORDER_DEFAULT, patch=(0, 0), device_klists=0,
-            tune_cache=None, trans_a=0, trans_b=0) -> Options:
+            tune_cache=None, trans_a=0, trans_b=0, elem=0) -> Options:
     o = Options()
     load().bsm_options_default(ctypes.byref(o))
     o.precision, o.sched, o.k_window, o.record_timings, o.tile = precision, sched, k_window, record_timings, tile
     o.use_graph, o.out, o.order = use_graph, out, order
     o.patch_rows, o.patch_cols = int(patch[0]), int(patch[1])
     o.device_klists = int(device_klists)
-    o.trans_a, o.trans_b = int(trans_a), int(trans_b)
+    o.trans_a, o.trans_b, o.elem = int(trans_a), int(trans_b), int(elem)
     o.tune_cache = tune_cache.encode() if tune_cache else None
     return o
 
@@ -193,8 +198,8 @@ def _dev_ptr(t) -> int:
 
 def _check_operands(info, A, B, C):
     """Device buffers handed to the library must hold the plan's element counts and be
-    contiguous device tensors of the right type: FP64 A and B, C in the plan's output type (the
-    C ABI only sees the pointers)."""
+    contiguous device tensors of the right type: FP64 (complex128) A and B, C in the plan's output
+    type (the C ABI only sees the pointers)."""
     bufs = (("A", A, info.a_elems), ("B", B, info.b_elems), ("C", C, info.c_elems))
     for name, t, need in bufs:
         if need > 0 and t is None:
@@ -203,7 +208,11 @@ def _check_operands(info, A, B, C):
             raise ValueError(f"{name} holds {t.numel()} elements, the plan needs {need}")
     used = [(name, t) for name, t, need in bufs if need > 0 and t is not None]
     for name, t in used:
-        want = "torch.float32" if (name == "C" and info.out == OUT_F32) else "torch.float64"
+        f32 = name == "C" and info.out == OUT_F32
+        if info.elem == COMPLEX:
+            want = "torch.complex64" if f32 else "torch.complex128"
+        else:
+            want = "torch.float32" if f32 else "torch.float64"
         if getattr(t, "dtype", None) is not None and str(t.dtype) != want:
             raise ValueError(f"{name} must be {want[6:]}, got {t.dtype}")
     for name, t in used:
@@ -267,7 +276,14 @@ class Plan:
     def execute(self, A, B, C, alpha: float = 1.0, accumulate: bool = False, stream=None):
         """C = alpha*A*B (+C); A, B are FP64 device tensors holding the packed tiles, C a device
         tensor of the plan's output type."""
-        _check_operands(self.info(), A, B, C)
+        info = self.info()
+        _check_operands(info, A, B, C)
+        if info.elem == COMPLEX:
+            a = complex(alpha)
+            _check(load().bsm_execute_complex(self._h, a.real, a.imag, _dev_ptr(A), _dev_ptr(B),
+                                              _dev_ptr(C), int(bool(accumulate)),
+                                              _stream_handle(stream)))
+            return
         _check(load().bsm_execute(self._h, float(alpha), _dev_ptr(A), _dev_ptr(B), _dev_ptr(C),
                                   int(bool(accumulate)), _stream_handle(stream)))
 

@@ -200,7 +200,14 @@ static int64_t staged_bytes(const HostPlan& h, bool b) {
 // Bytes of the block tables of the staging passes.
 static int64_t staging_table_bytes(const HostPlan& h) {
   return int64_t((h.split_a.size() + h.split_b.size()) * sizeof(SplitBlock) +
-                 (h.xpose_a.size() + h.xpose_b.size()) * sizeof(XposeBlock));
+                 (h.xpose_a.size() + h.xpose_b.size()) * sizeof(XposeBlock) +
+                 (h.zembed_a.size() + h.zembed_b.size()) * sizeof(ZBlock) +
+                 h.zc.size() * sizeof(ZCBlock));
+}
+
+// Complex elements: bytes of the embedded operands and of the real product's C.
+static int64_t complex_bytes(const HostPlan& h) {
+  return h.cplx ? (h.a_elems + h.b_elems + h.c_elems) * 8 : 0;
 }
 
 struct bsm_plan {
@@ -212,6 +219,12 @@ struct bsm_plan {
   SplitBlock* d_split_b = nullptr;
   XposeBlock* d_xpose_a = nullptr;  // transposed operands: block tables of the transposition pass
   XposeBlock* d_xpose_b = nullptr;
+  double* d_zA = nullptr;           // complex elements: the embedded operands, the real product's
+  double* d_zB = nullptr;           // [Re; Im] C blocks, and the tables of the passes
+  double* d_zP = nullptr;
+  ZBlock* d_zembed_a = nullptr;
+  ZBlock* d_zembed_b = nullptr;
+  ZCBlock* d_zc = nullptr;
   double* d_partial = nullptr;      // raw sums between k-windows (laid out like C)
   // device-built k-lists: shapes, offset tables and inner sizes
   uint64_t* d_abits = nullptr;
@@ -272,6 +285,14 @@ static bsm_status prepare(bsm_plan* p) {
   if ((s1 = table(&p->d_split_b, h.split_b)) != BSM_OK) return s1;
   if ((s1 = table(&p->d_xpose_a, h.xpose_a)) != BSM_OK) return s1;
   if ((s1 = table(&p->d_xpose_b, h.xpose_b)) != BSM_OK) return s1;
+  if (h.cplx) {
+    if ((s1 = table(&p->d_zembed_a, h.zembed_a)) != BSM_OK) return s1;
+    if ((s1 = table(&p->d_zembed_b, h.zembed_b)) != BSM_OK) return s1;
+    if ((s1 = table(&p->d_zc, h.zc)) != BSM_OK) return s1;
+    if (h.a_elems > 0) BSM_HIP(hipMalloc(&p->d_zA, size_t(h.a_elems) * 8), "hipMalloc(embedded A)");
+    if (h.b_elems > 0) BSM_HIP(hipMalloc(&p->d_zB, size_t(h.b_elems) * 8), "hipMalloc(embedded B)");
+    if (h.c_elems > 0) BSM_HIP(hipMalloc(&p->d_zP, size_t(h.c_elems) * 8), "hipMalloc(complex C parts)");
+  }
   if (h.windows > 1 && h.c_elems > 0)
     BSM_HIP(hipMalloc(&p->d_partial, size_t(h.c_elems) * 8), "hipMalloc(partial)");
   if (h.dev_klists) {
@@ -363,6 +384,12 @@ static bsm_status enqueue_convert(bsm_plan* p, const double* dA, const double* d
   return convert_into(p->hp, dA, dB, staging_of(p), s, pa);
 }
 
+// The whole product on stream q: (complex: embedding of the operands), operand staging, the tile
+// launches, (complex: the epilogue with alpha = ar + i ai).  Real plans take alpha = ar.
+static bsm_status enqueue_product(bsm_plan* plan, double ar, double ai, const double* dA,
+                                  const double* dB, void* dC, int accumulate, int skip,
+                                  hipStream_t q);
+
 static hipError_t launch_form(int precision, int variant, int64_t grid, const TileArgs& a,
                               hipStream_t s) {
   if (precision == BSM_FP64) return launch_tiles_f64(variant, grid, a, s);
@@ -418,9 +445,12 @@ static bsm_status check_operands(const HostPlan& h, const double* dA, const doub
                                  const void* dC, int accumulate) {
   if ((h.a_elems > 0 && !dA) || (h.b_elems > 0 && !dB) || (h.c_elems > 0 && !dC))
     return fail(BSM_E_INVALID, "null tile buffer");
-  const int64_t cb = h.c_elems * (h.cfg.out_f32 ? 4 : 8);
-  if (overlaps(dC, cb, dA, h.a_elems * 8) || overlaps(dC, cb, dB, h.b_elems * 8))
+  const int64_t es = h.cplx ? 16 : 8;  // bytes per element of A and B
+  const int64_t cb = h.user_c() * (h.user_out_f32() ? 4 : 8) * (h.cplx ? 2 : 1);
+  if (overlaps(dC, cb, dA, h.user_a() * es) || overlaps(dC, cb, dB, h.user_b() * es))
     return fail(BSM_E_INVALID, "C overlaps A or B");
+  if (h.cplx && ((uintptr_t(dA) | uintptr_t(dB)) % 16 || uintptr_t(dC) % (h.user_out_f32() ? 8 : 16)))
+    return fail(BSM_E_INVALID, "complex buffers must be aligned to their element size");
   if (accumulate != 0 && accumulate != 1) return fail(BSM_E_INVALID, "accumulate must be 0 or 1");
   return BSM_OK;
 }
@@ -718,6 +748,7 @@ bsm_status bsm_execute_static(const bsm_plan* plan, double alpha, const double* 
   if (st != BSM_OK) return st;
   if (h.dev_klists)
     return fail(BSM_E_UNSUPPORTED, "bsm_execute_static needs the k-lists in the plan's host list");
+  if (h.cplx) return fail(BSM_E_UNSUPPORTED, "bsm_execute_static runs real plans only");
   const StaticLayout L = static_layout(h);
   if (L.total > kStaticScratchBytes)
     return fail(BSM_E_NOMEM, "the plan needs " + std::to_string(L.total) +
@@ -781,6 +812,7 @@ void bsm_options_default(bsm_options* opt) {
   opt->device_klists = 0;
   opt->trans_a = 0;
   opt->trans_b = 0;
+  opt->elem = BSM_REAL;
   opt->tune_cache = nullptr;
 }
 
@@ -836,8 +868,11 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
   if (o.patch_rows > 0) cfg.patch_r = o.patch_rows;
   if (o.patch_cols > 0) cfg.patch_c = o.patch_cols;
   cfg.device_klists = o.device_klists;
-  cfg.trans_a = o.trans_a;
-  cfg.trans_b = o.trans_b;
+  if (o.elem != BSM_REAL && o.elem != BSM_COMPLEX) return fail(BSM_E_INVALID, "unknown element type");
+  cfg.cplx = o.elem == BSM_COMPLEX;
+  // for real elements the adjoint is the transpose
+  cfg.trans_a = (!cfg.cplx && o.trans_a == 2) ? 1 : o.trans_a;
+  cfg.trans_b = (!cfg.cplx && o.trans_b == 2) ? 1 : o.trans_b;
   if (o.tune_cache) cfg.tune_cache = o.tune_cache;
   bsm_plan* p = new (std::nothrow) bsm_plan;
   if (!p) return fail(BSM_E_NOMEM, "host allocation failed");
@@ -867,9 +902,9 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   info->a_blocks = h.a_blocks;
   info->b_blocks = h.b_blocks;
   info->c_blocks = h.c_blocks;
-  info->a_elems = h.a_elems;
-  info->b_elems = h.b_elems;
-  info->c_elems = h.c_elems;
+  info->a_elems = h.user_a();
+  info->b_elems = h.user_b();
+  info->c_elems = h.user_c();
   info->triples = h.triples_total;
   info->tasks = int64_t(h.items.size());
   info->useful_flops = h.useful_flops;
@@ -877,14 +912,15 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   if (h.dev_klists)
     ws += h.tri_capacity * int64_t(sizeof(Triple)) + int64_t(h.jobs.size() * sizeof(KJob)) +
           int64_t((h.a_bits.size() + h.bt_bits.size()) * 8 + (h.a_tab.size() + h.bt_tab.size() + h.inner.size()) * 8);
-  ws += staged_bytes(h, false) + staged_bytes(h, true) + staging_table_bytes(h);
+  ws += staged_bytes(h, false) + staged_bytes(h, true) + staging_table_bytes(h) + complex_bytes(h);
   if (h.windows > 1) ws += h.c_elems * 8;
   if (h.cfg.record_timings) ws += int64_t(h.items.size()) * 16;
   info->workspace_bytes = ws;
   info->k_windows = h.windows;
   info->tile = reported_tile(h);
-  info->out = h.cfg.out_f32 ? BSM_OUT_F32 : BSM_OUT_F64;
+  info->out = h.user_out_f32() ? BSM_OUT_F32 : BSM_OUT_F64;
   info->device_klists = h.dev_klists ? 1 : 0;
+  info->elem = h.cplx ? BSM_COMPLEX : BSM_REAL;
   return BSM_OK;
 }
 
@@ -899,13 +935,46 @@ bsm_status bsm_plan_c_offsets(const bsm_plan* plan, int64_t* c_offsets) {
   if (!plan || (!c_offsets && !plan->hp.c_off.empty())) return fail(BSM_E_INVALID, "null argument");
   if (!plan->hp.c_off.empty())
     std::memcpy(c_offsets, plan->hp.c_off.data(), plan->hp.c_off.size() * sizeof(int64_t));
+  if (plan->hp.cplx)  // the real product's [Re; Im] block sits at twice the complex offset
+    for (size_t q = 0; q < plan->hp.c_off.size(); ++q)
+      if (c_offsets[q] >= 0) c_offsets[q] /= 2;
   return BSM_OK;
 }
 
-bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
-                       void* dC, int accumulate, void* stream) {
+static bsm_status enqueue_product(bsm_plan* plan, double ar, double ai, const double* dA,
+                                  const double* dB, void* dC, int accumulate, int skip,
+                                  hipStream_t q) {
+  const HostPlan& h = plan->hp;
+  const double* xA = dA;
+  const double* xB = dB;
+  if (h.cplx) {
+    BSM_HIP(launch_embed_complex(plan->d_zembed_a, int64_t(h.zembed_a.size()), dA, plan->d_zA, q),
+            "embed A");
+    BSM_HIP(launch_embed_complex(plan->d_zembed_b, int64_t(h.zembed_b.size()), dB, plan->d_zB, q),
+            "embed B");
+    xA = plan->d_zA;
+    xB = plan->d_zB;
+  }
+  ProductArgs pa{};
+  bsm_status r = enqueue_convert(plan, xA, xB, q, pa);
+  if (r != BSM_OK) return r;
+  pa.C = h.cplx ? static_cast<void*>(plan->d_zP) : dC;
+  pa.c_f32 = h.cfg.out_f32;
+  pa.P = plan->d_partial;
+  pa.alpha = h.cplx ? 1.0 : ar;
+  r = enqueue_tiles(h, plan->ts, nullptr, pa, h.cplx ? 0 : accumulate, skip, q, &plan->dk);
+  if (r != BSM_OK || !h.cplx) return r;
+  BSM_HIP(launch_complex_epilogue(plan->d_zc, int64_t(h.zc.size()), plan->d_zP, dC, h.z_out_f32,
+                                  ar, ai, accumulate, q), "complex epilogue");
+  return BSM_OK;
+}
+
+bsm_status bsm_execute_complex(bsm_plan* plan, double alpha_re, double alpha_im, const double* dA,
+                               const double* dB, void* dC, int accumulate, void* stream) {
   if (!plan) return fail(BSM_E_INVALID, "plan is null");
   const HostPlan& h = plan->hp;
+  if (!h.cplx && alpha_im != 0.0)
+    return fail(BSM_E_MISMATCH, "a real plan takes a real alpha");
   hipStream_t s = static_cast<hipStream_t>(stream);
   bsm_status st = check_operands(h, dA, dB, dC, accumulate);
   if (st != BSM_OK) return st;
@@ -913,20 +982,13 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
   if ((st = sync_tasks(plan, s)) != BSM_OK) return st;
   if (h.items.empty()) return BSM_OK;
   auto body = [&](hipStream_t q) -> bsm_status {
-    ProductArgs pa{};
-    bsm_status r = enqueue_convert(plan, dA, dB, q, pa);
-    if (r != BSM_OK) return r;
-    pa.C = dC;
-    pa.c_f32 = h.cfg.out_f32;
-    pa.P = plan->d_partial;
-    pa.alpha = alpha;
-    return enqueue_tiles(h, plan->ts, nullptr, pa, accumulate, plan->skip_task, q, &plan->dk);
+    return enqueue_product(plan, alpha_re, alpha_im, dA, dB, dC, accumulate, plan->skip_task, q);
   };
   if (!plan->use_graph) {
     st = body(s);
   } else {
     std::vector<uint64_t> key{uint64_t(uintptr_t(dA)), uint64_t(uintptr_t(dB)), uint64_t(uintptr_t(dC)),
-                              bits_of(alpha), uint64_t(accumulate)};
+                              bits_of(alpha_re), bits_of(alpha_im), uint64_t(accumulate)};
     st = plan->gc.run(key, body, s);
     if (st == BSM_OK && plan->ts.stamps) plan->ts.timed = true;
   }
@@ -935,6 +997,11 @@ bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const dou
     plan->ts.expected += h.windows;
   }
   return st;
+}
+
+bsm_status bsm_execute(bsm_plan* plan, double alpha, const double* dA, const double* dB,
+                       void* dC, int accumulate, void* stream) {
+  return bsm_execute_complex(plan, alpha, 0.0, dA, dB, dC, accumulate, stream);
 }
 
 bsm_status bsm_plan_verify(bsm_plan* plan, void* stream) {
@@ -992,14 +1059,7 @@ bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, void
   };
   if (!tune_cache_lookup(h.cfg.tune_cache, key, nvar, cv)) {
     auto body = [&](hipStream_t q) -> bsm_status {
-      ProductArgs pa{};
-      bsm_status r = enqueue_convert(plan, dA, dB, q, pa);
-      if (r != BSM_OK) return r;
-      pa.C = dC;
-      pa.c_f32 = h.cfg.out_f32;
-      pa.P = plan->d_partial;
-      pa.alpha = 1.0;
-      return enqueue_tiles(h, plan->ts, nullptr, pa, 0, -1, q, &plan->dk);
+      return enqueue_product(plan, 1.0, 0.0, dA, dB, dC, 0, -1, q);
     };
     auto timeit = [&](float* ms) {
       plan->ts.used = true;
@@ -1046,6 +1106,9 @@ bsm_status bsm_plan_destroy(bsm_plan* plan) {
     for (void* ptr : {plan->d_opA, plan->d_opB, static_cast<void*>(plan->d_split_a),
                       static_cast<void*>(plan->d_split_b), static_cast<void*>(plan->d_xpose_a),
                       static_cast<void*>(plan->d_xpose_b), static_cast<void*>(plan->d_partial),
+                      static_cast<void*>(plan->d_zA), static_cast<void*>(plan->d_zB),
+                      static_cast<void*>(plan->d_zP), static_cast<void*>(plan->d_zembed_a),
+                      static_cast<void*>(plan->d_zembed_b), static_cast<void*>(plan->d_zc),
                       static_cast<void*>(plan->d_abits), static_cast<void*>(plan->d_btbits),
                       static_cast<void*>(plan->d_atab), static_cast<void*>(plan->d_bttab),
                       static_cast<void*>(plan->d_inner)})
@@ -1063,6 +1126,7 @@ bsm_status bsm_batch_create(bsm_batch** out, bsm_plan* const* plans, int64_t n) 
   std::vector<const HostPlan*> parts;
   for (int64_t q = 0; q < n; ++q) {
     if (!plans[q]) return fail(BSM_E_INVALID, "null plan in batch");
+    if (plans[q]->hp.cplx) return fail(BSM_E_UNSUPPORTED, "batches take real plans only");
     // the FP32 and split-bf16 forms convert a member's operands into buffers the plan owns, so a
     // plan can stand for one product of the batch only
     if (plans[q]->hp.cfg.precision != BSM_FP64)

@@ -74,6 +74,12 @@ hipError_t launch_transpose_f64(const XposeBlock* blocks, int64_t nblocks, const
                                 double* dst, hipStream_t stream);
 hipError_t launch_transpose_f32(const XposeBlock* blocks, int64_t nblocks, const double* src,
                                 float* dst, hipStream_t stream);
+// complex elements: the real embedding of the operands, and C = alpha [Re; Im] (+ C) as complex
+hipError_t launch_embed_complex(const ZBlock* blocks, int64_t nblocks, const double* src,
+                                double* dst, hipStream_t stream);
+hipError_t launch_complex_epilogue(const ZCBlock* blocks, int64_t nblocks, const double* P,
+                                   void* C, int c_f32, double ar, double ai, int accumulate,
+                                   hipStream_t stream);
 hipError_t launch_split_bf16x3(const SplitBlock* blocks, int64_t nblocks, const double* src,
                                uint16_t* dst, int64_t plane, hipStream_t stream);
 

@@ -1,7 +1,8 @@
 // Operand preparation passes (HBM-bound, ahead of the tile kernels): conversion for the
 // reduced-precision forms (the packed layout is kept, only the element type changes), and the
 // transposition of an operand that the product reads as X^T (Sec. 2.1's transposed variants) into
-// the product's packed layout.
+// the product's packed layout, and for complex elements the real embedding of the operands and
+// the complex epilogue.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -148,6 +149,98 @@ hipError_t launch_transpose_f64(const XposeBlock* blocks, int64_t nblocks, const
 hipError_t launch_transpose_f32(const XposeBlock* blocks, int64_t nblocks, const double* src,
                                 float* dst, hipStream_t stream) {
   return launch_transpose(blocks, nblocks, src, dst, stream);
+}
+
+// One workgroup per complex block: op(X) goes through LDS in 32 x 32 tiles of complex elements
+// (reads along the stored rows, transposed or not; writes along the embedded rows) and is written
+// as [[Re, -Im], [Im, Re]] (left operand, row pitch 2 cols) or [Re; Im] (right operand).
+__global__ __launch_bounds__(256) void embed_complex(const ZBlock* __restrict__ blocks,
+                                                     const double2* __restrict__ src,
+                                                     double* __restrict__ dst) {
+  __shared__ double2 tile[32][33];
+  const ZBlock b = blocks[blockIdx.x];
+  const bool tr = (b.mode & kZTrans) != 0, cj = (b.mode & kZConj) != 0;
+  const bool right = (b.mode & kZRight) != 0;
+  const double2* sb = src + b.src_off;
+  double* db = dst + b.dst_off;
+  const int R = b.rows, W = b.cols;
+  for (int x0 = 0; x0 < R; x0 += 32)
+    for (int y0 = 0; y0 < W; y0 += 32) {
+      for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+        const int xx = tr ? (e & 31) : (e >> 5), yy = tr ? (e >> 5) : (e & 31);
+        if (x0 + xx < R && y0 + yy < W) {
+          const int64_t idx = tr ? int64_t(y0 + yy) * R + x0 + xx : int64_t(x0 + xx) * W + y0 + yy;
+          double2 v = sb[idx];
+          if (cj) v.y = -v.y;
+          tile[xx][yy] = v;
+        }
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+        const int xx = e >> 5, yy = e & 31, x = x0 + xx, y = y0 + yy;
+        if (x < R && y < W) {
+          const double2 v = tile[xx][yy];
+          if (right) {
+            db[int64_t(x) * W + y] = v.x;
+            db[int64_t(R + x) * W + y] = v.y;
+          } else {
+            const int64_t ld = 2 * int64_t(W);
+            db[int64_t(x) * ld + y] = v.x;
+            db[int64_t(x) * ld + W + y] = -v.y;
+            db[int64_t(R + x) * ld + y] = v.y;
+            db[int64_t(R + x) * ld + W + y] = v.x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+hipError_t launch_embed_complex(const ZBlock* blocks, int64_t nblocks, const double* src,
+                                double* dst, hipStream_t stream) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(embed_complex, dim3(uint32_t(nblocks)), dim3(256), 0, stream, blocks,
+                     reinterpret_cast<const double2*>(src), dst);
+  return hipGetLastError();
+}
+
+// One workgroup per complex C block: C = alpha (Re + i Im) (+ C) from the real product's
+// [Re; Im] block, stored interleaved as complex FP64 (V = double2) or complex FP32 (float2).
+template <typename V>
+__global__ __launch_bounds__(256) void complex_epilogue(const ZCBlock* __restrict__ blocks,
+                                                        const double* __restrict__ P,
+                                                        V* __restrict__ C, double ar, double ai,
+                                                        int accumulate) {
+  const ZCBlock b = blocks[blockIdx.x];
+  const double* pr = P + 2 * b.off;
+  const double* pi = pr + b.n;
+  V* c = C + b.off;
+  for (int64_t e = threadIdx.x; e < b.n; e += blockDim.x) {
+    const double xr = pr[e], xi = pi[e];
+    double vr = ar * xr - ai * xi, vi = ar * xi + ai * xr;
+    if (accumulate) {
+      const V old = c[e];
+      vr += double(old.x);
+      vi += double(old.y);
+    }
+    V out;
+    out.x = decltype(out.x)(vr);
+    out.y = decltype(out.y)(vi);
+    c[e] = out;
+  }
+}
+
+hipError_t launch_complex_epilogue(const ZCBlock* blocks, int64_t nblocks, const double* P,
+                                   void* C, int c_f32, double ar, double ai, int accumulate,
+                                   hipStream_t stream) {
+  if (nblocks <= 0) return hipSuccess;
+  if (c_f32)
+    hipLaunchKernelGGL(complex_epilogue<float2>, dim3(uint32_t(nblocks)), dim3(256), 0, stream,
+                       blocks, P, static_cast<float2*>(C), ar, ai, accumulate);
+  else
+    hipLaunchKernelGGL(complex_epilogue<double2>, dim3(uint32_t(nblocks)), dim3(256), 0, stream,
+                       blocks, P, static_cast<double2*>(C), ar, ai, accumulate);
+  return hipGetLastError();
 }
 
 hipError_t launch_split_bf16x3(const SplitBlock* blocks, int64_t nblocks, const double* src,

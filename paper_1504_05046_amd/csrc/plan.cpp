@@ -380,12 +380,92 @@ void cut_items(HostPlan& p, const int class_var[kSizeClasses]) {
   }
 }
 
+// Complex elements: the product runs as the real product of the embeddings
+//   op(A)_ik -> [[Re, -Im], [Im, Re]] (2 r_i x 2 s_k),  op(B)_kj -> [Re; Im] (2 s_k x t_j),
+// whose C block is [Re C_ij; Im C_ij] (2 r_i x t_j), planned like any real product over the
+// doubled row and inner tilings; the tables of the embedding pass and of the epilogue are added.
+static std::string build_complex_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
+                                      const int64_t* inner, int64_t N, const int64_t* cols,
+                                      const uint64_t* a_bits, const uint64_t* b_bits,
+                                      const PlanConfig& cfg, int* code) {
+  std::string e;
+  if (cfg.cplx != 1) return "elem must be 0 (real) or 1 (complex)";
+  if (!(e = check_tiling("row_sizes", M, rows)).empty()) return e;
+  if (!(e = check_tiling("inner_sizes", K, inner)).empty()) return e;
+  if (!(e = check_tiling("col_sizes", N, cols)).empty()) return e;
+  for (int64_t i = 0; i < M; ++i)
+    if (rows[i] > kMaxBlock / 2) return "row_sizes: complex blocks allow at most 32767 rows";
+  for (int64_t k = 0; k < K; ++k)
+    if (inner[k] > kMaxBlock / 2) return "inner_sizes: complex blocks allow at most 32767 inner";
+  if (cfg.trans_a < 0 || cfg.trans_a > 2 || cfg.trans_b < 0 || cfg.trans_b > 2)
+    return "trans_a and trans_b must be 0, 1 or 2";
+  const int oa = cfg.trans_a, ob = cfg.trans_b;
+  if (!(e = check_bits("a_bits", oa ? K : M, oa ? M : K, a_bits)).empty()) return e;
+  if (!(e = check_bits("b_bits", ob ? N : K, ob ? K : N, b_bits)).empty()) return e;
+  const int64_t wk = words_for(K), wn = words_for(N);
+  std::vector<uint64_t> la = oa ? transpose_bits(a_bits, K, M)
+                                : std::vector<uint64_t>(a_bits, a_bits + M * wk);
+  std::vector<uint64_t> lb = ob ? transpose_bits(b_bits, N, K)
+                                : std::vector<uint64_t>(b_bits, b_bits + K * wn);
+  std::vector<int64_t> r2(rows, rows + M), s2(inner, inner + K);
+  for (auto& x : r2) x *= 2;
+  for (auto& x : s2) x *= 2;
+  PlanConfig rc = cfg;
+  rc.cplx = 0;
+  rc.trans_a = rc.trans_b = 0;
+  rc.out_f32 = 0;  // the real product writes FP64 [Re; Im] blocks; the epilogue rounds
+  e = build_plan(p, M, r2.data(), K, s2.data(), N, cols, la.data(), lb.data(), rc, code);
+  if (!e.empty()) return e;
+  *code = BSM_E_INVALID;
+  p.cplx = 1;
+  p.zop_a = oa;
+  p.zop_b = ob;
+  p.z_out_f32 = cfg.out_f32;
+  p.cfg.cplx = 1;
+  // the caller's packed offsets (complex elements) of the stored blocks
+  std::vector<int64_t> st_a, st_b;
+  int64_t nb;
+  {
+    std::vector<int64_t> r1(rows, rows + M), s1(inner, inner + K), t1(cols, cols + N);
+    std::vector<uint64_t> sa(a_bits, a_bits + (oa ? K * words_for(M) : M * wk));
+    std::vector<uint64_t> sb(b_bits, b_bits + (ob ? N * wk : K * wn));
+    if (oa) pack_offsets(K, M, s1, r1, sa, st_a, nb);
+    else pack_offsets(M, K, r1, s1, sa, st_a, nb);
+    if (ob) pack_offsets(N, K, t1, s1, sb, st_b, nb);
+    else pack_offsets(K, N, s1, t1, sb, st_b, nb);
+  }
+  const int ma = (oa ? kZTrans : 0) | (oa == 2 ? kZConj : 0);
+  const int mb = kZRight | (ob ? kZTrans : 0) | (ob == 2 ? kZConj : 0);
+  for (int64_t i = 0; i < M; ++i)
+    for (int64_t k = 0; k < K; ++k) {
+      const int64_t o = p.a_off[size_t(i * K + k)];
+      if (o < 0) continue;
+      const int64_t so = oa ? st_a[size_t(k * M + i)] : st_a[size_t(i * K + k)];
+      p.zembed_a.push_back(ZBlock{so, o, int32_t(rows[i]), int32_t(inner[k]), ma, 0});
+    }
+  for (int64_t k = 0; k < K; ++k)
+    for (int64_t j = 0; j < N; ++j) {
+      const int64_t o = p.b_off[size_t(k * N + j)];
+      if (o < 0) continue;
+      const int64_t so = ob ? st_b[size_t(j * K + k)] : st_b[size_t(k * N + j)];
+      p.zembed_b.push_back(ZBlock{so, o, int32_t(inner[k]), int32_t(cols[j]), mb, 0});
+    }
+  for (int64_t i = 0; i < M; ++i)
+    for (int64_t j = 0; j < N; ++j) {
+      const int64_t o = p.c_off[size_t(i * N + j)];
+      if (o >= 0) p.zc.push_back(ZCBlock{o / 2, rows[i] * cols[j]});
+    }
+  *code = BSM_OK;
+  return "";
+}
+
 std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
                        const int64_t* inner, int64_t N, const int64_t* cols,
                        const uint64_t* a_bits, const uint64_t* b_bits, const PlanConfig& cfg,
                        int* code) {
   *code = BSM_E_INVALID;
   std::string e;
+  if (cfg.cplx) return build_complex_plan(p, M, rows, K, inner, N, cols, a_bits, b_bits, cfg, code);
   if (!(e = check_tiling("row_sizes", M, rows)).empty()) return e;
   if (!(e = check_tiling("inner_sizes", K, inner)).empty()) return e;
   if (!(e = check_tiling("col_sizes", N, cols)).empty()) return e;

@@ -39,7 +39,9 @@ struct PlanConfig {
   int out_f32 = 0;    // C holds FP32 elements
   int patch_r = 4, patch_c = 8;  // C blocks per patch (ORDER_PATCH)
   int device_klists = 0;  // 0: when the triples would not fit the host list, 1: always, -1: never
-  int trans_a = 0, trans_b = 0;  // the product reads A^T (B^T): the operand is stored transposed
+  int trans_a = 0, trans_b = 0;  // the product reads A^T (B^T): the operand is stored transposed;
+                                 // with complex elements 2 = the adjoint
+  int cplx = 0;                  // complex elements (run as the real embedding)
   std::string tune_cache;  // autotuner choices file ("" = none)
 };
 
@@ -117,6 +119,18 @@ struct HostPlan {
   // FP64 and FP32 forms with a transposed operand: the transposition pass's block tables (stored
   // blocks -> op(A), op(B) in the product's packed layout)
   std::vector<XposeBlock> xpose_a, xpose_b;
+  // complex elements: this plan is the real embedding (rows and inner sizes doubled); the user's
+  // view, the embedding pass's tables and the epilogue's C blocks
+  int cplx = 0;
+  int zop_a = 0, zop_b = 0;      // 0 as is, 1 transpose, 2 adjoint
+  int z_out_f32 = 0;             // C holds complex FP32 elements
+  std::vector<ZBlock> zembed_a, zembed_b;
+  std::vector<ZCBlock> zc;
+  // buffer sizes in the caller's elements (complex elements of a complex plan)
+  int64_t user_a() const { return cplx ? a_elems / 4 : a_elems; }
+  int64_t user_b() const { return cplx ? b_elems / 2 : b_elems; }
+  int64_t user_c() const { return cplx ? c_elems / 2 : c_elems; }
+  bool user_out_f32() const { return cplx ? z_out_f32 != 0 : cfg.out_f32 != 0; }
   int64_t k_window_eff = 0;      // inner blocks per k-window
   int64_t windows = 1;           // number of k-windows
 

@@ -62,6 +62,28 @@ struct XposeBlock {
   int32_t cols;
 };
 
+// Complex elements run as a real product: one block of a complex operand as the embedding pass
+// sees it.  The op(X) block is rows x cols complex elements; src_off counts complex elements of the
+// caller's buffer, dst_off real elements of the embedded operand.  mode: bit 0 = stored transposed
+// (the source block is cols x rows), bit 1 = conjugate, bit 2 = right operand (written as the
+// 2 rows x cols real block [Re; Im]; otherwise the 2 rows x 2 cols block [[Re, -Im], [Im, Re]]).
+struct ZBlock {
+  int64_t src_off;
+  int64_t dst_off;
+  int32_t rows;
+  int32_t cols;
+  int32_t mode;
+  int32_t pad_;
+};
+constexpr int kZTrans = 1, kZConj = 2, kZRight = 4;
+
+// One complex C block for the epilogue: its offset (complex elements; the real product's
+// [Re; Im] block starts at 2 off) and its element count.
+struct ZCBlock {
+  int64_t off;
+  int64_t n;
+};
+
 // One (i,k,j) block triple of a C block's k-list: where A_ik and B_kj start and the inner block
 // size.  a = A offset | (s_k << 48);  b = B offset | (k << 48).
 struct Triple {

@@ -354,7 +354,7 @@ def test_transposed_operand_plans(precision, ta, tb):
 
 def test_transposed_shapes_validated():
     """A transposed operand's bitmap has the stored dimensions: its padding is checked against
-    them, the binding checks its length, and trans flags other than 0/1 are rejected."""
+    them, the binding checks its length, and trans flags other than 0/1/2 are rejected."""
     M, K, N = 70, 3, 2
     rows, inner, cols = [4] * M, [5] * K, [6] * N
     a_st = gen.pack_bits(np.ones((K, M), bool))      # K x M: 3 rows of 2 words
@@ -367,8 +367,54 @@ def test_transposed_shapes_validated():
     with pytest.raises(bsm.BsmError) as e:
         bsm.Plan(rows, inner, cols, bad, b, trans_a=1)
     assert e.value.code == bsm.E_INVALID
-    for flag in ({"trans_a": 2}, {"trans_b": -1}):
+    for flag in ({"trans_a": 3}, {"trans_b": -1}):
         with pytest.raises(bsm.BsmError) as e:
             bsm.Plan(rows, inner, cols, a_st, b, **flag) if "trans_a" in flag else \
                 bsm.Plan(rows, inner, cols, gen.pack_bits(np.ones((M, K), bool)), b, **flag)
         assert e.value.code == bsm.E_INVALID
+
+
+@pytest.mark.parametrize("ops", [(0, 0), (2, 1), (1, 2)])
+def test_complex_plans(ops):
+    """Complex elements: sizes and offsets count complex elements and follow the oracle's C
+    layout; the flop count is the complex product's (8 r s t per triple = the real embedding's)."""
+    ta, tb = ops
+    p = gen.random_problem(70 + ta + 3 * tb, 5, 6, 4, 1, 90, 0.5, 0.6)
+    a_bits = gen.pack_bits(p.a_mask.T) if ta else p.a_bits()
+    b_bits = gen.pack_bits(p.b_mask.T) if tb else p.b_bits()
+    plan = bsm.Plan(p.rows, p.inner, p.cols, a_bits, b_bits, elem=bsm.COMPLEX, trans_a=ta,
+                    trans_b=tb)
+    info = plan.info()
+    assert info.elem == bsm.COMPLEX
+    c_bits = oracle.product_shape(p.M, p.K, p.N, a_bits, b_bits, bool(ta), bool(tb))
+    off, total = oracle.block_offsets(p.rows, p.cols, c_bits)
+    assert np.array_equal(plan.c_shape(), c_bits)
+    assert np.array_equal(plan.c_offsets(), off)
+    assert (info.a_elems, info.b_elems, info.c_elems) == (p.a_data.size, p.b_data.size, total)
+    real = bsm.Plan.from_problem(p).info()
+    assert info.useful_flops == 4 * real.useful_flops
+    assert info.triples == real.triples
+
+
+def test_complex_limits_on_host():
+    bits = gen.pack_bits(np.ones((1, 1), bool))
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Plan([32768], [4], [4], bits, bits, elem=bsm.COMPLEX)
+    assert e.value.code == bsm.E_INVALID
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Plan([4], [4], [4], bits, bits, elem=2)
+    assert e.value.code == bsm.E_INVALID
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Plan([4], [4], [4], bits, bits, elem=bsm.COMPLEX, trans_a=3)
+    assert e.value.code == bsm.E_INVALID
+    # the adjoint of a real operand is its transpose
+    bsm.Plan([4], [4], [4], bits, bits, trans_a=2).close()
+    zp = bsm.Plan([4], [4], [4], bits, bits, elem=bsm.COMPLEX)
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Batch([zp])
+    assert e.value.code == bsm.E_UNSUPPORTED
+    L = bsm.load()
+    assert L.bsm_execute_static(zp.handle, 1.0, 1 << 32, 1 << 36, 1 << 40, 0, None) == bsm.E_UNSUPPORTED
+    assert L.bsm_execute_complex(zp.handle, 1.0, 0.0, (1 << 32) + 8, 1 << 36, 1 << 40, 0, None) == bsm.E_INVALID
+    rp = bsm.Plan([4], [4], [4], bits, bits)
+    assert L.bsm_execute_complex(rp.handle, 1.0, 0.5, 1 << 32, 1 << 36, 1 << 40, 0, None) == bsm.E_MISMATCH
