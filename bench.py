@@ -270,6 +270,53 @@ def forms_section(p, A, B, steps, warmup, stream, torch, bsm, dev, c_elems, ref_
     return out, results
 
 
+def operands_section(p, A, steps, warmup, stream, torch, bsm, dev, ref_wall_ms):
+    """The headline workload with B handed over transposed (FP64), and with complex N(0,1)
+    elements and B read as its adjoint (complex FP64): time per step including the staging passes
+    (transposition; complex embedding and epilogue), useful TFLOP/s (8 r s t per complex triple)."""
+    from paper_1504_05046_amd import gen
+    out = {}
+    bt_bits, bt = gen.stored_transpose(p.inner, p.cols, p.b_mask, p.b_data)
+    plan = bsm.Plan(p.rows, p.inner, p.cols, p.a_bits(), bt_bits, trans_b=1, use_graph=1)
+    info = plan.info()
+    Bt = torch.from_numpy(bt).to(dev)
+    C = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
+    w, e, _ = time_plan(plan, A, Bt, C, steps, warmup, stream, torch)
+    plan.verify(stream=stream)
+    extra = max(w - ref_wall_ms, 1e-9)
+    out["fp64_b_transposed"] = {
+        "value": round(info.useful_flops / (w * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+        "ms_per_step": round(w, 4), "launch_ms": round(e, 4),
+        "staging_ms": round(w - ref_wall_ms, 4),
+        "staging_gbps": round(2 * bt.nbytes / (extra * 1e-3) / 1e9, 1),
+        "note": "one transposition pass over B (read + write) ahead of the same tile kernels"}
+    plan.close()
+    del Bt, C
+    za, zb = gen.imag_parts(p, 16384)
+    zbt_bits, zbt = gen.stored_transpose(p.inner, p.cols, p.b_mask, zb.conj())
+    plan = bsm.Plan(p.rows, p.inner, p.cols, p.a_bits(), zbt_bits, elem=bsm.COMPLEX, trans_b=2,
+                    use_graph=1)
+    info = plan.info()
+    zA = torch.from_numpy(za).to(dev)
+    zB = torch.from_numpy(zbt).to(dev)
+    del za, zb, zbt
+    C = torch.zeros(max(1, info.c_elems), dtype=torch.complex128, device=dev)
+    zsteps = max(1, min(steps, 10))
+    w, e, _ = time_plan(plan, zA, zB, C, zsteps, min(warmup, 2), stream, torch)
+    plan.verify(stream=stream)
+    out["complex_fp64_b_adjoint"] = {
+        "value": round(info.useful_flops / (w * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+        "ms_per_step": round(w, 4), "launch_ms": round(e, 4), "steps": zsteps,
+        "useful_gflop": round(info.useful_flops / 1e9, 3),
+        "vs_real_time": round(w / ref_wall_ms, 3),
+        "mfma_frac": round(info.useful_flops / (e * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        "note": "complex flops = the real embedding's; embedding pass, real tile kernels and "
+                "complex epilogue in one graph"}
+    plan.close()
+    del zA, zB, C
+    return out
+
+
 def precision_section(torch, bsm, dev, stream, steps=5, warmup=2):
     """Config 4: the three forms on N = 32768 with per-block scaled values; every form's relative
     Frobenius error over all C blocks against the oracle's full product."""
@@ -562,6 +609,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the N=32768 precision section")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-product batch section")
     ap.add_argument("--no-latency", action="store_true", help="skip the N=1024 latency section")
+    ap.add_argument("--no-operands", action="store_true",
+                    help="skip the transposed-B and complex runs of the headline workload")
     ap.add_argument("--ab-reps", type=int, default=30)
     ap.add_argument("--decay-points", type=int, default=4000,
                     help="points of the decay_cloud workload (4000 = the configured size)")
@@ -634,6 +683,11 @@ def main():
         fs, forms_c = forms_section(p, A, B, args.steps, args.warmup, stream, torch, bsm, dev,
                                     info.c_elems, wall_ms)
         result.update(fs)
+    if not args.no_operands:
+        say("operands: B transposed, complex with B adjoint")
+        result["operands"] = operands_section(p, A, args.steps, args.warmup, stream, torch, bsm,
+                                              dev, wall_ms)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         say("cpu baseline: oracle on a sample of C blocks")
         got = C.cpu().numpy()[:info.c_elems]
