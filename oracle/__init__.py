@@ -57,6 +57,7 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_double, ctypes.c_int, _p, ctypes.c_int, ctypes.c_int]
         L.oracle_zbsmm_blocks.argtypes = [_i64, _i64, _i64, _p, _p, _p, _p, _p, _p, _p, _i64, _p,
                                           _p, _p, _p, ctypes.c_int, ctypes.c_int]
+        L.oracle_lr_expand.argtypes = [_i64, _i64, _p, _p, _p, _p, _p, _p]
         L.oracle_concurrent_iterations.restype = _i64
         L.oracle_concurrent_iterations.argtypes = [_i64, _i64, _i64]
         L.oracle_memory_overhead.restype = ctypes.c_double
@@ -243,6 +244,25 @@ def zbsmm_blocks(rows, inner, cols, a_bits, b_bits, A, B, sel: Sequence[Tuple[in
         blocks.append(out[pos:pos + n].reshape(int(r[i]), int(t[j])).copy())
         pos += n
     return blocks, [bool(x) for x in present[:len(sel)]]
+
+
+def lr_expand(rows, inner, a_bits, ranks, A_lr) -> np.ndarray:
+    """Dense packed A from a block-rank-sparse packed A (factored blocks U V^T multiplied out)."""
+    r, s = _c64(rows, np.int64), _c64(inner, np.int64)
+    a = _c64(a_bits, np.uint64)
+    rk = _c64(ranks, np.int32)
+    src = _c64(A_lr, np.float64)
+    M, K = r.size, s.size
+    w = (K + 63) // 64
+    total = 0
+    for i in range(M):
+        for k in range(K):
+            if (int(a[i * w + k // 64]) >> (k % 64)) & 1:
+                total += int(r[i]) * int(s[k])
+    out = np.zeros(max(1, total), dtype=np.float64)
+    if lib().oracle_lr_expand(M, K, _ptr(r), _ptr(s), _ptr(a), _ptr(rk), _ptr(src), _ptr(out)) != 0:
+        raise ValueError("negative rank")
+    return out[:total]
 
 
 def concurrent_iterations(prow: int, pcol: int, K: int) -> int:

@@ -37,6 +37,13 @@
  * and conjugate), and alpha is complex.  Every complex multiply-add is written out in real
  * arithmetic: (ar + i ai)(br + i bi) = (ar br - ai bi) + i (ar bi + ai br).
  *
+ * Block-rank-sparse operands (Sec. 1 names block-rank sparsity, data-sparse blocks of low rank,
+ * as the structure the task formulation targets): a present block of A may be stored as factors,
+ * A_ik = U V^T with U r_i x rho and V s_k x rho (both row-major, U first); rho = 0 marks a dense
+ * block.  The packed buffer holds each present block in row-major block order, r_i s_k elements
+ * for a dense block and (r_i + s_k) rho for a factored one.  The oracle multiplies out every
+ * factored block (plain loops, FP64) and then takes the ordinary product.
+ *
  * Also here: the paper's two closed forms, the concurrent-iteration limit (Eq. 1) and the
  * per-node memory overhead of one SUMMA iteration (Eq. 2).
  */
@@ -335,6 +342,36 @@ int oracle_zbsmm_blocks(int64_t M, int64_t K, int64_t N, const int64_t* r, const
   for (int64_t q = 0; q < nsel; ++q)
     present[q] = zblock_product(&p, A, B, op_a == 2, op_b == 2, sel_i[q], sel_j[q], out + pos[q]);
   free(pos); teardown(&p);
+  return 0;
+}
+
+/* Dense packed A (ordinary layout) from a block-rank-sparse A: ranks[q] of the q-th present block
+ * in row-major block order, 0 = dense.  Returns -1 for a negative rank. */
+int oracle_lr_expand(int64_t M, int64_t K, const int64_t* r, const int64_t* s,
+                     const uint64_t* a_bits, const int32_t* ranks, const double* A_lr,
+                     double* A_dense) {
+  int64_t q = 0, src = 0, dst = 0;
+  for (int64_t i = 0; i < M; ++i)
+    for (int64_t k = 0; k < K; ++k) {
+      if (!bit_at(a_bits, K, i, k)) continue;
+      int64_t h = r[i], d = s[k], rho = ranks[q++];
+      if (rho < 0) return -1;
+      if (rho == 0) {
+        for (int64_t e = 0; e < h * d; ++e) A_dense[dst + e] = A_lr[src + e];
+        src += h * d;
+      } else {
+        const double* u = A_lr + src;            /* h x rho */
+        const double* v = A_lr + src + h * rho;  /* d x rho */
+        for (int64_t x = 0; x < h; ++x)
+          for (int64_t y = 0; y < d; ++y) {
+            double acc = 0.0;
+            for (int64_t l = 0; l < rho; ++l) acc += u[x * rho + l] * v[y * rho + l];
+            A_dense[dst + x * d + y] = acc;
+          }
+        src += (h + d) * rho;
+      }
+      dst += h * d;
+    }
   return 0;
 }
 

@@ -42,6 +42,7 @@ import numpy as np
 _TILING, _SHAPE, _VALUES, _SCALE, _POINTS = 1, 2, 3, 4, 5
 MAT_A, MAT_B = 0, 1
 _IMAG_A, _IMAG_B = 2, 3  # streams of the imaginary parts of complex operands
+_FACTORS = 6             # streams of the factors of low-rank blocks
 
 
 def _rng(seed: int, *key: int) -> np.random.Generator:
@@ -168,6 +169,50 @@ def imag_parts(p: Problem, seed: int, draw=None) -> Tuple[np.ndarray, np.ndarray
     za = p.a_data + 1j * ia
     zb = za if p.b_is_a else p.b_data + 1j * ib
     return za, zb
+
+
+def low_rank_operand(p: Problem, seed: int, rank_fn, draw=None) -> Tuple[np.ndarray, np.ndarray]:
+    """Block-rank-sparse A with p's block shape: for every present block (row-major block order)
+    rank_fn(i, k, r_i, s_k) gives its rank rho; rho = 0 keeps p's dense block, otherwise the block
+    is stored as factors U (r_i x rho) then V (s_k x rho), drawn from the block's own stream
+    (N(0,1) / sqrt(rho) by default).  Returns (ranks int32, packed data)."""
+    def _scaled(rng, i, k, h, w):
+        return rng.standard_normal((h, w)) / np.sqrt(w)
+    draw = draw or _scaled
+    ranks, parts, pos = [], [], 0
+    for i, k in zip(*np.nonzero(p.a_mask)):
+        h, d = int(p.rows[i]), int(p.inner[k])
+        rho = int(rank_fn(int(i), int(k), h, d))
+        if rho == 0:
+            parts.append(p.a_data[pos:pos + h * d])
+        else:
+            rng = _rng(seed, _FACTORS, int(i), int(k))
+            parts.append(draw(rng, int(i), int(k), h, rho).reshape(-1))
+            parts.append(draw(rng, int(i), int(k), d, rho).reshape(-1))
+        ranks.append(rho)
+        pos += h * d
+    data = np.concatenate(parts) if parts else np.zeros(0)
+    return np.asarray(ranks, dtype=np.int32), data
+
+
+def block_rank_8192(seed: int = 6000):
+    """Block-rank-sparse workload: N=8192 with the nonuniform tilings (sizes U{32..256}), A with
+    every block present, blocks whose centres lie within 512 rows of the diagonal dense and the
+    others of rank U{4..16}; B Bernoulli(0.3), N(0,1).  Returns (problem with A's dense shape,
+    ranks, A's block-rank-sparse data)."""
+    rows = tiling_random(8192, 32, 256, _rng(seed, _TILING, 0))
+    inner = tiling_random(8192, 32, 256, _rng(seed, _TILING, 1))
+    cols = tiling_random(8192, 32, 256, _rng(seed, _TILING, 2))
+    a_mask = np.ones((rows.size, inner.size), dtype=bool)
+    b_mask = _rng(seed, _SHAPE).random((inner.size, cols.size)) < 0.3
+    p = make_problem("block_rank_8192", seed, rows, inner, cols, a_mask, b_mask)
+    rc = np.cumsum(rows) - rows / 2.0
+    ic = np.cumsum(inner) - inner / 2.0
+    pick = _rng(seed, _SHAPE, 1)
+    table = pick.integers(4, 17, (rows.size, inner.size))
+    ranks, data = low_rank_operand(
+        p, seed, lambda i, k, h, d: 0 if abs(rc[i] - ic[k]) < 512 else int(table[i, k]))
+    return p, ranks, data
 
 
 def _fill_blocks(seed: int, mat: int, mask: np.ndarray, rsz: np.ndarray, csz: np.ndarray,

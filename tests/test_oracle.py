@@ -543,3 +543,62 @@ def test_complex_selected_blocks_match_full_product():
     # adjoint of the stored conj-transpose is B itself: same result as the plain product
     plain = oracle.zbsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), za, zb)
     assert np.array_equal(full, plain)
+
+
+# ---- block-rank-sparse operands --------------------------------------------------------------
+def _factors_of(p, ranks, data):
+    """(i, k, U, V) of every factored block and (i, k, block) of every dense one, from the packed
+    block-rank-sparse buffer (test-side walk of the layout)."""
+    pos, fac, dense = 0, [], []
+    for q, (i, k) in enumerate(zip(*np.nonzero(p.a_mask))):
+        h, d, rho = int(p.rows[i]), int(p.inner[k]), int(ranks[q])
+        if rho == 0:
+            dense.append((i, k, data[pos:pos + h * d].reshape(h, d)))
+            pos += h * d
+        else:
+            U = data[pos:pos + h * rho].reshape(h, rho)
+            V = data[pos + h * rho:pos + (h + d) * rho].reshape(d, rho)
+            fac.append((i, k, U, V))
+            pos += (h + d) * rho
+    assert pos == data.size
+    return fac, dense
+
+
+def test_low_rank_expansion_matches_numpy():
+    """Factored blocks multiply out to numpy's U @ V^T (inside gamma_rho |U||V|^T), rank-1 blocks to
+    numpy's outer product bit for bit, dense blocks pass through bit for bit."""
+    p = gen.random_problem(460, 5, 6, 3, 1, 40, 0.8, 0.5)
+    ranks, data = gen.low_rank_operand(p, 461, lambda i, k, h, d: (i + k) % 4)
+    full = oracle.lr_expand(p.rows, p.inner, p.a_bits(), ranks, data)
+    D = to_dense(p.rows, p.inner, p.a_mask, full)
+    ro = np.concatenate([[0], np.cumsum(p.rows)])
+    so = np.concatenate([[0], np.cumsum(p.inner)])
+    fac, dense = _factors_of(p, ranks, data)
+    assert fac and dense
+    for i, k, U, V in fac:
+        blk = D[ro[i]:ro[i + 1], so[k]:so[k + 1]]
+        if U.shape[1] == 1:
+            assert np.array_equal(blk, np.outer(U[:, 0], V[:, 0]))
+        bound = 2 * higham_gamma(U.shape[1]) * (np.abs(U) @ np.abs(V).T) + 1e-300
+        assert np.all(np.abs(blk - U @ V.T) <= bound)
+    for i, k, B in dense:
+        assert np.array_equal(D[ro[i]:ro[i + 1], so[k]:so[k + 1]], B)
+
+
+def test_low_rank_integer_factors_exact_and_errors():
+    p = gen.integer_problem(470, 4, 5, 3, 1, 30, 0.9, 0.6)
+    ranks, data = gen.low_rank_operand(p, 472, lambda i, k, h, d: 3 if (i + 2 * k) % 3 else 0,
+                                       draw=lambda g, i, k, h, w: g.integers(-4, 5, (h, w)).astype(float))
+    full = oracle.lr_expand(p.rows, p.inner, p.a_bits(), ranks, data)
+    fac, _ = _factors_of(p, ranks, data)
+    D = to_dense(p.rows, p.inner, p.a_mask, full)
+    ro = np.concatenate([[0], np.cumsum(p.rows)])
+    so = np.concatenate([[0], np.cumsum(p.inner)])
+    for i, k, U, V in fac:
+        assert np.array_equal(D[ro[i]:ro[i + 1], so[k]:so[k + 1]],
+                              (U.astype(np.int64) @ V.T.astype(np.int64)).astype(float))
+    bad = ranks.copy()
+    bad[0] = -1
+    with pytest.raises(ValueError):
+        oracle.lr_expand(p.rows, p.inner, p.a_bits(), bad, data)
+
