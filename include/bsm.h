@@ -283,6 +283,61 @@ bsm_status bsm_plan_set_tile_classes(bsm_plan* plan, const int32_t* variants);
 /* Release the plan (waits for its device work first).  NULL is accepted. */
 bsm_status bsm_plan_destroy(bsm_plan* plan);
 
+/* ---- block-rank-sparse left operand -----------------------------------------------------------
+ * Sec. 1 names block-rank sparsity (blocks of low rank, as in hierarchical matrices) as the data
+ * sparsity the task formulation is a step towards.  Here a present block of A is either dense or
+ * stored as factors A_ik = U V^T, U r_i x rho and V s_k x rho, both row-major, U first.  The
+ * caller's A buffer holds the present blocks in row-major block order, r_i s_k elements for a
+ * dense block and (r_i + s_k) rho for a factored one; a_ranks[q] is the rank of the q-th present
+ * block (0 = dense).  B and C keep the ordinary layout; C's shape is the C-shape of A B.
+ *
+ * The product runs as two ordinary products on the library's kernels (same precision forms):
+ *   stage 1  W_(ik)j = V_ik^T B_kj for every factored (i,k) and present B_kj;
+ *   stage 2  C = alpha [A_dense | U] [B ; W] (+ C), the inner dimension extended by one block of
+ *            size rho per factored block,
+ * after staging passes on the stream (dense blocks and U factors gathered, V factors transposed,
+ * B copied in front of W) into device memory the plan owns.  A factored block therefore costs
+ * 2 rho (s_k + r_i) t_j flops per present B_kj instead of 2 r_i s_k t_j. */
+typedef struct bsm_lr_plan bsm_lr_plan;
+
+typedef struct {
+  int64_t M, K, N;
+  int64_t a_blocks;         /* present blocks of A */
+  int64_t factored_blocks;  /* of which stored as U V^T */
+  int64_t a_elems;          /* the caller's A buffer (factors of factored blocks) */
+  int64_t b_elems;
+  int64_t c_blocks, c_elems;
+  int64_t tasks;            /* tile-kernel tasks of both stages */
+  int64_t workspace_bytes;  /* device memory the plan holds besides the caller's buffers */
+  double useful_flops;      /* flops of both stages */
+  double dense_flops;       /* flops of the same product with every block of A dense */
+} bsm_lr_info;
+
+/* Plan C = alpha A B (+ C) with a block-rank-sparse A (host work only; arguments copied).
+ * a_ranks: one int32 per present A block in row-major block order, in [0, 65535].  opt as for
+ * bsm_plan_create (the output type, precision form, order, graph option apply to both stages);
+ * complex elements and transposed operands give BSM_E_UNSUPPORTED.  Errors: as bsm_plan_create. */
+bsm_status bsm_lr_plan_create(bsm_lr_plan** out, int64_t M, const int64_t* row_sizes, int64_t K,
+                              const int64_t* inner_sizes, int64_t N, const int64_t* col_sizes,
+                              const uint64_t* a_bits, const int32_t* a_ranks,
+                              const uint64_t* b_bits, const bsm_options* opt);
+
+bsm_status bsm_lr_plan_query(const bsm_lr_plan* plan, bsm_lr_info* info);
+
+/* Packed element offset of every C block, -1 for an absent block (M * N int64, host memory). */
+bsm_status bsm_lr_plan_c_offsets(const bsm_lr_plan* plan, int64_t* c_offsets);
+
+/* Queue the staging passes and both stages on `stream`.  dA: the caller's block-rank-sparse A
+ * (a_elems FP64), dB: packed B, dC: packed C of the plan's output type.  Errors: as bsm_execute. */
+bsm_status bsm_lr_execute(bsm_lr_plan* plan, double alpha, const double* dA, const double* dB,
+                          void* dC, int accumulate, void* stream);
+
+/* bsm_plan_verify for both stages. */
+bsm_status bsm_lr_plan_verify(bsm_lr_plan* plan, void* stream);
+
+/* Waits for the device, then frees the plan; NULL is ignored. */
+bsm_status bsm_lr_plan_destroy(bsm_lr_plan* plan);
+
 /* ---- batches: many independent products in one launch ---------------------------------------
  * Several matrix multiplications overlapped in one execution (Sec. 1 names the overlap of the
  * multiplications of one expression as a motivation of the task formulation).  A batch

@@ -55,6 +55,15 @@ class PlanInfo(ctypes.Structure):
                 ("elem", ctypes.c_int32)]
 
 
+class LrInfo(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("a_blocks", ctypes.c_int64), ("factored_blocks", ctypes.c_int64),
+                ("a_elems", ctypes.c_int64), ("b_elems", ctypes.c_int64),
+                ("c_blocks", ctypes.c_int64), ("c_elems", ctypes.c_int64),
+                ("tasks", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("useful_flops", ctypes.c_double), ("dense_flops", ctypes.c_double)]
+
+
 _lib: Optional[ctypes.CDLL] = None
 _p = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -119,6 +128,17 @@ def load() -> ctypes.CDLL:
     L.bsm_mlp_loss_grad.argtypes = [_p, _p, _p, _i64, _p, _p, _p]
     L.bsm_adam_step.argtypes = [_p, _p, _p, _p, _i64, _i64, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, _p]
+    L.bsm_lr_plan_create.argtypes = [ctypes.POINTER(_p), _i64, _p, _i64, _p, _i64, _p, _p, _p,
+                                     _p, ctypes.POINTER(Options)]
+    L.bsm_lr_plan_query.argtypes = [_p, ctypes.POINTER(LrInfo)]
+    L.bsm_lr_plan_c_offsets.argtypes = [_p, _p]
+    L.bsm_lr_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
+    L.bsm_lr_plan_verify.argtypes = [_p, _p]
+    L.bsm_lr_plan_destroy.argtypes = [_p]
+    for name in ("bsm_lr_plan_create", "bsm_lr_plan_query", "bsm_lr_plan_c_offsets",
+                 "bsm_lr_execute", "bsm_lr_plan_verify", "bsm_lr_plan_destroy",
+                 "bsm_execute_complex"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("bsm_plan_create", "bsm_plan_query", "bsm_plan_c_shape", "bsm_plan_c_offsets",
                  "bsm_execute", "bsm_execute_static", "bsm_plan_verify", "bsm_plan_tile_classes",
                  "bsm_plan_set_tile_classes", "bsm_batch_tile_classes", "bsm_plan_debug_skip_task", "bsm_batch_verify",
@@ -345,6 +365,75 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             _check(load().bsm_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LowRankPlan:
+    """C = alpha A B (+ C) with a block-rank-sparse A: a_ranks[q] is the rank of the q-th present
+    block of A (row-major block order), 0 = dense; factored blocks are stored as U (r x rho) then
+    V (s x rho), A_ik = U V^T."""
+
+    def __init__(self, rows, inner, cols, a_bits, a_ranks, b_bits, opts: Optional[Options] = None,
+                 **kw):
+        L = load()
+        self._rows = _arr(rows, np.int64)
+        self._inner = _arr(inner, np.int64)
+        self._cols = _arr(cols, np.int64)
+        self._a = _arr(a_bits, np.uint64)
+        self._r = _arr(a_ranks, np.int32)
+        self._b = _arr(b_bits, np.uint64)
+        M, K, N = self._rows.size, self._inner.size, self._cols.size
+        for name, bits, r, c in (("a_bits", self._a, M, K), ("b_bits", self._b, K, N)):
+            if bits.size < r * ((c + 63) // 64):
+                raise ValueError(f"{name}: {bits.size} words, the {r} x {c} shape needs "
+                                 f"{r * ((c + 63) // 64)}")
+        o = opts if opts is not None else options(**kw)
+        self._opts = o
+        present = int(sum(bin(int(w)).count("1") for w in self._a))
+        if self._r.size < present:
+            raise ValueError(f"a_ranks: {self._r.size} entries, A has {present} present blocks")
+        h = _p()
+        _check(L.bsm_lr_plan_create(ctypes.byref(h), M, self._rows.ctypes.data, K,
+                                    self._inner.ctypes.data, N, self._cols.ctypes.data,
+                                    self._a.ctypes.data, self._r.ctypes.data, self._b.ctypes.data,
+                                    ctypes.byref(o)))
+        self._h = h
+
+    def info(self) -> LrInfo:
+        i = LrInfo()
+        _check(load().bsm_lr_plan_query(self._h, ctypes.byref(i)))
+        return i
+
+    def c_offsets(self) -> np.ndarray:
+        out = np.zeros(self._rows.size * self._cols.size, dtype=np.int64)
+        _check(load().bsm_lr_plan_c_offsets(self._h, out.ctypes.data))
+        return out.reshape(self._rows.size, self._cols.size)
+
+    def execute(self, A, B, C, alpha: float = 1.0, accumulate: bool = False, stream=None):
+        i = self.info()
+        for name, t, need, dt in (("A", A, i.a_elems, "torch.float64"), ("B", B, i.b_elems, "torch.float64"),
+                                  ("C", C, i.c_elems, None)):
+            if need > 0 and (t is None or t.numel() < need):
+                raise ValueError(f"{name} must hold {need} elements")
+            if need > 0 and dt and str(t.dtype) != dt:
+                raise ValueError(f"{name} must be {dt[6:]}")
+            if need > 0 and hasattr(t, "is_contiguous") and not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+        _check(load().bsm_lr_execute(self._h, float(alpha), _dev_ptr(A), _dev_ptr(B), _dev_ptr(C),
+                                     int(bool(accumulate)), _stream_handle(stream)))
+
+    def verify(self, stream=None):
+        _check(load().bsm_lr_plan_verify(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().bsm_lr_plan_destroy(self._h))
             self._h = None
 
     def __del__(self):

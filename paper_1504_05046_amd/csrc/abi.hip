@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/bsm.h"
+#include "errors.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 
@@ -24,6 +25,8 @@ static bsm_status fail(bsm_status code, const std::string& msg) {
   g_error = msg;
   return code;
 }
+
+bsm_status bsm::set_error(bsm_status code, const std::string& msg) { return fail(code, msg); }
 
 static bsm_status hip_fail(hipError_t e, const char* what) {
   return fail(BSM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));

@@ -74,6 +74,9 @@ hipError_t launch_transpose_f64(const XposeBlock* blocks, int64_t nblocks, const
                                 double* dst, hipStream_t stream);
 hipError_t launch_transpose_f32(const XposeBlock* blocks, int64_t nblocks, const double* src,
                                 float* dst, hipStream_t stream);
+// runs of elements src[src_off .. src_off + n) -> dst[dst_off ..), one workgroup per run
+hipError_t launch_copy_blocks(const CopyBlock* blocks, int64_t nblocks, const double* src,
+                              double* dst, hipStream_t stream);
 // complex elements: the real embedding of the operands, and C = alpha [Re; Im] (+ C) as complex
 hipError_t launch_embed_complex(const ZBlock* blocks, int64_t nblocks, const double* src,
                                 double* dst, hipStream_t stream);

@@ -243,6 +243,31 @@ hipError_t launch_complex_epilogue(const ZCBlock* blocks, int64_t nblocks, const
   return hipGetLastError();
 }
 
+// One workgroup per run; 16-byte accesses when both ends are 16-byte aligned, else 8-byte ones.
+__global__ __launch_bounds__(256) void copy_blocks(const CopyBlock* __restrict__ blocks,
+                                                   const double* __restrict__ src,
+                                                   double* __restrict__ dst) {
+  const CopyBlock b = blocks[blockIdx.x];
+  const double* s = src + b.src_off;
+  double* d = dst + b.dst_off;
+  if (((reinterpret_cast<uintptr_t>(s) | reinterpret_cast<uintptr_t>(d)) & 15) == 0) {
+    const int64_t n2 = b.n / 2;
+    const double2* s2 = reinterpret_cast<const double2*>(s);
+    double2* d2 = reinterpret_cast<double2*>(d);
+    for (int64_t e = threadIdx.x; e < n2; e += blockDim.x) d2[e] = s2[e];
+    if ((b.n & 1) && threadIdx.x == 0) d[b.n - 1] = s[b.n - 1];
+  } else {
+    for (int64_t e = threadIdx.x; e < b.n; e += blockDim.x) d[e] = s[e];
+  }
+}
+
+hipError_t launch_copy_blocks(const CopyBlock* blocks, int64_t nblocks, const double* src,
+                              double* dst, hipStream_t stream) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_blocks, dim3(uint32_t(nblocks)), dim3(256), 0, stream, blocks, src, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_split_bf16x3(const SplitBlock* blocks, int64_t nblocks, const double* src,
                                uint16_t* dst, int64_t plane, hipStream_t stream) {
   if (nblocks <= 0) return hipSuccess;

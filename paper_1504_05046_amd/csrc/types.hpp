@@ -62,6 +62,14 @@ struct XposeBlock {
   int32_t cols;
 };
 
+// One contiguous run of n elements copied from src_off to dst_off (gathering the dense blocks and
+// U factors of a block-rank-sparse operand into an ordinary packed operand).
+struct CopyBlock {
+  int64_t src_off;
+  int64_t dst_off;
+  int64_t n;
+};
+
 // Complex elements run as a real product: one block of a complex operand as the embedding pass
 // sees it.  The op(X) block is rows x cols complex elements; src_off counts complex elements of the
 // caller's buffer, dst_off real elements of the embedded operand.  mode: bit 0 = stored transposed

@@ -418,3 +418,36 @@ def test_complex_limits_on_host():
     assert L.bsm_execute_complex(zp.handle, 1.0, 0.0, (1 << 32) + 8, 1 << 36, 1 << 40, 0, None) == bsm.E_INVALID
     rp = bsm.Plan([4], [4], [4], bits, bits)
     assert L.bsm_execute_complex(rp.handle, 1.0, 0.5, 1 << 32, 1 << 36, 1 << 40, 0, None) == bsm.E_MISMATCH
+
+
+def test_low_rank_plans_on_host():
+    """Block-rank-sparse plans: sizes, C layout (the oracle's), flops of both stages against the
+    closed form, the dense-equivalent flops against the oracle's count, and argument errors."""
+    p = gen.random_problem(80, 5, 6, 4, 1, 60, 0.7, 0.6)
+    rank = lambda i, k, h, d: (i * 3 + k) % 5
+    ranks, data = gen.low_rank_operand(p, 81, rank)
+    plan = bsm.LowRankPlan(p.rows, p.inner, p.cols, p.a_bits(), ranks, p.b_bits())
+    info = plan.info()
+    c_bits = oracle.shape_product(p.M, p.K, p.N, p.a_bits(), p.b_bits())
+    off, total = oracle.block_offsets(p.rows, p.cols, c_bits)
+    assert np.array_equal(plan.c_offsets(), off) and info.c_elems == total
+    assert info.a_elems == data.size and info.b_elems == p.b_data.size
+    assert info.a_blocks == int(p.a_mask.sum()) and info.factored_blocks == int((ranks > 0).sum())
+    assert info.dense_flops == oracle.useful_flops(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits())
+    bt = np.array([sum(int(p.cols[j]) for j in range(p.N) if p.b_mask[k, j]) for k in range(p.K)])
+    want = 0.0
+    for q, (i, k) in enumerate(zip(*np.nonzero(p.a_mask))):
+        r, s, rho = int(p.rows[i]), int(p.inner[k]), int(ranks[q])
+        want += 2.0 * (r * s if rho == 0 else rho * (r + s)) * bt[k]
+    assert info.useful_flops == want
+    bad = ranks.copy()
+    bad[0] = -2
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.LowRankPlan(p.rows, p.inner, p.cols, p.a_bits(), bad, p.b_bits())
+    assert e.value.code == bsm.E_INVALID
+    with pytest.raises(ValueError):
+        bsm.LowRankPlan(p.rows, p.inner, p.cols, p.a_bits(), ranks[:-1], p.b_bits())
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.LowRankPlan(p.rows, p.inner, p.cols, p.a_bits(), ranks, p.b_bits(), elem=bsm.COMPLEX)
+    assert e.value.code == bsm.E_UNSUPPORTED
+    plan.close()
