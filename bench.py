@@ -317,6 +317,65 @@ def operands_section(p, A, steps, warmup, stream, torch, bsm, dev, ref_wall_ms):
     return out
 
 
+def lowrank_section(torch, bsm, dev, stream, steps=10, warmup=3):
+    """Block-rank-sparse A (dense band, ranks 4..16 elsewhere): the two-stage product against the
+    ordinary product of the same A multiplied out (both FP64, graph replay)."""
+    from paper_1504_05046_amd import gen
+    say("block_rank_8192: generating inputs")
+    p, ranks, data = gen.block_rank_8192()
+    lr = bsm.LowRankPlan(p.rows, p.inner, p.cols, p.a_bits(), ranks, p.b_bits(), use_graph=1)
+    info = lr.info()
+    A = torch.from_numpy(data).to(dev)
+    B = torch.from_numpy(p.b_data).to(dev)
+    C = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
+    w, e, _ = time_plan(lr, A, B, C, steps, warmup, stream, torch)
+    lr.verify(stream=stream)
+    # the ordinary product of the multiplied-out A, its dense blocks built on the device
+    dense = torch.zeros(int(p.a_data.size), dtype=torch.float64, device=dev)
+    full = bsm.Plan.from_problem(p, use_graph=1)
+    pos = src = 0
+    parts = []
+    for q, (i, k) in enumerate(zip(*np.nonzero(p.a_mask))):
+        h, d, rho = int(p.rows[i]), int(p.inner[k]), int(ranks[q])
+        if rho == 0:
+            parts.append(A[src:src + h * d].view(h, d))
+            src += h * d
+        else:
+            U = A[src:src + h * rho].view(h, rho)
+            V = A[src + h * rho:src + (h + d) * rho].view(d, rho)
+            parts.append(U @ V.t().contiguous())
+            src += (h + d) * rho
+    off = 0
+    for blk in parts:
+        n = blk.numel()
+        dense[off:off + n] = blk.reshape(-1)
+        off += n
+    torch.cuda.synchronize()
+    Cd = torch.zeros_like(C)
+    wd, ed, _ = time_plan(full, dense, B, Cd, steps, warmup, stream, torch)
+    diff = float(torch.linalg.vector_norm(C - Cd) / torch.linalg.vector_norm(Cd))
+    out = {
+        "workload": "block_rank_8192: N=8192, block sizes U{32..256}, every A block present, "
+                    "blocks within 512 rows of the diagonal dense, the others U V^T of rank "
+                    "U{4..16}; B Bernoulli(0.3), N(0,1)",
+        "a_blocks": info.a_blocks, "factored_blocks": info.factored_blocks,
+        "a_elems_factored": info.a_elems, "a_elems_dense": int(dense.numel()),
+        "useful_gflop": round(info.useful_flops / 1e9, 3),
+        "dense_equivalent_gflop": round(info.dense_flops / 1e9, 3),
+        "ms_per_step": round(w, 4), "launch_ms": round(e, 4),
+        "value": round(info.useful_flops / (w * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+        "dense_equivalent_tflops": round(info.dense_flops / (w * 1e-3) / 1e12, 3),
+        "multiplied_out_ms_per_step": round(wd, 4),
+        "speedup_vs_multiplied_out": round(wd / w, 3),
+        "rel_diff_vs_multiplied_out": diff,
+        "note": "two stages (V^T B, then [A_dense | U][B; W]) plus staging passes, one graph per "
+                "stage; the multiplied-out product is the ordinary FP64 plan on U V^T",
+    }
+    lr.close()
+    full.close()
+    return out
+
+
 def precision_section(torch, bsm, dev, stream, steps=5, warmup=2):
     """Config 4: the three forms on N = 32768 with per-block scaled values; every form's relative
     Frobenius error over all C blocks against the oracle's full product."""
@@ -609,6 +668,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the N=32768 precision section")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-product batch section")
     ap.add_argument("--no-latency", action="store_true", help="skip the N=1024 latency section")
+    ap.add_argument("--no-lowrank", action="store_true", help="skip the block-rank-sparse section")
     ap.add_argument("--no-operands", action="store_true",
                     help="skip the transposed-B and complex runs of the headline workload")
     ap.add_argument("--ab-reps", type=int, default=30)
@@ -702,6 +762,9 @@ def main():
     if not args.no_latency:
         say("uniform_1024: latency")
         result["uniform_1024"] = latency_section(torch, bsm, dev, stream)
+    if not args.no_lowrank:
+        result["block_rank_8192"] = lowrank_section(torch, bsm, dev, stream)
+        torch.cuda.empty_cache()
     if not args.no_batch:
         result["batch64"] = batch_section(torch, bsm, dev, stream)
         torch.cuda.empty_cache()

@@ -4,8 +4,9 @@
 // library's own kernels, so every factored block costs O(rho) instead of O(s_k) per output element:
 //
 //   stage 1   W_(ik)j = V_ik^T B_kj   for every factored (i,k) and present B_kj: a block-sparse
-//             product whose rows are the factored blocks q = (i,k) (rho_q rows each, one present
-//             block per row, at inner block k);
+//             product with one row block per inner block k that has factored blocks, holding the
+//             V^T of all of them stacked (sum of their ranks rows; one present block per row, at
+//             inner block k), so that its C blocks are tall enough for full tiles;
 //   stage 2   C = alpha [A_dense | U] [B ; W] (+ C): one product over the inner dimension extended
 //             by one block per factored block (inner size rho_q), whose left operand holds the
 //             dense blocks and the U factors and whose right operand is B with W's rows appended.
@@ -13,7 +14,8 @@
 // Stage 2's C-shape is the C-shape of A B (row q of W has B's row k shape), so C keeps the
 // ordinary layout.  Staging on the stream: the dense blocks and U factors are gathered into the
 // stage-2 left operand, the V factors transposed into the stage-1 left operand, B copied in front
-// of W.
+// of W, and each W_(ik)j (a run of whole rows of stage 1's stacked C block) copied to its place
+// in stage 2's right operand.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -40,8 +42,11 @@ struct bsm_lr_plan {
   int64_t a2_elems = 0, v_elems = 0, w_elems = 0;
   std::vector<CopyBlock> gather;  // caller's dense blocks and U factors -> stage-2 left operand
   std::vector<XposeBlock> vt;     // caller's V factors (s_k x rho) -> V^T blocks of stage 1
+  std::vector<CopyBlock> restack; // stage 1's stacked W rows -> W_(ik)j blocks of stage 2
   CopyBlock* d_gather = nullptr;
   XposeBlock* d_vt = nullptr;
+  CopyBlock* d_restack = nullptr;
+  double* d_W = nullptr;          // stage 1's C (stacked W)
   double* d_A2 = nullptr;         // stage-2 left operand
   double* d_V1 = nullptr;         // stage-1 left operand
   double* d_B2 = nullptr;         // B followed by W
@@ -65,6 +70,8 @@ static bsm_status lr_prepare(bsm_lr_plan* p) {
   bsm_status st;
   if ((st = up(&p->d_gather, p->gather)) != BSM_OK) return st;
   if ((st = up(&p->d_vt, p->vt)) != BSM_OK) return st;
+  if ((st = up(&p->d_restack, p->restack)) != BSM_OK) return st;
+  if (p->w_elems > 0) LR_HIP(hipMalloc(&p->d_W, size_t(p->w_elems) * 8), "hipMalloc(stage-1 C)");
   if (p->a2_elems > 0) LR_HIP(hipMalloc(&p->d_A2, size_t(p->a2_elems) * 8), "hipMalloc(stage-2 A)");
   if (p->v_elems > 0) LR_HIP(hipMalloc(&p->d_V1, size_t(p->v_elems) * 8), "hipMalloc(stage-1 A)");
   const int64_t nb2 = p->info.b_elems + p->w_elems;
@@ -73,12 +80,29 @@ static bsm_status lr_prepare(bsm_lr_plan* p) {
   return BSM_OK;
 }
 
+// Every run of a staging table inside its source and destination buffers (checked on the host
+// before anything is launched).
+static bool runs_inside(const std::vector<CopyBlock>& t, int64_t src_n, int64_t dst_n) {
+  for (const CopyBlock& b : t)
+    if (b.src_off < 0 || b.dst_off < 0 || b.n < 0 || b.src_off + b.n > src_n || b.dst_off + b.n > dst_n)
+      return false;
+  return true;
+}
+static bool blocks_inside(const std::vector<XposeBlock>& t, int64_t src_n, int64_t dst_n) {
+  for (const XposeBlock& b : t) {
+    const int64_t n = int64_t(b.rows) * b.cols;
+    if (b.src_off < 0 || b.dst_off < 0 || b.src_off + n > src_n || b.dst_off + n > dst_n) return false;
+  }
+  return true;
+}
+
 static void lr_free(bsm_lr_plan* p) {
   if (p->stage1) bsm_plan_destroy(p->stage1);
   if (p->main) bsm_plan_destroy(p->main);
   if (p->ready) {
     (void)hipDeviceSynchronize();
     for (void* ptr : {static_cast<void*>(p->d_gather), static_cast<void*>(p->d_vt),
+                      static_cast<void*>(p->d_restack), static_cast<void*>(p->d_W),
                       static_cast<void*>(p->d_A2), static_cast<void*>(p->d_V1),
                       static_cast<void*>(p->d_B2)})
       if (ptr) (void)hipFree(ptr);
@@ -178,19 +202,76 @@ bsm_status bsm_lr_plan_create(bsm_lr_plan** out, int64_t M, const int64_t* row_s
       }
     }
     p->a2_elems = a2pos;
-    // stage 1: rows = factored blocks (rho_q rows), one block per row at inner block k_q, whose
-    // packed offsets follow q; each is V^T, written by transposing the caller's s_k x rho V
-    std::vector<int64_t> rows1;
-    std::vector<uint64_t> a1(size_t(Q * wk), 0);
+    // stage 1: one row block g per inner block k with factored blocks, R_g = the sum of their
+    // ranks rows; factored block q sits at rows [o_q, o_q + rho_q) of its group (groups in k
+    // order, blocks in row order inside a group).  Row block g has one block, at inner block k:
+    // the stacked V^T (R_g x s_k), each V^T written by transposing the caller's s_k x rho V.
+    std::vector<int64_t> group_of_k(size_t(K), -1), rows1, first_row(size_t(Q), 0), gk;
+    std::vector<std::vector<int64_t>> members;
+    constexpr int64_t kUsed = -2;  // inner block with factored blocks, numbered in k order below
+    for (int64_t f = 0; f < Q; ++f) group_of_k[size_t(fac[size_t(f)].k)] = kUsed;
+    for (int64_t k = 0; k < K; ++k)
+      if (group_of_k[size_t(k)] == kUsed) {
+        group_of_k[size_t(k)] = int64_t(gk.size());
+        gk.push_back(k);
+        rows1.push_back(0);
+        members.emplace_back();
+      }
+    for (int64_t f = 0; f < Q; ++f) {
+      const int64_t g = group_of_k[size_t(fac[size_t(f)].k)];
+      first_row[size_t(f)] = rows1[size_t(g)];
+      rows1[size_t(g)] += fac[size_t(f)].rho;
+      members[size_t(g)].push_back(f);
+    }
+    const int64_t G = int64_t(gk.size());
+    for (int64_t g = 0; g < G; ++g)
+      if (rows1[size_t(g)] > 65535) {
+        lr_free(p);
+        return set_error(BSM_E_UNSUPPORTED, "the ranks of the factored blocks of one inner block "
+                                            "sum to more than 65535");
+      }
+    std::vector<uint64_t> a1(size_t(G * wk), 0);
+    std::vector<int64_t> a1_off(size_t(G), 0);
     int64_t v1pos = 0;
+    for (int64_t g = 0; g < G; ++g) {
+      const int64_t k = gk[size_t(g)];
+      a1[size_t(g * wk + k / 64)] |= uint64_t(1) << (k % 64);
+      a1_off[size_t(g)] = v1pos;
+      v1pos += rows1[size_t(g)] * inner_sizes[k];
+    }
     for (int64_t f = 0; f < Q; ++f) {
       const Fac& x = fac[size_t(f)];
-      rows1.push_back(x.rho);
-      a1[size_t(f * wk + x.k / 64)] |= uint64_t(1) << (x.k % 64);
-      p->vt.push_back(XposeBlock{x.v_off, v1pos, int32_t(inner_sizes[x.k]), int32_t(x.rho)});
-      v1pos += x.rho * inner_sizes[x.k];
+      const int64_t g = group_of_k[size_t(x.k)];
+      p->vt.push_back(XposeBlock{x.v_off, a1_off[size_t(g)] + first_row[size_t(f)] * inner_sizes[x.k],
+                                 int32_t(inner_sizes[x.k]), int32_t(x.rho)});
     }
     p->v_elems = v1pos;
+    // stage 1's C: block (g, j) at the packed offset of the stacked R_g x t_j blocks; W_(q)j is
+    // rows [o_q, o_q + rho_q) of it.  Stage 2's right operand: B's blocks, then W's blocks in
+    // row-major order over (K + q, j).
+    {
+      std::vector<int64_t> c1_off(size_t(G * N), -1);
+      int64_t c1 = 0;
+      for (int64_t g = 0; g < G; ++g)
+        for (int64_t j = 0; j < N; ++j)
+          if (bit_of(b_bits, N, gk[size_t(g)], j)) {
+            c1_off[size_t(g * N + j)] = c1;
+            c1 += rows1[size_t(g)] * col_sizes[j];
+          }
+      p->w_elems = c1;
+      int64_t bpos = 0;  // offsets relative to the start of W in stage 2's right operand
+      for (int64_t f = 0; f < Q; ++f) {
+        const Fac& x = fac[size_t(f)];
+        const int64_t g = group_of_k[size_t(x.k)];
+        for (int64_t j = 0; j < N; ++j) {
+          if (!bit_of(b_bits, N, x.k, j)) continue;
+          const int64_t n = x.rho * col_sizes[j];
+          p->restack.push_back(
+              CopyBlock{c1_off[size_t(g * N + j)] + first_row[size_t(f)] * col_sizes[j], bpos, n});
+          bpos += n;
+        }
+      }
+    }
     bsm_options o1 = o;
     o1.out = BSM_OUT_F64;
     o1.k_window = 0;
@@ -199,7 +280,7 @@ bsm_status bsm_lr_plan_create(bsm_lr_plan** out, int64_t M, const int64_t* row_s
     o1.tune_cache = nullptr;
     bsm_status st;
     if (Q > 0) {
-      st = bsm_plan_create(&p->stage1, Q, rows1.data(), K, inner_sizes, N, col_sizes, a1.data(),
+      st = bsm_plan_create(&p->stage1, G, rows1.data(), K, inner_sizes, N, col_sizes, a1.data(),
                            b_bits, &o1);
       if (st != BSM_OK) {
         lr_free(p);
@@ -207,7 +288,10 @@ bsm_status bsm_lr_plan_create(bsm_lr_plan** out, int64_t M, const int64_t* row_s
       }
       bsm_plan_info i1;
       bsm_plan_query(p->stage1, &i1);
-      p->w_elems = i1.c_elems;
+      if (i1.c_elems != p->w_elems) {
+        lr_free(p);
+        return set_error(BSM_E_MISMATCH, "internal: stage-1 C layout differs from its restack table");
+      }
       p->info.useful_flops += i1.useful_flops;
       p->info.tasks += i1.tasks;
       p->info.workspace_bytes += i1.workspace_bytes;
@@ -230,6 +314,12 @@ bsm_status bsm_lr_plan_create(bsm_lr_plan** out, int64_t M, const int64_t* row_s
     for (int64_t k = 0; k < K; ++k)
       for (int64_t j = 0; j < N; ++j)
         if (bit_of(b_bits, N, k, j)) p->info.b_elems += inner_sizes[k] * col_sizes[j];
+    if (!runs_inside(p->gather, pos, p->a2_elems) || !blocks_inside(p->vt, pos, p->v_elems) ||
+        !runs_inside(p->restack, p->w_elems, p->w_elems) || im.a_elems != p->a2_elems ||
+        im.b_elems != p->info.b_elems + p->w_elems) {
+      lr_free(p);
+      return set_error(BSM_E_MISMATCH, "internal: a staging table leaves its buffers");
+    }
     p->info.c_blocks = im.c_blocks;
     p->info.c_elems = im.c_elems;
     p->info.useful_flops += im.useful_flops;
@@ -244,8 +334,8 @@ bsm_status bsm_lr_plan_create(bsm_lr_plan** out, int64_t M, const int64_t* row_s
         if (bit_of(a_bits, K, i, k))
           p->info.dense_flops += 2.0 * double(row_sizes[i]) * double(inner_sizes[k]) * brow[size_t(k)];
     p->info.workspace_bytes += im.workspace_bytes + (p->a2_elems + p->v_elems + p->info.b_elems +
-                                                     p->w_elems) * 8 +
-                               int64_t(p->gather.size() * sizeof(CopyBlock) +
+                                                     2 * p->w_elems) * 8 +
+                               int64_t((p->gather.size() + p->restack.size()) * sizeof(CopyBlock) +
                                        p->vt.size() * sizeof(XposeBlock));
   } catch (const std::bad_alloc&) {
     lr_free(p);
@@ -291,8 +381,10 @@ bsm_status bsm_lr_execute(bsm_lr_plan* plan, double alpha, const double* dA, con
     LR_HIP(hipMemcpyAsync(plan->d_B2, dB, size_t(in.b_elems) * 8, hipMemcpyDeviceToDevice, s),
            "copy B");
   if (plan->stage1 && plan->w_elems > 0) {
-    st = bsm_execute(plan->stage1, 1.0, plan->d_V1, dB, plan->d_B2 + in.b_elems, 0, stream);
+    st = bsm_execute(plan->stage1, 1.0, plan->d_V1, dB, plan->d_W, 0, stream);
     if (st != BSM_OK) return st;
+    LR_HIP(launch_copy_blocks(plan->d_restack, int64_t(plan->restack.size()), plan->d_W,
+                              plan->d_B2 + in.b_elems, s), "place W blocks");
   }
   return bsm_execute(plan->main, alpha, plan->d_A2, plan->d_B2, dC, accumulate, stream);
 }
