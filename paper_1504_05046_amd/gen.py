@@ -43,6 +43,7 @@ _TILING, _SHAPE, _VALUES, _SCALE, _POINTS = 1, 2, 3, 4, 5
 MAT_A, MAT_B = 0, 1
 _IMAG_A, _IMAG_B = 2, 3  # streams of the imaginary parts of complex operands
 _FACTORS = 6             # streams of the factors of low-rank blocks
+_TENSOR = 7              # streams of block-sparse tensors
 
 
 def _rng(seed: int, *key: int) -> np.random.Generator:
@@ -213,6 +214,33 @@ def block_rank_8192(seed: int = 6000):
     ranks, data = low_rank_operand(
         p, seed, lambda i, k, h, d: 0 if abs(rc[i] - ic[k]) < 512 else int(table[i, k]))
     return p, ranks, data
+
+
+def block_sparse_tensor(seed: int, tilings: Sequence[Sequence[int]], density: float,
+                        draw=None) -> Tuple[np.ndarray, np.ndarray]:
+    """A block-sparse tensor with the given per-mode tilings: each block tuple present with
+    probability `density` (at least one present), values N(0,1) (or draw(rng, shape)), one stream
+    per block.  Returns (present: bool array over the block grid, data packed in row-major block
+    order, each block row-major over its modes)."""
+    tilings = [np.asarray(t, dtype=np.int64) for t in tilings]
+    grid = tuple(len(t) for t in tilings)
+    present = _rng(seed, _TENSOR, 0).random(grid) < density
+    if present.size and not present.any():
+        present.flat[0] = True
+    parts = []
+    for idx in zip(*np.nonzero(present)):
+        shape = tuple(int(tilings[m][int(idx[m])]) for m in range(len(idx)))
+        rng = _rng(seed, _TENSOR, 1, *[int(v) for v in idx])
+        blk = draw(rng, shape) if draw else rng.standard_normal(shape)
+        parts.append(np.asarray(blk, dtype=np.float64).reshape(-1))
+    return present, (np.concatenate(parts) if parts else np.zeros(0))
+
+
+def tensor_bits(present: np.ndarray) -> np.ndarray:
+    """Block shape of a tensor in the library's word layout: bit q = the block with flattened
+    (row-major) index q."""
+    flat = np.asarray(present, dtype=bool).reshape(1, -1)
+    return pack_bits(flat) if flat.size else np.zeros(0, np.uint64)
 
 
 def _fill_blocks(seed: int, mat: int, mask: np.ndarray, rsz: np.ndarray, csz: np.ndarray,

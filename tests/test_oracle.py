@@ -602,3 +602,108 @@ def test_low_rank_integer_factors_exact_and_errors():
     with pytest.raises(ValueError):
         oracle.lr_expand(p.rows, p.inner, p.a_bits(), bad, data)
 
+
+
+# ---- block-sparse tensor contraction ----------------------------------------------------------
+from oracle import contract as tc  # noqa: E402
+
+_LETTERS = "abcdefghij"
+
+
+def _tensor(seed, modes, tilings, density, draw=None):
+    present, data = gen.block_sparse_tensor(seed, tilings, density, draw)
+    return tc.Tensor(modes, tilings, present, data)
+
+
+def _einsum(A, B, c_modes, Da, Db):
+    spec = ("".join(_LETTERS[m] for m in A.modes) + "," + "".join(_LETTERS[m] for m in B.modes)
+            + "->" + "".join(_LETTERS[m] for m in c_modes))
+    return np.einsum(spec, Da, Db)
+
+
+CONTRACTIONS = [
+    # (A modes, B modes, C modes): matrix product, C order interleaving A and B modes, two
+    # contracted modes in different orders, order-4 result
+    ([0, 2], [2, 1], [0, 1]),
+    ([0, 3, 2], [2, 1, 3], [1, 0]),
+    ([0, 2, 3, 1], [3, 4, 2], [4, 0, 1]),
+    ([0, 4], [4, 1, 2, 3], [0, 1, 2, 3]),
+    ([2, 0, 4, 1], [3, 4, 2], [0, 3, 1]),
+]
+
+
+def _tilings(rng, labels):
+    return {m: rng.integers(1, 6, int(rng.integers(1, 4))) for m in labels}
+
+
+@pytest.mark.parametrize("case", range(len(CONTRACTIONS)))
+def test_contraction_matches_numpy_einsum(case):
+    """Against numpy's einsum of the zero-filled dense tensors: C-shape from the boolean
+    contraction of the block shapes (exact), values inside the Higham bound of the contracted
+    length."""
+    am, bm, cm = CONTRACTIONS[case]
+    rng = np.random.default_rng(900 + case)
+    til = _tilings(rng, set(am) | set(bm))
+    A = _tensor(910 + case, am, [til[m] for m in am], 0.6)
+    B = _tensor(920 + case, bm, [til[m] for m in bm], 0.6)
+    shape, data = tc.contract(A, B, cm, alpha=-1.25)
+    mask = _einsum(A, B, cm, A.present.astype(np.int64), B.present.astype(np.int64)) > 0
+    assert np.array_equal(shape, mask)
+    ref = -1.25 * _einsum(A, B, cm, tc.densify(A), tc.densify(B))
+    absref = 1.25 * _einsum(A, B, cm, np.abs(tc.densify(A)), np.abs(tc.densify(B)))
+    n = int(np.prod([til[m].sum() for m in am if m in bm and m not in cm]))
+    c_til = [til[m] for m in cm]
+    got = tc.densify(tc.Tensor(cm, c_til, shape, data))
+    assert np.all(np.abs(got - ref) <= 2 * higham_gamma(max(n, 1)) * absref + 1e-300)
+    # absent C blocks are zero in the dense contraction too
+    assert np.array_equal(tc.pack(shape, c_til, ref).size, data.size)
+
+
+def test_contraction_order2_is_the_block_sparse_matrix_product():
+    """Modes (i,k), (k,j) -> (i,j): the C-shape is the block-sparse matrix oracle's bit for bit and
+    the values agree inside the Higham bound."""
+    p = gen.random_problem(930, 4, 5, 3, 1, 9, 0.6, 0.6)
+    A = tc.Tensor([0, 2], [p.rows, p.inner], p.a_mask, p.a_data)
+    B = tc.Tensor([2, 1], [p.inner, p.cols], p.b_mask, p.b_data)
+    shape, data = tc.contract(A, B, [0, 1])
+    c_bits = oracle.shape_product(p.M, p.K, p.N, p.a_bits(), p.b_bits())
+    assert np.array_equal(shape, gen.unpack_bits(c_bits, p.M, p.N))
+    ref = oracle.bsmm(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data, p.b_data)
+    assert data.shape == ref.shape
+    assert np.allclose(data, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_contraction_brute_force_tiny():
+    """Element-level brute force (pure Python loops over every index) on a tiny order-3 x order-3
+    contraction with an accumulated C."""
+    am, bm, cm = [0, 2, 3], [3, 1, 2], [1, 0]
+    til = {0: np.array([2, 1]), 1: np.array([1, 2]), 2: np.array([2, 1]), 3: np.array([1, 2])}
+    A = _tensor(940, am, [til[m] for m in am], 0.7)
+    B = _tensor(941, bm, [til[m] for m in bm], 0.7)
+    shape, first = tc.contract(A, B, cm)
+    C0 = np.random.default_rng(942).standard_normal(first.size)
+    shape2, data = tc.contract(A, B, cm, alpha=2.0, C=(shape, C0))
+    Da, Db = tc.densify(A), tc.densify(B)
+    dims = {m: int(til[m].sum()) for m in til}
+    ref = np.zeros((dims[1], dims[0]))
+    for x1 in range(dims[1]):
+        for x0 in range(dims[0]):
+            s = 0.0
+            for x2 in range(dims[2]):
+                for x3 in range(dims[3]):
+                    s += Da[x0, x2, x3] * Db[x3, x1, x2]
+            ref[x1, x0] = s
+    want = 2.0 * tc.pack(shape, [til[1], til[0]], ref) + C0
+    assert np.allclose(data, want, rtol=1e-14, atol=1e-14)
+
+
+def test_contraction_integer_values_exact():
+    am, bm, cm = CONTRACTIONS[2]
+    rng = np.random.default_rng(950)
+    til = _tilings(rng, set(am) | set(bm))
+    draw = lambda g, shape: g.integers(-6, 7, shape).astype(float)
+    A = _tensor(951, am, [til[m] for m in am], 0.7, draw)
+    B = _tensor(952, bm, [til[m] for m in bm], 0.7, draw)
+    shape, data = tc.contract(A, B, cm)
+    ref = _einsum(A, B, cm, tc.densify(A).astype(np.int64), tc.densify(B).astype(np.int64))
+    assert np.array_equal(data, tc.pack(shape, [til[m] for m in cm], ref).astype(float))
