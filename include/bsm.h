@@ -338,6 +338,63 @@ bsm_status bsm_lr_plan_verify(bsm_lr_plan* plan, void* stream);
 /* Waits for the device, then frees the plan; NULL is ignored. */
 bsm_status bsm_lr_plan_destroy(bsm_lr_plan* plan);
 
+/* ---- block-sparse tensor contraction -----------------------------------------------------------
+ * The paper's title and Sec. 1 present the block-sparse matrix product as a step towards
+ * block-sparse tensor computing.  A block-sparse tensor of order d (1..8) has a tiling per mode and
+ * a block shape over its block grid; its present blocks are packed in row-major order over the
+ * grid (last mode fastest), each block dense and row-major over its modes.  Modes carry integer
+ * labels.  C = alpha contract(A, B) (+ C): a label shared by A and B and absent from C is summed
+ * over (its tilings must agree); every label of C comes from exactly one of A and B (labels in A,
+ * B and C, or summed labels of one operand only, give BSM_E_UNSUPPORTED).  The contraction runs
+ * as a block-sparse matrix product of the matricized operands (free modes of A in C's order x
+ * contracted modes in A's order, times contracted x free modes of B in C's order); a permutation
+ * pass per operand brings it into that order unless its mode order already is, and one brings C
+ * into its mode order unless C lists A's free modes before B's.  Matricized blocks must stay
+ * within 65535 rows and columns. */
+typedef struct {
+  int32_t order;           /* modes, 1..8 */
+  const int32_t* modes;    /* label of each mode */
+  const int64_t* nblocks;  /* blocks along each mode */
+  const int64_t* sizes;    /* block sizes, mode after mode (sum of nblocks entries) */
+  const uint64_t* bits;    /* block shape: bit q (word q / 64, bit q % 64) = the block with
+                              row-major flattened grid index q; ceil(grid / 64) words */
+} bsm_tensor;
+
+typedef struct bsm_tc_plan bsm_tc_plan;
+
+typedef struct {
+  int64_t M, K, N;             /* block counts of the matricized product */
+  int64_t a_blocks, b_blocks, c_blocks;
+  int64_t a_elems, b_elems, c_elems;
+  int64_t tasks;
+  int64_t workspace_bytes;
+  double useful_flops;         /* 2 x (elements of each contributing block pair product) */
+  int32_t permute_a, permute_b, permute_c;  /* 1: that operand goes through a permutation pass */
+} bsm_tc_info;
+
+/* Plan a contraction (host work; descriptors and labels are copied).  C's tilings and block shape
+ * follow from A and B.  opt as for bsm_plan_create (precision form, output type, order, graph);
+ * complex elements and the trans options give BSM_E_UNSUPPORTED.  Errors: BSM_E_INVALID for a
+ * malformed descriptor, BSM_E_MISMATCH for contracted modes with different tilings. */
+bsm_status bsm_tc_plan_create(bsm_tc_plan** out, const bsm_tensor* A, const bsm_tensor* B,
+                              int32_t c_order, const int32_t* c_modes, const bsm_options* opt);
+
+bsm_status bsm_tc_plan_query(const bsm_tc_plan* plan, bsm_tc_info* info);
+
+/* C's block shape over its flattened grid (ceil(grid / 64) words, host memory). */
+bsm_status bsm_tc_plan_c_shape(const bsm_tc_plan* plan, uint64_t* c_bits);
+
+/* Queue the permutation passes and the product on `stream`.  dA, dB: packed FP64 tensors; dC: C
+ * packed in its own mode order, of the plan's output type.  Errors: as bsm_execute. */
+bsm_status bsm_tc_execute(bsm_tc_plan* plan, double alpha, const double* dA, const double* dB,
+                          void* dC, int accumulate, void* stream);
+
+/* bsm_plan_verify for the product. */
+bsm_status bsm_tc_plan_verify(bsm_tc_plan* plan, void* stream);
+
+/* Waits for the device, then frees the plan; NULL is ignored. */
+bsm_status bsm_tc_plan_destroy(bsm_tc_plan* plan);
+
 /* ---- batches: many independent products in one launch ---------------------------------------
  * Several matrix multiplications overlapped in one execution (Sec. 1 names the overlap of the
  * multiplications of one expression as a motivation of the task formulation).  A batch

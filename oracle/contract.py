@@ -92,8 +92,9 @@ def contract(A: Tensor, B: Tensor, c_modes: Sequence[int], alpha: float = 1.0,
     parts = []
     prev = C[1] if C is not None else None
     pos = 0
-    for cidx in zip(*np.nonzero(c_present)):
-        cidx = tuple(int(v) for v in cidx)
+    for cidx in np.ndindex(*c_present.shape):   # row-major; also the scalar (order-0) C
+        if not c_present[cidx]:
+            continue
         blk = results[cidx].reshape(-1)
         if prev is not None:
             blk = blk + prev[pos:pos + blk.size]
@@ -102,6 +103,33 @@ def contract(A: Tensor, B: Tensor, c_modes: Sequence[int], alpha: float = 1.0,
     if C is not None and pos != prev.size:
         raise ValueError("C has the wrong size")
     return c_present, (np.concatenate(parts) if parts else np.zeros(0))
+
+
+def contract_blocks(A: Tensor, B: Tensor, c_modes: Sequence[int],
+                    sel: Sequence[Tuple[int, ...]]) -> List[Optional[np.ndarray]]:
+    """Selected C blocks (alpha = 1), each from the same definition as `contract`; None for a
+    block outside C's shape."""
+    c_modes = [int(m) for m in c_modes]
+    contracted = [m for m in A.modes if m in B.modes and m not in c_modes]
+    ab, bb = A.blocks(), B.blocks()
+    t_ranges = [range(len(A.tilings[A.modes.index(m)])) for m in contracted]
+    order = [m for m in A.modes if m in c_modes] + [m for m in B.modes if m in c_modes]
+    out = []
+    for cidx in sel:
+        acc = None
+        for t in itertools.product(*t_ranges):
+            a_idx = tuple(cidx[c_modes.index(m)] if m in c_modes else t[contracted.index(m)]
+                          for m in A.modes)
+            b_idx = tuple(cidx[c_modes.index(m)] if m in c_modes else t[contracted.index(m)]
+                          for m in B.modes)
+            if a_idx not in ab or b_idx not in bb:
+                continue
+            part = np.tensordot(ab[a_idx], bb[b_idx],
+                                axes=([A.modes.index(m) for m in contracted],
+                                      [B.modes.index(m) for m in contracted]))
+            acc = part if acc is None else acc + part
+        out.append(None if acc is None else np.transpose(acc, [order.index(m) for m in c_modes]))
+    return out
 
 
 def densify(T: Tensor) -> np.ndarray:
@@ -118,7 +146,9 @@ def pack(c_present: np.ndarray, tilings: Sequence[np.ndarray], D: np.ndarray) ->
     """Packed data of the present blocks of a dense tensor D (inverse of densify)."""
     offs = [np.concatenate([[0], np.cumsum(t)]) for t in tilings]
     parts = []
-    for idx in zip(*np.nonzero(c_present)):
+    for idx in np.ndindex(*c_present.shape):
+        if not c_present[idx]:
+            continue
         sl = tuple(slice(int(offs[m][idx[m]]), int(offs[m][idx[m] + 1])) for m in range(len(idx)))
         parts.append(D[sl].reshape(-1))
     return np.concatenate(parts) if parts else np.zeros(0)

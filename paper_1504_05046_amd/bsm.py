@@ -64,6 +64,21 @@ class LrInfo(ctypes.Structure):
                 ("useful_flops", ctypes.c_double), ("dense_flops", ctypes.c_double)]
 
 
+class TensorDesc(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("modes", ctypes.c_void_p), ("nblocks", ctypes.c_void_p),
+                ("sizes", ctypes.c_void_p), ("bits", ctypes.c_void_p)]
+
+
+class TcInfo(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("K", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("a_blocks", ctypes.c_int64), ("b_blocks", ctypes.c_int64),
+                ("c_blocks", ctypes.c_int64), ("a_elems", ctypes.c_int64),
+                ("b_elems", ctypes.c_int64), ("c_elems", ctypes.c_int64),
+                ("tasks", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("useful_flops", ctypes.c_double), ("permute_a", ctypes.c_int32),
+                ("permute_b", ctypes.c_int32), ("permute_c", ctypes.c_int32)]
+
+
 _lib: Optional[ctypes.CDLL] = None
 _p = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -135,6 +150,17 @@ def load() -> ctypes.CDLL:
     L.bsm_lr_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
     L.bsm_lr_plan_verify.argtypes = [_p, _p]
     L.bsm_lr_plan_destroy.argtypes = [_p]
+    L.bsm_tc_plan_create.argtypes = [ctypes.POINTER(_p), ctypes.POINTER(TensorDesc),
+                                     ctypes.POINTER(TensorDesc), ctypes.c_int32, _p,
+                                     ctypes.POINTER(Options)]
+    L.bsm_tc_plan_query.argtypes = [_p, ctypes.POINTER(TcInfo)]
+    L.bsm_tc_plan_c_shape.argtypes = [_p, _p]
+    L.bsm_tc_execute.argtypes = [_p, ctypes.c_double, _p, _p, _p, ctypes.c_int, _p]
+    L.bsm_tc_plan_verify.argtypes = [_p, _p]
+    L.bsm_tc_plan_destroy.argtypes = [_p]
+    for name in ("bsm_tc_plan_create", "bsm_tc_plan_query", "bsm_tc_plan_c_shape",
+                 "bsm_tc_execute", "bsm_tc_plan_verify", "bsm_tc_plan_destroy"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("bsm_lr_plan_create", "bsm_lr_plan_query", "bsm_lr_plan_c_offsets",
                  "bsm_lr_execute", "bsm_lr_plan_verify", "bsm_lr_plan_destroy",
                  "bsm_execute_complex"):
@@ -434,6 +460,81 @@ class LowRankPlan:
     def close(self):
         if getattr(self, "_h", None):
             _check(load().bsm_lr_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Contraction:
+    """C = alpha contract(A, B) (+ C) of block-sparse tensors.  Each operand is given as
+    (labels, tilings, bits): one label and one block-size vector per mode, and the block shape in
+    the library's word layout over the flattened (row-major) block grid."""
+
+    def __init__(self, a, b, c_modes, opts: Optional[Options] = None, **kw):
+        L = load()
+        self._keep = []
+
+        def desc(labels, tilings, bits):
+            modes = _arr(labels, np.int32)
+            nb = _arr([len(t) for t in tilings], np.int64)
+            sizes = _arr(np.concatenate([np.asarray(t, np.int64) for t in tilings])
+                         if len(tilings) else [], np.int64)
+            grid = int(np.prod(nb)) if nb.size else 1
+            bw = _arr(bits, np.uint64)
+            if bw.size < (grid + 63) // 64:
+                raise ValueError(f"bits: {bw.size} words, a grid of {grid} blocks needs {(grid + 63) // 64}")
+            self._keep += [modes, nb, sizes, bw]
+            return TensorDesc(int(modes.size), modes.ctypes.data, nb.ctypes.data,
+                              sizes.ctypes.data if sizes.size else None, bw.ctypes.data if bw.size else None)
+
+        da, db = desc(*a), desc(*b)
+        cm = _arr(c_modes, np.int32)
+        self._keep.append(cm)
+        self._c_grid = int(np.prod([len(a[1][list(a[0]).index(m)]) if m in list(a[0])
+                                    else len(b[1][list(b[0]).index(m)]) for m in c_modes])) \
+            if len(c_modes) else 1
+        o = opts if opts is not None else options(**kw)
+        self._opts = o
+        h = _p()
+        _check(L.bsm_tc_plan_create(ctypes.byref(h), ctypes.byref(da), ctypes.byref(db),
+                                    int(cm.size), cm.ctypes.data if cm.size else None,
+                                    ctypes.byref(o)))
+        self._h = h
+
+    def info(self) -> TcInfo:
+        i = TcInfo()
+        _check(load().bsm_tc_plan_query(self._h, ctypes.byref(i)))
+        return i
+
+    def c_shape(self) -> np.ndarray:
+        out = np.zeros(max(1, (self._c_grid + 63) // 64), dtype=np.uint64)
+        _check(load().bsm_tc_plan_c_shape(self._h, out.ctypes.data))
+        return out
+
+    def execute(self, A, B, C, alpha: float = 1.0, accumulate: bool = False, stream=None):
+        i = self.info()
+        cdt = "torch.float32" if self._opts.out == OUT_F32 else "torch.float64"
+        for name, t, need, dt in (("A", A, i.a_elems, "torch.float64"),
+                                  ("B", B, i.b_elems, "torch.float64"), ("C", C, i.c_elems, cdt)):
+            if need > 0 and (t is None or t.numel() < need):
+                raise ValueError(f"{name} must hold {need} elements")
+            if need > 0 and str(t.dtype) != dt:
+                raise ValueError(f"{name} must be {dt[6:]}")
+            if need > 0 and hasattr(t, "is_contiguous") and not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+        _check(load().bsm_tc_execute(self._h, float(alpha), _dev_ptr(A), _dev_ptr(B), _dev_ptr(C),
+                                     int(bool(accumulate)), _stream_handle(stream)))
+
+    def verify(self, stream=None):
+        _check(load().bsm_tc_plan_verify(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().bsm_tc_plan_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -74,6 +74,10 @@ hipError_t launch_transpose_f64(const XposeBlock* blocks, int64_t nblocks, const
                                 double* dst, hipStream_t stream);
 hipError_t launch_transpose_f32(const XposeBlock* blocks, int64_t nblocks, const double* src,
                                 float* dst, hipStream_t stream);
+// tensor blocks permuted element by element (matricization, and back for C); with accumulate the
+// destination receives src + dst; dst is FP64 or (c_f32) FP32
+hipError_t launch_permute_blocks(const PermBlock* blocks, int64_t nblocks, const double* src,
+                                 void* dst, int c_f32, int accumulate, hipStream_t stream);
 // runs of elements src[src_off .. src_off + n) -> dst[dst_off ..), one workgroup per run
 hipError_t launch_copy_blocks(const CopyBlock* blocks, int64_t nblocks, const double* src,
                               double* dst, hipStream_t stream);

@@ -243,6 +243,42 @@ hipError_t launch_complex_epilogue(const ZCBlock* blocks, int64_t nblocks, const
   return hipGetLastError();
 }
 
+// One workgroup per tensor block: reads follow the source block (coalesced), each element's
+// destination is the mixed-radix decomposition of its index against the block's extents, weighted
+// by the destination strides.
+template <typename T>
+__global__ __launch_bounds__(256) void permute_blocks(const PermBlock* __restrict__ blocks,
+                                                      const double* __restrict__ src,
+                                                      T* __restrict__ dst, int accumulate) {
+  const PermBlock b = blocks[blockIdx.x];
+  int64_t n = 1;
+  for (int m = 0; m < b.order; ++m) n *= b.ext[m];
+  const double* s = src + b.src_off;
+  T* d = dst + b.dst_off;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    int64_t rem = e, o = 0;
+    for (int m = b.order - 1; m >= 0; --m) {
+      const int64_t x = rem % b.ext[m];
+      rem /= b.ext[m];
+      o += x * b.dst_stride[m];
+    }
+    const double v = s[e];
+    d[o] = T(accumulate ? v + double(d[o]) : v);
+  }
+}
+
+hipError_t launch_permute_blocks(const PermBlock* blocks, int64_t nblocks, const double* src,
+                                 void* dst, int c_f32, int accumulate, hipStream_t stream) {
+  if (nblocks <= 0) return hipSuccess;
+  if (c_f32)
+    hipLaunchKernelGGL(permute_blocks<float>, dim3(uint32_t(nblocks)), dim3(256), 0, stream,
+                       blocks, src, static_cast<float*>(dst), accumulate);
+  else
+    hipLaunchKernelGGL(permute_blocks<double>, dim3(uint32_t(nblocks)), dim3(256), 0, stream,
+                       blocks, src, static_cast<double*>(dst), accumulate);
+  return hipGetLastError();
+}
+
 // One workgroup per run; 16-byte accesses when both ends are 16-byte aligned, else 8-byte ones.
 __global__ __launch_bounds__(256) void copy_blocks(const CopyBlock* __restrict__ blocks,
                                                    const double* __restrict__ src,

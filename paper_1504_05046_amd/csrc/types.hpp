@@ -70,6 +70,20 @@ struct CopyBlock {
   int64_t n;
 };
 
+// One block of a tensor operand as the permutation pass sees it: the source block is row-major
+// over its `order` modes with extents ext (last mode fastest); element (x_0 .. x_{d-1}) goes to
+// dst_off + sum_m x_m dst_stride[m] (the matricized block's, or the tensor block's, row-major
+// position).
+constexpr int kMaxModes = 8;
+struct PermBlock {
+  int64_t src_off;
+  int64_t dst_off;
+  int32_t order;
+  int32_t pad_;
+  int32_t ext[kMaxModes];
+  int64_t dst_stride[kMaxModes];
+};
+
 // Complex elements run as a real product: one block of a complex operand as the embedding pass
 // sees it.  The op(X) block is rows x cols complex elements; src_off counts complex elements of the
 // caller's buffer, dst_off real elements of the embedded operand.  mode: bit 0 = stored transposed

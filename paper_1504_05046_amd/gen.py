@@ -236,6 +236,19 @@ def block_sparse_tensor(seed: int, tilings: Sequence[Sequence[int]], density: fl
     return present, (np.concatenate(parts) if parts else np.zeros(0))
 
 
+def ladder_tensors(seed: int = 7000):
+    """The coupled-cluster particle-particle ladder shape, C[i,j,a,b] = sum_{c,d} T[i,j,c,d]
+    V[a,b,c,d]: 48 occupied indices in blocks U{8..24}, 192 virtual indices in blocks U{16..48}
+    (one tiling per index space, shared by its modes), T with block density 0.5, V (stored with
+    the contracted modes last, as integrals usually are) with block density 0.3, N(0,1) values.
+    Returns (occupied tiling, virtual tiling, (T present, T data), (V present, V data))."""
+    occ = tiling_random(48, 8, 24, _rng(seed, _TILING, 0))
+    vir = tiling_random(192, 16, 48, _rng(seed, _TILING, 1))
+    T = block_sparse_tensor(seed * 10 + 1, [occ, occ, vir, vir], 0.5)
+    V = block_sparse_tensor(seed * 10 + 2, [vir, vir, vir, vir], 0.3)
+    return occ, vir, T, V
+
+
 def tensor_bits(present: np.ndarray) -> np.ndarray:
     """Block shape of a tensor in the library's word layout: bit q = the block with flattened
     (row-major) index q."""

@@ -451,3 +451,43 @@ def test_low_rank_plans_on_host():
         bsm.LowRankPlan(p.rows, p.inner, p.cols, p.a_bits(), ranks, p.b_bits(), elem=bsm.COMPLEX)
     assert e.value.code == bsm.E_UNSUPPORTED
     plan.close()
+
+
+def test_contraction_plans_on_host():
+    """Tensor contraction plans: C's block shape equals the oracle's (boolean contraction of the
+    shapes), sizes and flop counts follow, permutation passes only where the mode order needs one,
+    and malformed descriptors are rejected."""
+    from oracle import contract as tc
+    rng = np.random.default_rng(90)
+    til = {m: rng.integers(1, 6, int(rng.integers(1, 4))) for m in range(5)}
+    cases = [([0, 2], [2, 1], [0, 1], (0, 0, 0)),
+             ([0, 3, 2], [2, 1, 3], [1, 0], (0, 1, 1)),
+             ([0, 2, 3, 1], [3, 4, 2], [0, 1, 4], (1, 1, 0)),
+             ([0, 4], [4, 1, 2, 3], [0, 1, 2, 3], (0, 0, 0))]
+    for n, (am, bm, cm, perms) in enumerate(cases):
+        pa, da = gen.block_sparse_tensor(91 + n, [til[m] for m in am], 0.6)
+        pb, db = gen.block_sparse_tensor(95 + n, [til[m] for m in bm], 0.6)
+        plan = bsm.Contraction((am, [til[m] for m in am], gen.tensor_bits(pa)),
+                               (bm, [til[m] for m in bm], gen.tensor_bits(pb)), cm)
+        info = plan.info()
+        shape, data = tc.contract(tc.Tensor(am, [til[m] for m in am], pa, da),
+                                  tc.Tensor(bm, [til[m] for m in bm], pb, db), cm)
+        assert np.array_equal(plan.c_shape()[:max(1, (shape.size + 63) // 64)], gen.tensor_bits(shape))
+        assert (info.a_elems, info.b_elems, info.c_elems) == (da.size, db.size, data.size)
+        assert (info.permute_a, info.permute_b, info.permute_c) == perms, (n, info.permute_a, info.permute_b, info.permute_c)
+        plan.close()
+    bits = gen.tensor_bits(np.ones((2, 2), bool))
+    good = ([0, 1], [[2, 3], [4, 5]], bits)
+    with pytest.raises(bsm.BsmError) as e:   # contracted tilings differ
+        bsm.Contraction(good, ([1, 2], [[4, 6], [1, 1]], bits), [0, 2])
+    assert e.value.code == bsm.E_MISMATCH
+    with pytest.raises(bsm.BsmError) as e:   # a batch label (in A, B and C)
+        bsm.Contraction(good, ([1, 2], [[4, 5], [1, 1]], bits), [0, 1, 2])
+    assert e.value.code == bsm.E_UNSUPPORTED
+    with pytest.raises(bsm.BsmError) as e:   # a label twice in one operand
+        bsm.Contraction(([0, 0], [[2, 3], [2, 3]], bits), ([0, 2], [[2, 3], [1, 1]], bits), [2])
+    assert e.value.code == bsm.E_INVALID
+    with pytest.raises(bsm.BsmError) as e:   # padding bit
+        bsm.Contraction(([0, 1], [[2, 3], [4, 5]], np.array([1 << 5], np.uint64)),
+                        ([1, 2], [[4, 5], [1, 1]], bits), [0, 2])
+    assert e.value.code == bsm.E_INVALID

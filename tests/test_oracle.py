@@ -707,3 +707,32 @@ def test_contraction_integer_values_exact():
     shape, data = tc.contract(A, B, cm)
     ref = _einsum(A, B, cm, tc.densify(A).astype(np.int64), tc.densify(B).astype(np.int64))
     assert np.array_equal(data, tc.pack(shape, [til[m] for m in cm], ref).astype(float))
+
+
+def test_contraction_selected_blocks_match_full():
+    am, bm, cm = CONTRACTIONS[4]
+    rng = np.random.default_rng(960)
+    til = _tilings(rng, set(am) | set(bm))
+    A = _tensor(961, am, [til[m] for m in am], 0.6)
+    B = _tensor(962, bm, [til[m] for m in bm], 0.6)
+    shape, data = tc.contract(A, B, cm)
+    full = tc.Tensor(cm, [til[m] for m in cm], shape, data).blocks()
+    sel = [tuple(int(v) for v in idx) for idx in np.ndindex(*shape.shape)]
+    for idx, blk in zip(sel, tc.contract_blocks(A, B, cm, sel)):
+        if blk is None:
+            assert idx not in full
+        else:
+            assert np.array_equal(blk, full[idx])
+
+
+def test_contraction_to_a_scalar():
+    """All modes contracted: C is one number, the sum over present block pairs of their elementwise
+    products (numpy einsum of the dense tensors)."""
+    til = {0: np.array([3, 1]), 1: np.array([2]), 2: np.array([4, 2])}
+    A = _tensor(970, [0, 1, 2], [til[0], til[1], til[2]], 0.7)
+    B = _tensor(971, [2, 1, 0], [til[2], til[1], til[0]], 0.7)
+    shape, data = tc.contract(A, B, [])
+    ref = np.einsum("abc,cba->", tc.densify(A), tc.densify(B))
+    assert shape.shape == () and data.size == (1 if shape else 0)
+    if shape:
+        assert abs(data[0] - ref) <= 1e-12 * max(1.0, abs(ref))
