@@ -8,9 +8,11 @@
 // and its free modes (in C's order) as the column index.  Row, inner and column blocks are tuples
 // of mode blocks (mixed radix, last mode fastest) whose sizes are products of the modes' block
 // sizes, so the matricized operands are block-sparse matrices with nonuniform blocks and the
-// product is an ordinary plan of this library.  A permutation pass (one workgroup per block)
-// brings an operand into matrix order unless its mode order already is (then it is used in place),
-// and one brings C back into its own mode order unless C lists A's free modes before B's.
+// product is an ordinary plan of this library.  A permutation pass brings an operand into matrix
+// order unless its mode order already is (then it is used in place), and one brings C back into
+// its own mode order unless C lists A's free modes before B's.  A block whose modes stay in order
+// is copied, one whose modes fall into two swapped groups is transposed through LDS, any other is
+// permuted element by element; each in pieces of one workgroup.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +24,7 @@
 #include "../../include/bsm.h"
 #include "errors.hpp"
 #include "kernels.hpp"
+#include "staging.hpp"
 
 using namespace bsm;
 
@@ -99,16 +102,62 @@ int64_t tuple_index(const std::vector<int>& pos, const int64_t* idx, const Tenso
 
 }  // namespace
 
+// A permutation pass split by kind: blocks whose modes stay in order are copies, blocks whose
+// modes fall into two swapped groups are 2-D transposes, the rest go element by element.
+struct Pass {
+  std::vector<CopyBlock> copy;
+  std::vector<XposeBlock> xpose;
+  std::vector<PermBlock> perm;
+  CopyBlock* d_copy = nullptr;
+  XposeBlock* d_xpose = nullptr;
+  PermBlock* d_perm = nullptr;
+  bool empty() const { return copy.empty() && xpose.empty() && perm.empty(); }
+};
+
+// Cut a whole-block permutation into pieces of one workgroup.  Source modes m and m+1 that stay
+// adjacent in the destination (stride[m] = stride[m+1] ext[m+1]) merge into one group, modes of
+// extent 1 drop out; one group is a copy, two groups in swapped order a transpose.
+static void lower(const PermBlock& b, bool generic_only, Pass& out) {
+  int64_t n = 1;
+  for (int m = 0; m < b.order; ++m) n *= b.ext[m];
+  if (n == 0) return;
+  if (!generic_only) {
+    std::vector<std::pair<int64_t, int64_t>> g;  // (extent, destination stride), source order
+    for (int m = 0; m < b.order; ++m) {
+      if (b.ext[m] == 1) continue;
+      if (!g.empty() && g.back().second == b.dst_stride[m] * b.ext[m]) {
+        g.back().first *= b.ext[m];
+        g.back().second = b.dst_stride[m];
+      } else {
+        g.emplace_back(b.ext[m], b.dst_stride[m]);
+      }
+    }
+    if (g.empty() || (g.size() == 1 && g[0].second == 1)) {
+      push_copy(out.copy, b.src_off, b.dst_off, n);
+      return;
+    }
+    if (g.size() == 2 && g[1].second == g[0].first && g[0].second == 1 && g[0].first <= 65535 &&
+        g[1].first <= 65535) {
+      push_transpose(out.xpose, b.src_off, b.dst_off, int32_t(g[0].first), int32_t(g[1].first));
+      return;
+    }
+  }
+  for (int64_t e = 0; e < n; e += kPermPiece) {
+    PermBlock piece = b;
+    piece.e0 = e;
+    piece.e1 = std::min(n, e + kPermPiece);
+    out.perm.push_back(piece);
+  }
+}
+
 struct bsm_tc_plan {
   bsm_plan* mat = nullptr;
   bsm_tc_info info{};
-  std::vector<PermBlock> pa, pb, pc;
+  std::vector<PermBlock> pa, pb, pc;  // whole blocks
+  Pass xa, xb, xc;                    // the pieces launched
   int64_t a_mat = 0, b_mat = 0, c_mat = 0;  // elements of the matricized operands
   int c_f32 = 0;
   std::vector<uint64_t> c_bits;
-  PermBlock* d_pa = nullptr;
-  PermBlock* d_pb = nullptr;
-  PermBlock* d_pc = nullptr;
   double* d_A = nullptr;
   double* d_B = nullptr;
   double* d_C = nullptr;
@@ -119,12 +168,42 @@ static void tc_free(bsm_tc_plan* p) {
   if (p->mat) bsm_plan_destroy(p->mat);
   if (p->ready) {
     (void)hipDeviceSynchronize();
-    for (void* ptr : {static_cast<void*>(p->d_pa), static_cast<void*>(p->d_pb),
-                      static_cast<void*>(p->d_pc), static_cast<void*>(p->d_A),
-                      static_cast<void*>(p->d_B), static_cast<void*>(p->d_C)})
+    for (Pass* x : {&p->xa, &p->xb, &p->xc})
+      for (void* ptr : {static_cast<void*>(x->d_copy), static_cast<void*>(x->d_xpose),
+                        static_cast<void*>(x->d_perm)})
+        if (ptr) (void)hipFree(ptr);
+    for (void* ptr : {static_cast<void*>(p->d_A), static_cast<void*>(p->d_B),
+                      static_cast<void*>(p->d_C)})
       if (ptr) (void)hipFree(ptr);
   }
   delete p;
+}
+
+static bsm_status upload_pass(Pass& x) {
+  auto up = [](auto** dst, const auto& v) -> bsm_status {
+    const size_t bytes = v.size() * sizeof(v[0]);
+    if (!bytes) return BSM_OK;
+    TC_HIP(hipMalloc(dst, bytes), "hipMalloc(permutation tables)");
+    TC_HIP(hipMemcpy(*dst, v.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy(permutation tables)");
+    return BSM_OK;
+  };
+  bsm_status st;
+  if ((st = up(&x.d_copy, x.copy)) != BSM_OK) return st;
+  if ((st = up(&x.d_xpose, x.xpose)) != BSM_OK) return st;
+  return up(&x.d_perm, x.perm);
+}
+
+static bsm_status run_pass(const Pass& x, const double* src, void* dst, int c_f32, int accumulate,
+                           hipStream_t s, const char* what) {
+  if (!x.copy.empty())
+    TC_HIP(launch_copy_blocks(x.d_copy, int64_t(x.copy.size()), src, static_cast<double*>(dst), s), what);
+  if (!x.xpose.empty())
+    TC_HIP(launch_transpose_f64(x.d_xpose, int64_t(x.xpose.size()), src, static_cast<double*>(dst), s),
+           what);
+  if (!x.perm.empty())
+    TC_HIP(launch_permute_blocks(x.d_perm, int64_t(x.perm.size()), src, dst, c_f32, accumulate, s),
+           what);
+  return BSM_OK;
 }
 
 // Destination strides, per source mode, of a row-major layout over `layout` (source mode
@@ -367,8 +446,7 @@ bsm_status bsm_tc_plan_create(bsm_tc_plan** out, const bsm_tensor* A, const bsm_
     p->info.workspace_bytes = im.workspace_bytes +
                               (p->info.permute_a ? p->a_mat * 8 : 0) +
                               (p->info.permute_b ? p->b_mat * 8 : 0) +
-                              (p->info.permute_c ? p->c_mat * 8 : 0) +
-                              int64_t((p->pa.size() + p->pb.size() + p->pc.size()) * sizeof(PermBlock));
+                              (p->info.permute_c ? p->c_mat * 8 : 0);
     // the tables stay inside their buffers, and the matricized sizes agree with the plan's
     auto inside = [](const std::vector<PermBlock>& t, int64_t src_n, int64_t dst_n) {
       for (const PermBlock& b : t) {
@@ -382,6 +460,33 @@ bsm_status bsm_tc_plan_create(bsm_tc_plan** out, const bsm_tensor* A, const bsm_
       }
       return true;
     };
+    // pieces: A and B by kind; C element by element (it may accumulate or round to FP32)
+    for (const PermBlock& b : p->pa) lower(b, false, p->xa);
+    for (const PermBlock& b : p->pb) lower(b, false, p->xb);
+    for (const PermBlock& b : p->pc) lower(b, true, p->xc);
+    auto pieces_inside = [](const Pass& x, int64_t src_n, int64_t dst_n) {
+      for (const CopyBlock& b : x.copy)
+        if (b.src_off < 0 || b.dst_off < 0 || b.src_off + b.n > src_n || b.dst_off + b.n > dst_n)
+          return false;
+      for (const XposeBlock& b : x.xpose)
+        if (b.src_off < 0 || b.dst_off < 0 ||
+            b.src_off + int64_t(b.rows - 1) * b.ld_src + b.cols > src_n ||
+            b.dst_off + int64_t(b.cols - 1) * b.ld_dst + b.rows > dst_n)
+          return false;
+      for (const PermBlock& b : x.perm) {
+        int64_t last = 0;
+        for (int m = 0; m < b.order; ++m) last += int64_t(b.ext[m] - 1) * b.dst_stride[m];
+        if (b.e0 < 0 || b.e1 - b.e0 > kPermPiece || b.src_off + b.e1 > src_n ||
+            b.dst_off + last >= dst_n || b.e1 > (int64_t(1) << 32))
+          return false;
+      }
+      return true;
+    };
+    if (!pieces_inside(p->xa, ta_elems, p->a_mat) || !pieces_inside(p->xb, tb_elems, p->b_mat) ||
+        !pieces_inside(p->xc, p->c_mat, p->info.c_elems)) {
+      tc_free(p);
+      return set_error(BSM_E_MISMATCH, "internal: a permutation piece leaves its buffers");
+    }
     if (im.a_elems != p->a_mat || im.b_elems != p->b_mat || ta_elems != p->a_mat ||
         tb_elems != p->b_mat || toff != p->c_mat || !inside(p->pa, ta_elems, p->a_mat) ||
         !inside(p->pb, tb_elems, p->b_mat) || !inside(p->pc, p->c_mat, toff)) {
@@ -418,17 +523,9 @@ bsm_status bsm_tc_execute(bsm_tc_plan* plan, double alpha, const double* dA, con
   if (in.c_elems == 0) return BSM_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!plan->ready) {
-    auto up = [&](PermBlock** dst, const std::vector<PermBlock>& v) -> bsm_status {
-      if (v.empty()) return BSM_OK;
-      TC_HIP(hipMalloc(dst, v.size() * sizeof(PermBlock)), "hipMalloc(permutation tables)");
-      TC_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(PermBlock), hipMemcpyHostToDevice),
-             "hipMemcpy(permutation tables)");
-      return BSM_OK;
-    };
     bsm_status st;
-    if ((st = up(&plan->d_pa, plan->pa)) != BSM_OK) return st;
-    if ((st = up(&plan->d_pb, plan->pb)) != BSM_OK) return st;
-    if ((st = up(&plan->d_pc, plan->pc)) != BSM_OK) return st;
+    for (Pass* x : {&plan->xa, &plan->xb, &plan->xc})
+      if ((st = upload_pass(*x)) != BSM_OK) return st;
     if (in.permute_a && plan->a_mat > 0)
       TC_HIP(hipMalloc(&plan->d_A, size_t(plan->a_mat) * 8), "hipMalloc(matricized A)");
     if (in.permute_b && plan->b_mat > 0)
@@ -439,22 +536,19 @@ bsm_status bsm_tc_execute(bsm_tc_plan* plan, double alpha, const double* dA, con
   }
   const double* xa = dA;
   const double* xb = dB;
+  bsm_status st;
   if (in.permute_a) {
-    TC_HIP(launch_permute_blocks(plan->d_pa, int64_t(plan->pa.size()), dA, plan->d_A, 0, 0, s),
-           "matricize A");
+    if ((st = run_pass(plan->xa, dA, plan->d_A, 0, 0, s, "matricize A")) != BSM_OK) return st;
     xa = plan->d_A;
   }
   if (in.permute_b) {
-    TC_HIP(launch_permute_blocks(plan->d_pb, int64_t(plan->pb.size()), dB, plan->d_B, 0, 0, s),
-           "matricize B");
+    if ((st = run_pass(plan->xb, dB, plan->d_B, 0, 0, s, "matricize B")) != BSM_OK) return st;
     xb = plan->d_B;
   }
   if (!in.permute_c) return bsm_execute(plan->mat, alpha, xa, xb, dC, accumulate, stream);
-  bsm_status st = bsm_execute(plan->mat, alpha, xa, xb, plan->d_C, 0, stream);
+  st = bsm_execute(plan->mat, alpha, xa, xb, plan->d_C, 0, stream);
   if (st != BSM_OK) return st;
-  TC_HIP(launch_permute_blocks(plan->d_pc, int64_t(plan->pc.size()), plan->d_C, dC, plan->c_f32,
-                               accumulate, s), "C into its mode order");
-  return BSM_OK;
+  return run_pass(plan->xc, plan->d_C, dC, plan->c_f32, accumulate, s, "C into its mode order");
 }
 
 bsm_status bsm_tc_plan_verify(bsm_tc_plan* plan, void* stream) {

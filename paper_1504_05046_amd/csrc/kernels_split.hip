@@ -104,9 +104,9 @@ __global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict
   }
 }
 
-// One workgroup per block: the stored rows x cols block goes through LDS in 64 x 64 tiles (reads
-// coalesced along the stored rows, writes along the transposed rows) and is written cols x rows,
-// rounded to T.  The 65-element row pitch spreads both phases over the LDS banks.
+// One workgroup per piece (at most 64 source rows): the piece goes through LDS in 64 x 64 tiles
+// (reads coalesced along the source rows, writes along the destination rows), rounded to T.  The
+// 65-element row pitch spreads both phases over the LDS banks.
 template <typename T>
 __global__ __launch_bounds__(256) void transpose_blocks(const XposeBlock* __restrict__ blocks,
                                                         const double* __restrict__ src,
@@ -121,12 +121,12 @@ __global__ __launch_bounds__(256) void transpose_blocks(const XposeBlock* __rest
       const int tw = b.cols - c0 < 64 ? b.cols - c0 : 64;
       for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
         const int rr = e >> 6, cc = e & 63;
-        if (rr < th && cc < tw) tile[rr][cc] = sb[int64_t(r0 + rr) * b.cols + c0 + cc];
+        if (rr < th && cc < tw) tile[rr][cc] = sb[int64_t(r0 + rr) * b.ld_src + c0 + cc];
       }
       __syncthreads();
       for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
         const int cc = e >> 6, rr = e & 63;
-        if (rr < th && cc < tw) db[int64_t(c0 + cc) * b.rows + r0 + rr] = T(tile[rr][cc]);
+        if (rr < th && cc < tw) db[int64_t(c0 + cc) * b.ld_dst + r0 + rr] = T(tile[rr][cc]);
       }
       __syncthreads();
     }
@@ -251,16 +251,17 @@ __global__ __launch_bounds__(256) void permute_blocks(const PermBlock* __restric
                                                       const double* __restrict__ src,
                                                       T* __restrict__ dst, int accumulate) {
   const PermBlock b = blocks[blockIdx.x];
-  int64_t n = 1;
-  for (int m = 0; m < b.order; ++m) n *= b.ext[m];
   const double* s = src + b.src_off;
   T* d = dst + b.dst_off;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
-    int64_t rem = e, o = 0;
+  // a piece holds fewer than 2^32 elements of one block: 32-bit index arithmetic
+  for (int64_t e = b.e0 + threadIdx.x; e < b.e1; e += blockDim.x) {
+    uint32_t rem = uint32_t(e);
+    int64_t o = 0;
     for (int m = b.order - 1; m >= 0; --m) {
-      const int64_t x = rem % b.ext[m];
-      rem /= b.ext[m];
-      o += x * b.dst_stride[m];
+      const uint32_t ext = uint32_t(b.ext[m]);
+      const uint32_t q = rem / ext;
+      o += int64_t(rem - q * ext) * b.dst_stride[m];
+      rem = q;
     }
     const double v = s[e];
     d[o] = T(accumulate ? v + double(d[o]) : v);

@@ -26,6 +26,7 @@
 #include "../../include/bsm.h"
 #include "errors.hpp"
 #include "kernels.hpp"
+#include "staging.hpp"
 
 using namespace bsm;
 
@@ -90,8 +91,10 @@ static bool runs_inside(const std::vector<CopyBlock>& t, int64_t src_n, int64_t 
 }
 static bool blocks_inside(const std::vector<XposeBlock>& t, int64_t src_n, int64_t dst_n) {
   for (const XposeBlock& b : t) {
-    const int64_t n = int64_t(b.rows) * b.cols;
-    if (b.src_off < 0 || b.dst_off < 0 || b.src_off + n > src_n || b.dst_off + n > dst_n) return false;
+    if (b.rows <= 0 || b.cols <= 0) continue;
+    const int64_t last_src = b.src_off + int64_t(b.rows - 1) * b.ld_src + b.cols - 1;
+    const int64_t last_dst = b.dst_off + int64_t(b.cols - 1) * b.ld_dst + b.rows - 1;
+    if (b.src_off < 0 || b.dst_off < 0 || last_src >= src_n || last_dst >= dst_n) return false;
   }
   return true;
 }
@@ -192,12 +195,12 @@ bsm_status bsm_lr_plan_create(bsm_lr_plan** out, int64_t M, const int64_t* row_s
         const int64_t o = dense_off[size_t(i * K + k)];
         if (o < 0) continue;
         const int64_t n = row_sizes[i] * inner_sizes[k];
-        p->gather.push_back(CopyBlock{o, a2pos, n});
+        push_copy(p->gather, o, a2pos, n);
         a2pos += n;
       }
       for (; fq < fac.size() && fac[fq].i == i; ++fq) {
         const int64_t n = row_sizes[i] * fac[fq].rho;
-        p->gather.push_back(CopyBlock{fac[fq].u_off, a2pos, n});
+        push_copy(p->gather, fac[fq].u_off, a2pos, n);
         a2pos += n;
       }
     }
@@ -242,8 +245,8 @@ bsm_status bsm_lr_plan_create(bsm_lr_plan** out, int64_t M, const int64_t* row_s
     for (int64_t f = 0; f < Q; ++f) {
       const Fac& x = fac[size_t(f)];
       const int64_t g = group_of_k[size_t(x.k)];
-      p->vt.push_back(XposeBlock{x.v_off, a1_off[size_t(g)] + first_row[size_t(f)] * inner_sizes[x.k],
-                                 int32_t(inner_sizes[x.k]), int32_t(x.rho)});
+      push_transpose(p->vt, x.v_off, a1_off[size_t(g)] + first_row[size_t(f)] * inner_sizes[x.k],
+                     int32_t(inner_sizes[x.k]), int32_t(x.rho));
     }
     p->v_elems = v1pos;
     // stage 1's C: block (g, j) at the packed offset of the stacked R_g x t_j blocks; W_(q)j is
@@ -266,8 +269,8 @@ bsm_status bsm_lr_plan_create(bsm_lr_plan** out, int64_t M, const int64_t* row_s
         for (int64_t j = 0; j < N; ++j) {
           if (!bit_of(b_bits, N, x.k, j)) continue;
           const int64_t n = x.rho * col_sizes[j];
-          p->restack.push_back(
-              CopyBlock{c1_off[size_t(g * N + j)] + first_row[size_t(f)] * col_sizes[j], bpos, n});
+          push_copy(p->restack, c1_off[size_t(g * N + j)] + first_row[size_t(f)] * col_sizes[j],
+                    bpos, n);
           bpos += n;
         }
       }

@@ -13,6 +13,7 @@
 #include <tuple>
 
 #include "../../include/bsm.h"
+#include "staging.hpp"
 
 namespace bsm {
 
@@ -582,16 +583,16 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
         for (int64_t k = 0; k < K; ++k) {
           const int64_t o = p.a_off[size_t(i * K + k)];
           if (o >= 0)
-            p.xpose_a.push_back(XposeBlock{st_a[size_t(k * M + i)], o, int32_t(p.inner[size_t(k)]),
-                                           int32_t(p.rows[size_t(i)])});
+            push_transpose(p.xpose_a, st_a[size_t(k * M + i)], o, int32_t(p.inner[size_t(k)]),
+                           int32_t(p.rows[size_t(i)]));
         }
     if (tb)
       for (int64_t k = 0; k < K; ++k)
         for (int64_t j = 0; j < N; ++j) {
           const int64_t o = p.b_off[size_t(k * N + j)];
           if (o >= 0)
-            p.xpose_b.push_back(XposeBlock{st_b[size_t(j * K + k)], o, int32_t(p.cols[size_t(j)]),
-                                           int32_t(p.inner[size_t(k)])});
+            push_transpose(p.xpose_b, st_b[size_t(j * K + k)], o, int32_t(p.cols[size_t(j)]),
+                           int32_t(p.inner[size_t(k)]));
         }
   }
 

@@ -52,14 +52,17 @@ struct SplitBlock {
   int32_t transpose;  // 1: the source is ks x rows (B) and is written transposed
 };
 
-// One block of a transposed operand as the transposition pass sees it: the stored block at
-// src_off is rows x cols (row-major); it is written transposed (cols x rows, row-major) at dst_off
-// of the operand in the product's own layout.
+// One piece of a transposition pass (a transposed operand into the product's layout, V factors
+// into V^T, a tensor block whose modes fall into two swapped groups): rows x cols source elements,
+// element (r, c) at src_off + r ld_src + c, written to dst_off + c ld_dst + r.  Large blocks are
+// cut into bands of rows so that one workgroup handles one band.
 struct XposeBlock {
   int64_t src_off;
   int64_t dst_off;
   int32_t rows;
   int32_t cols;
+  int32_t ld_src;
+  int32_t ld_dst;
 };
 
 // One contiguous run of n elements copied from src_off to dst_off (gathering the dense blocks and
@@ -75,6 +78,7 @@ struct CopyBlock {
 // dst_off + sum_m x_m dst_stride[m] (the matricized block's, or the tensor block's, row-major
 // position).
 constexpr int kMaxModes = 8;
+// Source elements [e0, e1) of the block (a large block is cut into several pieces).
 struct PermBlock {
   int64_t src_off;
   int64_t dst_off;
@@ -82,6 +86,7 @@ struct PermBlock {
   int32_t pad_;
   int32_t ext[kMaxModes];
   int64_t dst_stride[kMaxModes];
+  int64_t e0, e1;
 };
 
 // Complex elements run as a real product: one block of a complex operand as the embedding pass
