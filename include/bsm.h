@@ -132,6 +132,17 @@ typedef struct {
                              1 for real elements); 0 = as is */
   int32_t trans_b;        /* the same for B: 1 = B^T, 2 = B^H, stored as the N x K block matrix */
   int32_t elem;           /* bsm_elem: element type of A, B and C */
+  int32_t k_split;        /* reduction variant (Sec. 3.2 splits each update into a multiply and a
+                             reduction into C; the tile kernels fuse the two, one task per C
+                             sub-tile): n in 2..16 cuts every task's k-list into up to n pieces
+                             of equal triple count that run as separate tasks, each writing FP64
+                             partial sums, which a reduction pass adds in piece order; for products
+                             whose C has too few tiles to fill the GPU.  -1 = n chosen by the
+                             library (2048 / tasks, at most 16) for products with fewer than 1024
+                             tasks, none otherwise; 0 or 1 = off.  Changes the summation order,
+                             not which terms are summed.  Needs k_window 0 and host k-lists
+                             (BSM_E_UNSUPPORTED otherwise for n >= 2; -1 then means off); batches
+                             and bsm_execute_static take plans without it. */
   const char* tune_cache; /* NULL, or a file where bsm_autotune looks up and records its choices
                              (lines "signature variant"); the string is copied */
 } bsm_options;
@@ -150,6 +161,7 @@ typedef struct {
   int32_t out;             /* bsm_out: element type of C */
   int32_t device_klists;   /* 1: the k-lists are built on the device, batch by batch */
   int32_t elem;            /* bsm_elem; a_elems, b_elems, c_elems count elements of this type */
+  int32_t k_split;         /* pieces per k-list (1 = the fused C-stationary tasks only) */
 } bsm_plan_info;
 
 typedef struct bsm_batch bsm_batch;

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
                 ("out", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("patch_rows", ctypes.c_int32), ("patch_cols", ctypes.c_int32),
                 ("device_klists", ctypes.c_int32), ("trans_a", ctypes.c_int32),
-                ("trans_b", ctypes.c_int32), ("elem", ctypes.c_int32),
+                ("trans_b", ctypes.c_int32), ("elem", ctypes.c_int32), ("k_split", ctypes.c_int32),
                 ("tune_cache", ctypes.c_char_p)]
 
 
@@ -52,7 +52,7 @@ class PlanInfo(ctypes.Structure):
                 ("useful_flops", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
                 ("k_windows", ctypes.c_int64), ("tile", ctypes.c_int32),
                 ("out", ctypes.c_int32), ("device_klists", ctypes.c_int32),
-                ("elem", ctypes.c_int32)]
+                ("elem", ctypes.c_int32), ("k_split", ctypes.c_int32)]
 
 
 class LrInfo(ctypes.Structure):
@@ -200,14 +200,14 @@ def _arr(a, dtype):
 
 def options(precision=FP64, sched=SCHED_FLOPS, k_window=0, record_timings=0, tile=0,
             use_graph=0, out=OUT_F64, order=ORDER_DEFAULT, patch=(0, 0), device_klists=0,
-            tune_cache=None, trans_a=0, trans_b=0, elem=0) -> Options:
+            tune_cache=None, trans_a=0, trans_b=0, elem=0, k_split=0) -> Options:
     o = Options()
     load().bsm_options_default(ctypes.byref(o))
     o.precision, o.sched, o.k_window, o.record_timings, o.tile = precision, sched, k_window, record_timings, tile
     o.use_graph, o.out, o.order = use_graph, out, order
     o.patch_rows, o.patch_cols = int(patch[0]), int(patch[1])
     o.device_klists = int(device_klists)
-    o.trans_a, o.trans_b, o.elem = int(trans_a), int(trans_b), int(elem)
+    o.trans_a, o.trans_b, o.elem, o.k_split = int(trans_a), int(trans_b), int(elem), int(k_split)
     o.tune_cache = tune_cache.encode() if tune_cache else None
     return o
 

@@ -228,6 +228,10 @@ struct bsm_plan {
   ZBlock* d_zembed_a = nullptr;
   ZBlock* d_zembed_b = nullptr;
   ZCBlock* d_zc = nullptr;
+  double* d_splitP = nullptr;       // reduction variant: ksplit partial sums laid out like C
+  ProductArgs* d_kprods = nullptr;  // ... and the operand table of the pieces
+  std::vector<ProductArgs> h_kprods;
+  bool kprods_used = false;         // a queued launch may read d_kprods
   double* d_partial = nullptr;      // raw sums between k-windows (laid out like C)
   // device-built k-lists: shapes, offset tables and inner sizes
   uint64_t* d_abits = nullptr;
@@ -295,6 +299,11 @@ static bsm_status prepare(bsm_plan* p) {
     if (h.a_elems > 0) BSM_HIP(hipMalloc(&p->d_zA, size_t(h.a_elems) * 8), "hipMalloc(embedded A)");
     if (h.b_elems > 0) BSM_HIP(hipMalloc(&p->d_zB, size_t(h.b_elems) * 8), "hipMalloc(embedded B)");
     if (h.c_elems > 0) BSM_HIP(hipMalloc(&p->d_zP, size_t(h.c_elems) * 8), "hipMalloc(complex C parts)");
+  }
+  if (h.ksplit > 1) {
+    if (h.c_elems > 0)
+      BSM_HIP(hipMalloc(&p->d_splitP, size_t(h.c_elems) * 8 * size_t(h.ksplit)), "hipMalloc(partial sums)");
+    BSM_HIP(hipMalloc(&p->d_kprods, sizeof(ProductArgs) * size_t(h.ksplit)), "hipMalloc(piece table)");
   }
   if (h.windows > 1 && h.c_elems > 0)
     BSM_HIP(hipMalloc(&p->d_partial, size_t(h.c_elems) * 8), "hipMalloc(partial)");
@@ -752,6 +761,7 @@ bsm_status bsm_execute_static(const bsm_plan* plan, double alpha, const double* 
   if (h.dev_klists)
     return fail(BSM_E_UNSUPPORTED, "bsm_execute_static needs the k-lists in the plan's host list");
   if (h.cplx) return fail(BSM_E_UNSUPPORTED, "bsm_execute_static runs real plans only");
+  if (h.ksplit > 1) return fail(BSM_E_UNSUPPORTED, "bsm_execute_static runs plans without k_split");
   const StaticLayout L = static_layout(h);
   if (L.total > kStaticScratchBytes)
     return fail(BSM_E_NOMEM, "the plan needs " + std::to_string(L.total) +
@@ -816,6 +826,7 @@ void bsm_options_default(bsm_options* opt) {
   opt->trans_a = 0;
   opt->trans_b = 0;
   opt->elem = BSM_REAL;
+  opt->k_split = 0;
   opt->tune_cache = nullptr;
 }
 
@@ -872,6 +883,7 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
   if (o.patch_cols > 0) cfg.patch_c = o.patch_cols;
   cfg.device_klists = o.device_klists;
   if (o.elem != BSM_REAL && o.elem != BSM_COMPLEX) return fail(BSM_E_INVALID, "unknown element type");
+  cfg.k_split = o.k_split;
   cfg.cplx = o.elem == BSM_COMPLEX;
   // for real elements the adjoint is the transpose
   cfg.trans_a = (!cfg.cplx && o.trans_a == 2) ? 1 : o.trans_a;
@@ -916,6 +928,7 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
     ws += h.tri_capacity * int64_t(sizeof(Triple)) + int64_t(h.jobs.size() * sizeof(KJob)) +
           int64_t((h.a_bits.size() + h.bt_bits.size()) * 8 + (h.a_tab.size() + h.bt_tab.size() + h.inner.size()) * 8);
   ws += staged_bytes(h, false) + staged_bytes(h, true) + staging_table_bytes(h) + complex_bytes(h);
+  if (h.ksplit > 1) ws += h.c_elems * 8 * h.ksplit + int64_t(sizeof(ProductArgs)) * h.ksplit;
   if (h.windows > 1) ws += h.c_elems * 8;
   if (h.cfg.record_timings) ws += int64_t(h.items.size()) * 16;
   info->workspace_bytes = ws;
@@ -924,6 +937,7 @@ bsm_status bsm_plan_query(const bsm_plan* plan, bsm_plan_info* info) {
   info->out = h.user_out_f32() ? BSM_OUT_F32 : BSM_OUT_F64;
   info->device_klists = h.dev_klists ? 1 : 0;
   info->elem = h.cplx ? BSM_COMPLEX : BSM_REAL;
+  info->k_split = h.ksplit;
   return BSM_OK;
 }
 
@@ -965,10 +979,47 @@ static bsm_status enqueue_product(bsm_plan* plan, double ar, double ai, const do
   pa.c_f32 = h.cfg.out_f32;
   pa.P = plan->d_partial;
   pa.alpha = h.cplx ? 1.0 : ar;
-  r = enqueue_tiles(h, plan->ts, nullptr, pa, h.cplx ? 0 : accumulate, skip, q, &plan->dk);
+  if (h.ksplit > 1) {
+    // pieces into their partial buffers (absent pieces leave zeros), then their ordered sum
+    BSM_HIP(launch_fill_zero(plan->d_splitP, h.c_elems * h.ksplit, q), "clear partial sums");
+    r = enqueue_tiles(h, plan->ts, plan->d_kprods, pa, 0, skip, q, &plan->dk);
+    if (r != BSM_OK) return r;
+    plan->kprods_used = true;
+    BSM_HIP(launch_reduce_splits(plan->d_splitP, h.ksplit, h.c_elems, pa.C, pa.c_f32, pa.alpha,
+                                 h.cplx ? 0 : accumulate, q), "sum partial sums");
+  } else {
+    r = enqueue_tiles(h, plan->ts, nullptr, pa, h.cplx ? 0 : accumulate, skip, q, &plan->dk);
+  }
   if (r != BSM_OK || !h.cplx) return r;
   BSM_HIP(launch_complex_epilogue(plan->d_zc, int64_t(h.zc.size()), plan->d_zP, dC, h.z_out_f32,
                                   ar, ai, accumulate, q), "complex epilogue");
+  return BSM_OK;
+}
+
+// Reduction variant: the operand table of the ksplit pieces (the operands as the tile kernels read
+// them, piece s writing its raw sums to partial buffer s), refreshed before anything is queued
+// when the operands changed; a launch still queued may read the old table, so it is waited for.
+static bsm_status kprods_refresh(bsm_plan* plan, const double* dA, const double* dB,
+                                 hipStream_t s) {
+  const HostPlan& h = plan->hp;
+  if (h.ksplit <= 1) return BSM_OK;
+  ProductArgs pa{};
+  bind_operands(h, h.cplx ? plan->d_zA : dA, h.cplx ? plan->d_zB : dB, staging_of(plan), pa);
+  std::vector<ProductArgs> t(size_t(h.ksplit));
+  for (int q = 0; q < h.ksplit; ++q) {
+    t[size_t(q)] = pa;
+    t[size_t(q)].C = plan->d_splitP + int64_t(q) * h.c_elems;
+    t[size_t(q)].c_f32 = 0;
+    t[size_t(q)].P = nullptr;
+    t[size_t(q)].alpha = 1.0;
+  }
+  if (t.size() == plan->h_kprods.size() &&
+      std::memcmp(t.data(), plan->h_kprods.data(), t.size() * sizeof(ProductArgs)) == 0)
+    return BSM_OK;
+  if (plan->kprods_used) BSM_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  BSM_HIP(hipMemcpy(plan->d_kprods, t.data(), t.size() * sizeof(ProductArgs), hipMemcpyHostToDevice),
+          "hipMemcpy(piece table)");
+  plan->h_kprods = t;
   return BSM_OK;
 }
 
@@ -984,6 +1035,7 @@ bsm_status bsm_execute_complex(bsm_plan* plan, double alpha_re, double alpha_im,
   if ((st = prepare(plan)) != BSM_OK) return st;
   if ((st = sync_tasks(plan, s)) != BSM_OK) return st;
   if (h.items.empty()) return BSM_OK;
+  if ((st = kprods_refresh(plan, dA, dB, s)) != BSM_OK) return st;
   auto body = [&](hipStream_t q) -> bsm_status {
     return enqueue_product(plan, alpha_re, alpha_im, dA, dB, dC, accumulate, plan->skip_task, q);
   };
@@ -1060,6 +1112,7 @@ bsm_status bsm_autotune(bsm_plan* plan, const double* dA, const double* dB, void
     plan->tasks_dirty = true;
     return sync_tasks(plan, s);
   };
+  if ((st = kprods_refresh(plan, dA, dB, s)) != BSM_OK) return st;
   if (!tune_cache_lookup(h.cfg.tune_cache, key, nvar, cv)) {
     auto body = [&](hipStream_t q) -> bsm_status {
       return enqueue_product(plan, 1.0, 0.0, dA, dB, dC, 0, -1, q);
@@ -1112,6 +1165,7 @@ bsm_status bsm_plan_destroy(bsm_plan* plan) {
                       static_cast<void*>(plan->d_zA), static_cast<void*>(plan->d_zB),
                       static_cast<void*>(plan->d_zP), static_cast<void*>(plan->d_zembed_a),
                       static_cast<void*>(plan->d_zembed_b), static_cast<void*>(plan->d_zc),
+                      static_cast<void*>(plan->d_splitP), static_cast<void*>(plan->d_kprods),
                       static_cast<void*>(plan->d_abits), static_cast<void*>(plan->d_btbits),
                       static_cast<void*>(plan->d_atab), static_cast<void*>(plan->d_bttab),
                       static_cast<void*>(plan->d_inner)})

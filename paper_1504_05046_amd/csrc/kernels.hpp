@@ -78,6 +78,11 @@ hipError_t launch_transpose_f32(const XposeBlock* blocks, int64_t nblocks, const
 // destination receives src + dst; dst is FP64 or (c_f32) FP32
 hipError_t launch_permute_blocks(const PermBlock* blocks, int64_t nblocks, const double* src,
                                  void* dst, int c_f32, int accumulate, hipStream_t stream);
+// reduction variant: dst[0 .. n) = 0, and C[e] = alpha sum_{s < S} P[s n + e] (+ C[e]) with the
+// pieces added in order s = 0 .. S-1 (FP64; C FP64 or, with c_f32, rounded once to FP32)
+hipError_t launch_fill_zero(double* dst, int64_t n, hipStream_t stream);
+hipError_t launch_reduce_splits(const double* P, int S, int64_t n, void* C, int c_f32,
+                                double alpha, int accumulate, hipStream_t stream);
 // runs of elements src[src_off .. src_off + n) -> dst[dst_off ..), one workgroup per run
 hipError_t launch_copy_blocks(const CopyBlock* blocks, int64_t nblocks, const double* src,
                               double* dst, hipStream_t stream);

@@ -280,6 +280,48 @@ hipError_t launch_permute_blocks(const PermBlock* blocks, int64_t nblocks, const
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void fill_zero(double* __restrict__ d, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += stride) d[e] = 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_splits(const double* __restrict__ P, int S,
+                                                     int64_t n, T* __restrict__ C, double alpha,
+                                                     int accumulate) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += stride) {
+    double acc = P[e];
+    for (int s = 1; s < S; ++s) acc += P[int64_t(s) * n + e];
+    const double v = alpha * acc;
+    C[e] = T(accumulate ? v + double(C[e]) : v);
+  }
+}
+
+static int64_t flat_grid(int64_t n) {
+  int64_t blocks = (n + 255) / 256;
+  return blocks < 1 ? 1 : (blocks > 256 * 32 ? 256 * 32 : blocks);
+}
+
+hipError_t launch_fill_zero(double* dst, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero, dim3(uint32_t(flat_grid(n))), dim3(256), 0, stream, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_splits(const double* P, int S, int64_t n, void* C, int c_f32,
+                                double alpha, int accumulate, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid(uint32_t(flat_grid(n)));
+  if (c_f32)
+    hipLaunchKernelGGL(reduce_splits<float>, grid, dim3(256), 0, stream, P, S, n,
+                       static_cast<float*>(C), alpha, accumulate);
+  else
+    hipLaunchKernelGGL(reduce_splits<double>, grid, dim3(256), 0, stream, P, S, n,
+                       static_cast<double*>(C), alpha, accumulate);
+  return hipGetLastError();
+}
+
 // One workgroup per run; 16-byte accesses when both ends are 16-byte aligned, else 8-byte ones.
 __global__ __launch_bounds__(256) void copy_blocks(const CopyBlock* __restrict__ blocks,
                                                    const double* __restrict__ src,

@@ -379,6 +379,31 @@ void cut_items(HostPlan& p, const int class_var[kSizeClasses]) {
         p.features.push_back(float(p.k_total > 0 ? cb.sk / p.k_total : 0.0));
       }
   }
+  if (p.ksplit > 1) {
+    // reduction variant: each task's k-list cut into up to ksplit contiguous pieces of equal
+    // triple count; piece s writes its partial sums into partial buffer s (the task's product)
+    std::vector<Item> its;
+    std::vector<ItemMeta> ms;
+    std::vector<float> fs;
+    for (size_t q = 0; q < p.items.size(); ++q) {
+      const Item& it = p.items[q];
+      const uint64_t T = it.tri_count;
+      const uint64_t S = std::min<uint64_t>(uint64_t(p.ksplit), std::max<uint64_t>(T, 1));
+      for (uint64_t s = 0; s < S; ++s) {
+        Item x = it;
+        const uint64_t b0 = T * s / S, b1 = T * (s + 1) / S;
+        x.tri_begin = uint32_t(it.tri_begin + b0);
+        x.tri_count = uint32_t(b1 - b0);
+        x.product = uint32_t(s);
+        its.push_back(x);
+        ms.push_back(p.meta[q]);
+        for (int f = 0; f < 5; ++f) fs.push_back(p.features[q * 5 + size_t(f)]);
+      }
+    }
+    p.items.swap(its);
+    p.meta.swap(ms);
+    p.features.swap(fs);
+  }
 }
 
 // Complex elements: the product runs as the real product of the embeddings
@@ -483,6 +508,7 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
     return "unknown tile variant";
   if (cfg.order < ORDER_LOCALITY || cfg.order > ORDER_PATCH) return "unknown task order";
   if (cfg.device_klists < -1) return "device_klists must be -1, 0, 1 or a batch size >= 2";
+  if (cfg.k_split < -1 || cfg.k_split > 16) return "k_split must be -1 (auto), 0, 1 or 2..16";
   if (cfg.patch_r < 1 || cfg.patch_c < 1) return "patch sizes must be >= 1";
 
   p.cfg = cfg;
@@ -722,6 +748,28 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   p.k_total = 0;
   for (int64_t k = 0; k < K; ++k) p.k_total += double(p.inner[size_t(k)]);
   cut_items(p, cfg.tile > 0 ? cfg.tile - 1 : (bf16 ? kDefaultBf16Variant : kDefaultVariant));
+  // reduction variant (Sec. 3.2 splits every update into a multiply task and a reduction into C;
+  // the tile kernel fuses the two, which leaves a product with few C tiles too few tasks): cut
+  // every task's k-list into pieces whose partial sums a reduction pass adds, in piece order
+  if (cfg.k_split > 1 || cfg.k_split == -1) {
+    const bool windows = cfg.k_window != 0 && cfg.k_window < K;
+    if (p.dev_klists || windows) {
+      if (cfg.k_split > 1) {
+        *code = BSM_E_UNSUPPORTED;
+        return "k_split needs k-lists in the host list and k_window 0";
+      }
+    } else {
+      int S = cfg.k_split;
+      if (S == -1) {  // auto: split only products with fewer than 1024 tasks, towards 2048
+        const int64_t n = int64_t(p.items.size());
+        S = n > 0 && n < 1024 ? int(std::min<int64_t>(16, (2048 + n - 1) / n)) : 1;
+      }
+      if (S > 1) {
+        p.ksplit = S;
+        cut_items(p, p.class_var);
+      }
+    }
+  }
   // S5: k-windows (0 = all K inner blocks in flight at once)
   p.k_window_eff = (cfg.k_window == 0 || cfg.k_window >= K) ? std::max<int64_t>(K, 1) : cfg.k_window;
   p.windows = K > 0 ? (K + p.k_window_eff - 1) / p.k_window_eff : 1;
@@ -747,6 +795,10 @@ std::string merge_plans(HostPlan& out, const std::vector<const HostPlan*>& parts
     const HostPlan& p = *parts[q];
     if (p.cfg.precision != p0.cfg.precision) return "batch members differ in precision";
     if (p.windows != 1) return "batch members must issue all k-iterations at once (k_window 0)";
+    if (p.ksplit > 1) {
+      *code = BSM_E_UNSUPPORTED;
+      return "batch members cannot split their k-lists (k_split)";
+    }
     if (p.dev_klists) {
       *code = BSM_E_UNSUPPORTED;
       return "batch members must keep their k-lists on the host (device k-lists are per plan)";

@@ -42,6 +42,7 @@ struct PlanConfig {
   int trans_a = 0, trans_b = 0;  // the product reads A^T (B^T): the operand is stored transposed;
                                  // with complex elements 2 = the adjoint
   int cplx = 0;                  // complex elements (run as the real embedding)
+  int k_split = 0;               // reduction variant: 0/1 off, n >= 2 pieces per k-list, -1 auto
   std::string tune_cache;  // autotuner choices file ("" = none)
 };
 
@@ -131,6 +132,7 @@ struct HostPlan {
   int64_t user_b() const { return cplx ? b_elems / 2 : b_elems; }
   int64_t user_c() const { return cplx ? c_elems / 2 : c_elems; }
   bool user_out_f32() const { return cplx ? z_out_f32 != 0 : cfg.out_f32 != 0; }
+  int ksplit = 1;                // pieces each task's k-list is cut into (reduction variant)
   int64_t k_window_eff = 0;      // inner blocks per k-window
   int64_t windows = 1;           // number of k-windows
 

@@ -491,3 +491,36 @@ def test_contraction_plans_on_host():
         bsm.Contraction(([0, 1], [[2, 3], [4, 5]], np.array([1 << 5], np.uint64)),
                         ([1, 2], [[4, 5], [1, 1]], bits), [0, 2])
     assert e.value.code == bsm.E_INVALID
+
+
+def test_k_split_plans_on_host():
+    """Reduction variant: every task's k-list cut into pieces (task count grows, C layout and flops
+    do not), auto only for products with few tasks, and the combinations it does not support."""
+    rng = np.random.default_rng(95)
+    rows, inner = np.array([100, 60, 90]), rng.integers(32, 200, 40)
+    a_mask = np.ones((3, 40), bool)
+    p = gen.make_problem("tall", 95, rows, inner, rows, a_mask, a_mask.T.copy())
+    base = bsm.Plan.from_problem(p).info()
+    for ks in (2, 5, 16):
+        i = bsm.Plan.from_problem(p, k_split=ks).info()
+        assert i.k_split == ks and i.tasks == base.tasks * ks
+        assert (i.c_elems, i.useful_flops, i.triples) == (base.c_elems, base.useful_flops, base.triples)
+        assert i.workspace_bytes > base.workspace_bytes
+    auto = bsm.Plan.from_problem(p, k_split=-1).info()
+    assert auto.k_split == min(16, -(-2048 // base.tasks)) and base.tasks < 1024
+    big = gen.uniform_1024()
+    assert bsm.Plan.from_problem(big, k_split=-1).info().k_split == 1 or \
+        bsm.Plan.from_problem(big).info().tasks < 1024
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Plan.from_problem(p, k_split=4, k_window=3)
+    assert e.value.code == bsm.E_UNSUPPORTED
+    assert bsm.Plan.from_problem(p, k_split=-1, k_window=3).info().k_split == 1
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Plan.from_problem(p, k_split=17)
+    assert e.value.code == bsm.E_INVALID
+    sp = bsm.Plan.from_problem(p, k_split=3)
+    with pytest.raises(bsm.BsmError) as e:
+        bsm.Batch([sp])
+    assert e.value.code == bsm.E_UNSUPPORTED
+    L = bsm.load()
+    assert L.bsm_execute_static(sp.handle, 1.0, 1 << 32, 1 << 36, 1 << 40, 0, None) == bsm.E_UNSUPPORTED
