@@ -376,6 +376,76 @@ def lowrank_section(torch, bsm, dev, stream, steps=10, warmup=3):
     return out
 
 
+def contraction_section(torch, bsm, dev, stream, steps=10, warmup=3):
+    """The coupled-cluster ladder contraction C[i,j,a,b] = sum_cd T[i,j,c,d] V[a,b,c,d] with V
+    stored contracted-modes-last (so it goes through the permutation pass every step)."""
+    from paper_1504_05046_amd import gen
+    say("ladder_contraction: generating inputs")
+    t0 = time.perf_counter()
+    occ, vir, (pt, dt_), (pv, dv) = gen.ladder_tensors()
+    gen_s = time.perf_counter() - t0
+    plan = bsm.Contraction(([0, 1, 2, 3], [occ, occ, vir, vir], gen.tensor_bits(pt)),
+                           ([4, 5, 2, 3], [vir] * 4, gen.tensor_bits(pv)), [0, 1, 4, 5], use_graph=1)
+    info = plan.info()
+    T = torch.from_numpy(dt_).to(dev)
+    V = torch.from_numpy(dv).to(dev)
+    del dt_, dv
+    C = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
+    w, e, _ = time_plan(plan, T, V, C, steps, warmup, stream, torch)
+    plan.verify(stream=stream)
+    out = {
+        "workload": "ladder_contraction: C[i,j,a,b] = sum_cd T[i,j,c,d] V[a,b,c,d], 48 occupied "
+                    "indices in blocks U{8..24}, 192 virtual in blocks U{16..48}, T block density "
+                    "0.5, V 0.3, N(0,1)",
+        "t_blocks": int(pt.sum()), "v_blocks": int(pv.sum()), "v_gb": round(V.numel() * 8 / 1e9, 3),
+        "useful_gflop": round(info.useful_flops / 1e9, 3), "matricized": [info.M, info.K, info.N],
+        "permutation_passes": [info.permute_a, info.permute_b, info.permute_c],
+        "ms_per_step": round(w, 4), "launch_ms": round(e, 4),
+        "value": round(info.useful_flops / (w * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+        "mfma_frac": round(info.useful_flops / (e * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        "gen_s": round(gen_s, 1),
+        "note": "V permuted into matrix order inside every step (HBM pass over V), then the FP64 "
+                "block-sparse product",
+    }
+    plan.close()
+    del T, V, C
+    return out
+
+
+def gram_section(torch, bsm, dev, stream, steps=20, warmup=3):
+    """A Gram product C = X^T X of a tall block-sparse X (65536 x 2048, blocks U{32..256} by
+    U{64..256}, density 0.5), X handed over once (A = X read transposed, B = X): few C tiles and
+    long k-lists, with and without the reduction variant."""
+    from paper_1504_05046_amd import gen
+    say("gram_65536x2048: generating inputs")
+    rng = np.random.default_rng(7500)
+    xr = gen.tiling_random(65536, 32, 256, rng)
+    xc = gen.tiling_random(2048, 64, 256, np.random.default_rng(7501))
+    mask = np.random.default_rng(7502).random((xr.size, xc.size)) < 0.5
+    x = gen.make_problem("X", 7503, xr, xc, xc, mask, np.ones((xc.size, xc.size), bool))
+    X = torch.from_numpy(x.a_data).to(dev)
+    out = {"workload": "gram_65536x2048: C = X^T X, X 65536 x 2048 in blocks U{32..256} x "
+                       "U{64..256}, block density 0.5, N(0,1); X passed once as both operands"}
+    ref = None
+    for key, ks in (("fused", 0), ("k_split_auto", -1)):
+        plan = bsm.Plan(xc, xr, xc, x.a_bits(), x.a_bits(), trans_a=1, k_split=ks, use_graph=1)
+        info = plan.info()
+        C = torch.zeros(max(1, info.c_elems), dtype=torch.float64, device=dev)
+        w, e, _ = time_plan(plan, X, X, C, steps, warmup, stream, torch)
+        plan.verify(stream=stream)
+        out[key] = {"k_split": info.k_split, "tasks": info.tasks, "ms_per_step": round(w, 4),
+                    "value": round(info.useful_flops / (w * 1e-3) / 1e12, 3), "unit": "TFLOP/s"}
+        out["useful_gflop"] = round(info.useful_flops / 1e9, 3)
+        if ref is None:
+            ref = C.clone()
+        else:
+            out[key]["rel_diff_vs_fused"] = float(torch.linalg.vector_norm(C - ref) /
+                                                  torch.linalg.vector_norm(ref))
+        plan.close()
+    out["speedup"] = round(out["fused"]["ms_per_step"] / out["k_split_auto"]["ms_per_step"], 3)
+    return out
+
+
 def precision_section(torch, bsm, dev, stream, steps=5, warmup=2):
     """Config 4: the three forms on N = 32768 with per-block scaled values; every form's relative
     Frobenius error over all C blocks against the oracle's full product."""
@@ -669,6 +739,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-product batch section")
     ap.add_argument("--no-latency", action="store_true", help="skip the N=1024 latency section")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the block-rank-sparse section")
+    ap.add_argument("--no-contraction", action="store_true", help="skip the tensor-contraction section")
+    ap.add_argument("--no-gram", action="store_true", help="skip the tall Gram-product section")
     ap.add_argument("--no-operands", action="store_true",
                     help="skip the transposed-B and complex runs of the headline workload")
     ap.add_argument("--ab-reps", type=int, default=30)
@@ -764,6 +836,12 @@ def main():
         result["uniform_1024"] = latency_section(torch, bsm, dev, stream)
     if not args.no_lowrank:
         result["block_rank_8192"] = lowrank_section(torch, bsm, dev, stream)
+        torch.cuda.empty_cache()
+    if not args.no_contraction:
+        result["ladder_contraction"] = contraction_section(torch, bsm, dev, stream)
+        torch.cuda.empty_cache()
+    if not args.no_gram:
+        result["gram_65536x2048"] = gram_section(torch, bsm, dev, stream)
         torch.cuda.empty_cache()
     if not args.no_batch:
         result["batch64"] = batch_section(torch, bsm, dev, stream)
