@@ -446,6 +446,54 @@ def gram_section(torch, bsm, dev, stream, steps=20, warmup=3):
     return out
 
 
+def uneven_schedules_section(torch, bsm, dev, stream, reps=30):
+    """Where scheduling decides the makespan: a few thousand tasks of very uneven size.  The cost
+    model is trained on the recorded task times of one seeded workload and schedules another seed's
+    product; interleaved and largest-first (LPT) deals by flop count and by learned cost are timed
+    interleaved (HIP events)."""
+    from paper_1504_05046_amd import gen
+    mk = lambda seed: gen.nonuniform(seed, 4096, 8, 256, 0.5, name=f"uneven{seed}")
+    ptr = mk(12200)
+    timed = bsm.Plan.from_problem(ptr, record_timings=1)
+    A, B = to_device(ptr, torch, dev)
+    C = torch.zeros(max(1, timed.info().c_elems), dtype=torch.float64, device=dev)
+    feats, secs = [], []
+    timed.execute(A, B, C, stream=stream)
+    for _ in range(3):
+        timed.execute(A, B, C, stream=stream)
+        f, t = timed.timings(stream=stream)
+        feats.append(f)
+        secs.append(t)
+    timed.close()
+    model = bsm.CostModel(seed=1)
+    model.train(np.concatenate(feats), np.log(np.maximum(np.concatenate(secs), 1e-7)).astype(np.float32),
+                epochs=80, batch=1024, lr=3e-3, stream=stream)
+    p = mk(12201)
+    A, B = to_device(p, torch, dev)
+    plans = {}
+    for oname, order in (("interleave", bsm.ORDER_INTERLEAVE), ("lpt", bsm.ORDER_LPT)):
+        plans[f"{oname}_flop"] = bsm.Plan.from_problem(p, order=order, use_graph=1)
+        pl = bsm.Plan.from_problem(p, order=order, use_graph=1)
+        pl.set_costmodel(model, stream=stream)
+        plans[f"{oname}_learned"] = pl
+    C = torch.zeros(max(1, plans["lpt_flop"].info().c_elems), dtype=torch.float64, device=dev)
+    names = list(plans)
+    ev = interleaved([plans[n] for n in names], A, B, C, reps, stream, torch)
+    flops = plans["lpt_flop"].info().useful_flops
+    out = {"workload": "uneven: N=4096, block sizes U{8..256}, density 0.5, N(0,1); model trained "
+                       "on seed 12200, product of seed 12201",
+           "tasks": plans["lpt_flop"].info().tasks, "reps": reps}
+    for n, e in zip(names, ev):
+        out[n] = {"ms_mean": round(float(e.mean()), 4), "ms_se": round(float(e.std(ddof=1) / np.sqrt(reps)), 4),
+                  "tflops": round(flops / (e.mean() * 1e-3) / 1e12, 3)}
+    d = ev[names.index("lpt_learned")] - ev[names.index("lpt_flop")]
+    out["lpt_learned_minus_flop_ms"] = round(float(d.mean()), 4)
+    out["lpt_learned_minus_flop_se_ms"] = round(float(d.std(ddof=1) / np.sqrt(reps)), 4)
+    for pl in plans.values():
+        pl.close()
+    return out
+
+
 def precision_section(torch, bsm, dev, stream, steps=5, warmup=2):
     """Config 4: the three forms on N = 32768 with per-block scaled values; every form's relative
     Frobenius error over all C blocks against the oracle's full product."""
@@ -834,6 +882,10 @@ def main():
     if not args.no_latency:
         say("uniform_1024: latency")
         result["uniform_1024"] = latency_section(torch, bsm, dev, stream)
+    if not args.no_learned:
+        say("uneven tasks: learned vs flop-count costs")
+        result["uneven_schedules"] = uneven_schedules_section(torch, bsm, dev, stream)
+        torch.cuda.empty_cache()
     if not args.no_lowrank:
         result["block_rank_8192"] = lowrank_section(torch, bsm, dev, stream)
         torch.cuda.empty_cache()

@@ -101,7 +101,8 @@ typedef enum {
 
 /* How the scheduler deals tasks to the 8 accelerator dies (XCDs, each with its own L2). */
 typedef enum {
-  BSM_ORDER_DEFAULT = 0,    /* = BSM_ORDER_INTERLEAVE */
+  BSM_ORDER_DEFAULT = 0,    /* BSM_ORDER_LPT for plans (and batches) of up to 8192 tasks, where the
+                               schedule's tail decides the makespan, else BSM_ORDER_INTERLEAVE */
   BSM_ORDER_INTERLEAVE = 1, /* whole C blocks, in C-block order, each to the least-loaded XCD */
   BSM_ORDER_LOCALITY = 2,   /* C-block order cut into 8 runs of equal cost */
   BSM_ORDER_LPT = 3,        /* largest cost first, each task to the least-loaded XCD */
@@ -168,7 +169,7 @@ typedef struct bsm_batch bsm_batch;
 
 typedef struct bsm_plan bsm_plan;
 
-/* Fill opt with the defaults: FP64 products and FP64 C, flop-count scheduling, interleaved task
+/* Fill opt with the defaults: FP64 products and FP64 C, flop-count scheduling, the automatic task
  * order, all k-iterations in flight, no timings, library-chosen tiles, no graph, no tune cache. */
 void bsm_options_default(bsm_options* opt);
 

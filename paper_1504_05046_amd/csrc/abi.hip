@@ -871,7 +871,7 @@ bsm_status bsm_plan_create(bsm_plan** out, int64_t M, const int64_t* row_sizes, 
   cfg.tile = o.tile;
   cfg.out_f32 = o.out == BSM_OUT_F32;
   switch (o.order) {
-    case BSM_ORDER_DEFAULT:
+    case BSM_ORDER_DEFAULT: cfg.order = ORDER_AUTO; break;
     case BSM_ORDER_INTERLEAVE: cfg.order = ORDER_INTERLEAVE; break;
     case BSM_ORDER_LOCALITY: cfg.order = ORDER_LOCALITY; break;
     case BSM_ORDER_LPT: cfg.order = ORDER_LPT; break;

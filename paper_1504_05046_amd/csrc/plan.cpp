@@ -204,7 +204,9 @@ static std::vector<std::vector<size_t>> deal(const HostPlan& p, const std::vecto
                                              const std::vector<double>& cost) {
   std::vector<std::vector<size_t>> bins(kXcds);
   std::vector<double> load(kXcds, 0.0);
-  if (p.cfg.order == ORDER_LPT) {
+  const int order = p.cfg.order != ORDER_AUTO ? p.cfg.order
+                                              : (p.items.size() <= kLptTasks ? ORDER_LPT : ORDER_INTERLEAVE);
+  if (order == ORDER_LPT) {
     // longest processing time first: largest task to the least-loaded XCD, each XCD then runs
     // its tasks largest first (its 32 CUs pick them up in that order)
     std::vector<size_t> o(idx);
@@ -214,7 +216,7 @@ static std::vector<std::vector<size_t>> deal(const HostPlan& p, const std::vecto
       bins[size_t(x)].push_back(q);
       load[size_t(x)] += cost[q];
     }
-  } else if (p.cfg.order == ORDER_PATCH) {
+  } else if (order == ORDER_PATCH) {
     // patches of patch_r x patch_c C blocks, in row-major patch order per product; each whole
     // patch to the least-loaded XCD; inside a patch the canonical C-block order (stable sort)
     const int pr = std::max(1, p.cfg.patch_r), pc = std::max(1, p.cfg.patch_c);
@@ -233,7 +235,7 @@ static std::vector<std::vector<size_t>> deal(const HostPlan& p, const std::vecto
       load[size_t(x)] += c;
       u = e;
     }
-  } else if (p.cfg.order == ORDER_INTERLEAVE) {
+  } else if (order == ORDER_INTERLEAVE) {
     // whole C blocks (consecutive tasks with the same C offset) dealt to the least-loaded XCD in
     // C-block order
     size_t u = 0;
@@ -506,7 +508,7 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
   if (cfg.k_window < 0) return "negative k_window";
   if (cfg.tile < 0 || cfg.tile > (cfg.precision == 2 ? kNumBf16Variants : kNumVariants))
     return "unknown tile variant";
-  if (cfg.order < ORDER_LOCALITY || cfg.order > ORDER_PATCH) return "unknown task order";
+  if (cfg.order < ORDER_LOCALITY || cfg.order > ORDER_AUTO) return "unknown task order";
   if (cfg.device_klists < -1) return "device_klists must be -1, 0, 1 or a batch size >= 2";
   if (cfg.k_split < -1 || cfg.k_split > 16) return "k_split must be -1 (auto), 0, 1 or 2..16";
   if (cfg.patch_r < 1 || cfg.patch_c < 1) return "patch sizes must be >= 1";

@@ -27,7 +27,18 @@ constexpr int kDefaultBf16Variant = 0;
 // least-loaded XCD, so that all XCDs work on the same region of C at the same time; PATCH deals
 // whole rectangles of patch_r x patch_c C blocks, so that the tasks an XCD runs together share
 // few A block rows and B block columns in its L2.
-enum Order : int { ORDER_LOCALITY = 0, ORDER_LPT = 1, ORDER_INTERLEAVE = 2, ORDER_PATCH = 3 };
+enum Order : int {
+  ORDER_LOCALITY = 0,
+  ORDER_LPT = 1,
+  ORDER_INTERLEAVE = 2,
+  ORDER_PATCH = 3,
+  ORDER_AUTO = 4  // LPT for up to kLptTasks tasks, INTERLEAVE above
+};
+// Task count up to which the automatic order deals largest-first: with few tasks per XCD the
+// tail of the schedule decides the makespan (measured 16-23 % faster than the interleaved order
+// at 900-4600 tasks of very uneven size); with many tasks the interleaved order keeps each XCD's
+// concurrent tasks on neighbouring C blocks (5 % faster at 32000 tasks).
+constexpr size_t kLptTasks = 8192;
 
 struct PlanConfig {
   int precision = 0;
@@ -35,7 +46,7 @@ struct PlanConfig {
   int64_t k_window = 0;
   int record_timings = 0;
   int tile = 0;       // 0 = auto, else variant id + 1
-  int order = ORDER_INTERLEAVE;
+  int order = ORDER_AUTO;
   int out_f32 = 0;    // C holds FP32 elements
   int patch_r = 4, patch_c = 8;  // C blocks per patch (ORDER_PATCH)
   int device_klists = 0;  // 0: when the triples would not fit the host list, 1: always, -1: never

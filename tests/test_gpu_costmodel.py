@@ -166,3 +166,58 @@ def test_learned_model_beats_flop_count_model():
     tf, tl = np.array(times["flop"]), np.array(times["learned"])
     _say(f"[costmodel] makespan flop-count {tf.mean():.2f} +- {tf.std(ddof=1):.2f} ms, "
          f"learned {tl.mean():.2f} +- {tl.std(ddof=1):.2f} ms")
+
+
+def _wide(seed):
+    """Nonuniform blocks of very uneven size (U{4..512}, N=3072, density 0.6): few hundred tasks,
+    where the tail of the schedule decides the makespan and flop counts mispredict small tiles."""
+    return gen.nonuniform(seed, 3072, 4, 512, 0.6, name=f"wide{seed}")
+
+
+def test_learned_model_makespan_on_uneven_tasks_is_recorded():
+    """Trained on the recorded task times of one seeded workload, the network's costs drive the
+    largest-first (LPT) deal of another seed's tasks; the makespans of both cost models are
+    recorded with their noise.  Both schedules give the same bits, and the learned one is never
+    much slower.  (Measured so far: between 5 % faster and 0.3 % slower depending on the seeds,
+    so no gain is asserted.)"""
+    ptr = _wide(12100)
+    plan = bsm.Plan.from_problem(ptr, record_timings=1)
+    A = torch.from_numpy(ptr.a_data).to(DEV)
+    B = torch.from_numpy(ptr.b_data).to(DEV)
+    C = torch.zeros(plan.info().c_elems, dtype=torch.float64, device=DEV)
+    plan.execute(A, B, C)
+    torch.cuda.synchronize()
+    X, T = _harvest(plan, A, B, C, reps=3)
+    model = bsm.CostModel(seed=1)
+    model.train(X, np.log(np.maximum(T, 1e-7)).astype(np.float32), epochs=80, batch=1024, lr=3e-3)
+    p = _wide(12101)
+    A = torch.from_numpy(p.a_data).to(DEV)
+    B = torch.from_numpy(p.b_data).to(DEV)
+    plan_f = bsm.Plan.from_problem(p, order=bsm.ORDER_LPT, use_graph=1)
+    plan_l = bsm.Plan.from_problem(p, order=bsm.ORDER_LPT, use_graph=1)
+    plan_l.set_costmodel(model)
+    C = torch.zeros(plan_f.info().c_elems, dtype=torch.float64, device=DEV)
+    for pl in (plan_f, plan_l, plan_f, plan_l):
+        pl.execute(A, B, C)
+    torch.cuda.synchronize()
+    times = {"flop": [], "learned": []}
+    outs = {}
+    for _ in range(30):
+        for name, pl in (("flop", plan_f), ("learned", plan_l)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pl.execute(A, B, C)
+            e1.record()
+            torch.cuda.synchronize()
+            times[name].append(e0.elapsed_time(e1))
+    for name, pl in (("flop", plan_f), ("learned", plan_l)):
+        pl.execute(A, B, C)
+        torch.cuda.synchronize()
+        outs[name] = C.cpu().numpy().copy()
+    assert np.array_equal(outs["flop"], outs["learned"])
+    tf, tl = np.array(times["flop"]), np.array(times["learned"])
+    se = float(np.std(tl - tf, ddof=1) / np.sqrt(tf.size))
+    _say(f"[costmodel] uneven tasks ({plan_f.info().tasks}), LPT deal: flop-count costs "
+         f"{tf.mean():.4f} ms, learned costs {tl.mean():.4f} ms (difference {tl.mean() - tf.mean():+.4f} "
+         f"+- {se:.4f} ms)")
+    assert tl.mean() < 1.05 * tf.mean()
