@@ -271,8 +271,51 @@ static bsm_status check_device(int* dev) {
 }
 
 // Device buffers of a plan other than its task list.
+// Every device buffer of a plan besides its task list (freed by release_buffers).
+static std::vector<void**> buffer_slots(bsm_plan* p) {
+  return {&p->d_opA, &p->d_opB,
+          reinterpret_cast<void**>(&p->d_split_a), reinterpret_cast<void**>(&p->d_split_b),
+          reinterpret_cast<void**>(&p->d_xpose_a), reinterpret_cast<void**>(&p->d_xpose_b),
+          reinterpret_cast<void**>(&p->d_partial), reinterpret_cast<void**>(&p->d_zA),
+          reinterpret_cast<void**>(&p->d_zB), reinterpret_cast<void**>(&p->d_zP),
+          reinterpret_cast<void**>(&p->d_zembed_a), reinterpret_cast<void**>(&p->d_zembed_b),
+          reinterpret_cast<void**>(&p->d_zc), reinterpret_cast<void**>(&p->d_splitP),
+          reinterpret_cast<void**>(&p->d_kprods), reinterpret_cast<void**>(&p->d_abits),
+          reinterpret_cast<void**>(&p->d_btbits), reinterpret_cast<void**>(&p->d_atab),
+          reinterpret_cast<void**>(&p->d_bttab), reinterpret_cast<void**>(&p->d_inner)};
+}
+
+// Frees every buffer of buffer_slots (after the device is idle) and clears the pointers.
+static bsm_status release_buffers(bsm_plan* p) {
+  bool any = false;
+  for (void** s : buffer_slots(p)) any = any || *s;
+  if (!any) return BSM_OK;
+  hipError_t e = hipDeviceSynchronize();
+  for (void** s : buffer_slots(p)) {
+    if (*s) (void)hipFree(*s);
+    *s = nullptr;
+  }
+  p->h_kprods.clear();
+  p->dk = DevKlists{};
+  return e == hipSuccess ? BSM_OK : hip_fail(e, "hipDeviceSynchronize");
+}
+
+static bsm_status prepare_buffers(bsm_plan* p);
+
+// Device buffers of a plan other than its task list; a failure part-way releases what was
+// allocated, so that a later call starts again from nothing.
 static bsm_status prepare(bsm_plan* p) {
   if (p->ready) return BSM_OK;
+  const bsm_status st = prepare_buffers(p);
+  if (st != BSM_OK) {
+    const std::string msg = g_error;
+    (void)release_buffers(p);
+    return fail(st, msg);
+  }
+  return BSM_OK;
+}
+
+static bsm_status prepare_buffers(bsm_plan* p) {
   int dev;
   bsm_status st = check_device(&dev);
   if (st != BSM_OK) return st;
@@ -1159,18 +1202,9 @@ bsm_status bsm_plan_destroy(bsm_plan* plan) {
     if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize");
     plan->gc.release();
     plan->ts.release();
-    for (void* ptr : {plan->d_opA, plan->d_opB, static_cast<void*>(plan->d_split_a),
-                      static_cast<void*>(plan->d_split_b), static_cast<void*>(plan->d_xpose_a),
-                      static_cast<void*>(plan->d_xpose_b), static_cast<void*>(plan->d_partial),
-                      static_cast<void*>(plan->d_zA), static_cast<void*>(plan->d_zB),
-                      static_cast<void*>(plan->d_zP), static_cast<void*>(plan->d_zembed_a),
-                      static_cast<void*>(plan->d_zembed_b), static_cast<void*>(plan->d_zc),
-                      static_cast<void*>(plan->d_splitP), static_cast<void*>(plan->d_kprods),
-                      static_cast<void*>(plan->d_abits), static_cast<void*>(plan->d_btbits),
-                      static_cast<void*>(plan->d_atab), static_cast<void*>(plan->d_bttab),
-                      static_cast<void*>(plan->d_inner)})
-      if (ptr) (void)hipFree(ptr);
   }
+  const bsm_status sr = release_buffers(plan);
+  if (st == BSM_OK) st = sr;
   delete plan;
   return st;
 }

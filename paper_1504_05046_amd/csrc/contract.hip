@@ -166,14 +166,17 @@ struct bsm_tc_plan {
 
 static void tc_free(bsm_tc_plan* p) {
   if (p->mat) bsm_plan_destroy(p->mat);
-  if (p->ready) {
+  // also the buffers of a preparation that failed part-way
+  std::vector<void*> bufs = {p->d_A, p->d_B, p->d_C};
+  for (Pass* x : {&p->xa, &p->xb, &p->xc})
+    for (void* ptr : {static_cast<void*>(x->d_copy), static_cast<void*>(x->d_xpose),
+                      static_cast<void*>(x->d_perm)})
+      bufs.push_back(ptr);
+  bool any = false;
+  for (void* ptr : bufs) any = any || ptr;
+  if (any) {
     (void)hipDeviceSynchronize();
-    for (Pass* x : {&p->xa, &p->xb, &p->xc})
-      for (void* ptr : {static_cast<void*>(x->d_copy), static_cast<void*>(x->d_xpose),
-                        static_cast<void*>(x->d_perm)})
-        if (ptr) (void)hipFree(ptr);
-    for (void* ptr : {static_cast<void*>(p->d_A), static_cast<void*>(p->d_B),
-                      static_cast<void*>(p->d_C)})
+    for (void* ptr : bufs)
       if (ptr) (void)hipFree(ptr);
   }
   delete p;
@@ -513,6 +516,22 @@ bsm_status bsm_tc_plan_c_shape(const bsm_tc_plan* plan, uint64_t* c_bits) {
   return BSM_OK;
 }
 
+// Device tables and matricized buffers at the first execute.
+static bsm_status tc_prepare(bsm_tc_plan* plan) {
+  const bsm_tc_info& in = plan->info;
+  bsm_status st;
+  for (Pass* x : {&plan->xa, &plan->xb, &plan->xc})
+    if ((st = upload_pass(*x)) != BSM_OK) return st;
+  if (in.permute_a && plan->a_mat > 0)
+    TC_HIP(hipMalloc(&plan->d_A, size_t(plan->a_mat) * 8), "hipMalloc(matricized A)");
+  if (in.permute_b && plan->b_mat > 0)
+    TC_HIP(hipMalloc(&plan->d_B, size_t(plan->b_mat) * 8), "hipMalloc(matricized B)");
+  if (in.permute_c && plan->c_mat > 0)
+    TC_HIP(hipMalloc(&plan->d_C, size_t(plan->c_mat) * 8), "hipMalloc(matricized C)");
+  plan->ready = true;
+  return BSM_OK;
+}
+
 bsm_status bsm_tc_execute(bsm_tc_plan* plan, double alpha, const double* dA, const double* dB,
                           void* dC, int accumulate, void* stream) {
   if (!plan) return set_error(BSM_E_INVALID, "plan is null");
@@ -523,16 +542,23 @@ bsm_status bsm_tc_execute(bsm_tc_plan* plan, double alpha, const double* dA, con
   if (in.c_elems == 0) return BSM_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!plan->ready) {
-    bsm_status st;
-    for (Pass* x : {&plan->xa, &plan->xb, &plan->xc})
-      if ((st = upload_pass(*x)) != BSM_OK) return st;
-    if (in.permute_a && plan->a_mat > 0)
-      TC_HIP(hipMalloc(&plan->d_A, size_t(plan->a_mat) * 8), "hipMalloc(matricized A)");
-    if (in.permute_b && plan->b_mat > 0)
-      TC_HIP(hipMalloc(&plan->d_B, size_t(plan->b_mat) * 8), "hipMalloc(matricized B)");
-    if (in.permute_c && plan->c_mat > 0)
-      TC_HIP(hipMalloc(&plan->d_C, size_t(plan->c_mat) * 8), "hipMalloc(matricized C)");
-    plan->ready = true;
+    bsm_status st = tc_prepare(plan);
+    if (st != BSM_OK) {
+      // release what was allocated, so that a later call starts again from nothing
+      std::vector<void**> slots = {reinterpret_cast<void**>(&plan->d_A),
+                                   reinterpret_cast<void**>(&plan->d_B),
+                                   reinterpret_cast<void**>(&plan->d_C)};
+      for (Pass* x : {&plan->xa, &plan->xb, &plan->xc}) {
+        slots.push_back(reinterpret_cast<void**>(&x->d_copy));
+        slots.push_back(reinterpret_cast<void**>(&x->d_xpose));
+        slots.push_back(reinterpret_cast<void**>(&x->d_perm));
+      }
+      for (void** sl : slots) {
+        if (*sl) (void)hipFree(*sl);
+        *sl = nullptr;
+      }
+      return st;
+    }
   }
   const double* xa = dA;
   const double* xb = dB;

@@ -59,8 +59,26 @@ static bool bit_of(const uint64_t* bits, int64_t ncols, int64_t i, int64_t j) {
   return (bits[i * words_of(ncols) + j / 64] >> (j % 64)) & 1;
 }
 
+static bsm_status lr_prepare_buffers(bsm_lr_plan* p);
+
+// Device buffers at the first execute; a failure part-way releases what was allocated.
 static bsm_status lr_prepare(bsm_lr_plan* p) {
   if (p->ready) return BSM_OK;
+  const bsm_status st = lr_prepare_buffers(p);
+  if (st != BSM_OK) {
+    void** slots[] = {reinterpret_cast<void**>(&p->d_gather), reinterpret_cast<void**>(&p->d_vt),
+                      reinterpret_cast<void**>(&p->d_restack), reinterpret_cast<void**>(&p->d_W),
+                      reinterpret_cast<void**>(&p->d_A2), reinterpret_cast<void**>(&p->d_V1),
+                      reinterpret_cast<void**>(&p->d_B2)};
+    for (void** s : slots) {
+      if (*s) (void)hipFree(*s);
+      *s = nullptr;
+    }
+  }
+  return st;
+}
+
+static bsm_status lr_prepare_buffers(bsm_lr_plan* p) {
   auto up = [&](auto** dst, const auto& v) -> bsm_status {
     const size_t bytes = v.size() * sizeof(v[0]);
     if (!bytes) return BSM_OK;
@@ -102,12 +120,16 @@ static bool blocks_inside(const std::vector<XposeBlock>& t, int64_t src_n, int64
 static void lr_free(bsm_lr_plan* p) {
   if (p->stage1) bsm_plan_destroy(p->stage1);
   if (p->main) bsm_plan_destroy(p->main);
-  if (p->ready) {
+  // also the buffers of a preparation that failed part-way
+  const std::initializer_list<void*> bufs = {
+      static_cast<void*>(p->d_gather), static_cast<void*>(p->d_vt), static_cast<void*>(p->d_restack),
+      static_cast<void*>(p->d_W), static_cast<void*>(p->d_A2), static_cast<void*>(p->d_V1),
+      static_cast<void*>(p->d_B2)};
+  bool any = false;
+  for (void* ptr : bufs) any = any || ptr;
+  if (any) {
     (void)hipDeviceSynchronize();
-    for (void* ptr : {static_cast<void*>(p->d_gather), static_cast<void*>(p->d_vt),
-                      static_cast<void*>(p->d_restack), static_cast<void*>(p->d_W),
-                      static_cast<void*>(p->d_A2), static_cast<void*>(p->d_V1),
-                      static_cast<void*>(p->d_B2)})
+    for (void* ptr : bufs)
       if (ptr) (void)hipFree(ptr);
   }
   delete p;
