@@ -3,7 +3,7 @@
  * MI355X (gfx950).  C ABI.
  *
  * The operation (Calvin & Valeev, "Task-Based Algorithm for Matrix Multiplication", SC15):
- * SUMMA computes C = A B as a series of rank-k updates C_ij <- A_ik B_kj + C_ij (Sec. 2.1;
+ * SUMMA builds C = A B up from one rank-k update C_ij <- A_ik B_kj + C_ij per k (Sec. 2.1;
  * Alg. 1's local step C <- alpha A(*,k) B(k,*) + C).  The task-based form over-decomposes the
  * matrices into arbitrarily sized blocks (Sec. 3.2), splits every update into a block product and
  * a reduction into C, and lets many k-iterations run at once (multiple issue, Eq. 1).  This
