@@ -47,10 +47,30 @@ __device__ inline void split3(double a, uint16_t& s0, uint16_t& s1, uint16_t& s2
 
 static_assert(kSliceK == 32, "panel indexing below assumes 32-wide k-panels");
 
-// One workgroup per operand block: writes the block's three slices into the planes (plane p at
-// dst + p * plane), inner size padded with zeros to a multiple of 32, in 32-wide k-panels (element
-// (r, k) of a block of R rows at (k / 32) * 32 R + 32 r + k % 32); B blocks are transposed through
-// LDS in 32 x 64 tiles so that both the reads and the writes are coalesced.
+// Four consecutive slice values of one plane as one 8-byte word (the lowest k first).
+__device__ inline uint64_t pack4(const uint16_t (&x)[4]) {
+  return uint64_t(x[0]) | (uint64_t(x[1]) << 16) | (uint64_t(x[2]) << 32) | (uint64_t(x[3]) << 48);
+}
+
+// Splits four values and stores the three slices' four bf16 each at element offset o (a multiple
+// of 4, so every store is one aligned 8-byte word).
+__device__ inline void split_store4(const double (&v)[4], uint16_t* d0, uint16_t* d1, uint16_t* d2,
+                                    int64_t o) {
+  uint16_t x0[4], x1[4], x2[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) split3(v[j], x0[j], x1[j], x2[j]);
+  *reinterpret_cast<uint64_t*>(d0 + o) = pack4(x0);
+  *reinterpret_cast<uint64_t*>(d1 + o) = pack4(x1);
+  *reinterpret_cast<uint64_t*>(d2 + o) = pack4(x2);
+}
+
+// One workgroup per table entry: an operand block, or a piece of one (the planner gives every
+// 32-wide k-panel its own entry), written as three slices into the planes (plane p at
+// dst + p * plane) with the inner size padded with zeros to a multiple of 32, in 32-wide k-panels
+// (element (r, k) of a block of R rows at (k / 32) * 32 R + 32 r + k % 32).  Each thread handles
+// four consecutive k of one row (one 8-byte store per plane; entry offsets in the planes are
+// multiples of 32 elements).  B blocks are transposed through LDS in 32 x 64 tiles so that both
+// the reads and the writes are coalesced.
 __global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict__ blocks,
                                                     const double* __restrict__ src,
                                                     uint16_t* __restrict__ dst, int64_t plane) {
@@ -62,19 +82,17 @@ __global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict
   uint16_t* d1 = d0 + plane;
   uint16_t* d2 = d1 + plane;
   if (!b.transpose) {
-    // panel by panel; inside a panel element e is row e / 32, k e % 32 of the panel
-    const int panel = b.rows * kSliceK;
-    for (int k0 = 0; k0 < ks32; k0 += kSliceK) {
-      const int64_t pbase = int64_t(k0) * b.rows;
-      for (int e = threadIdx.x; e < panel; e += blockDim.x) {
-        const int r = e >> 5, k = k0 + (e & (kSliceK - 1));
-        const double v = k < b.ks ? sb[int64_t(r) * b.ld_src + k] : 0.0;
-        uint16_t x0, x1, x2;
-        split3(v, x0, x1, x2);
-        d0[pbase + e] = x0;
-        d1[pbase + e] = x1;
-        d2[pbase + e] = x2;
-      }
+    // quad u: panel u / (8 rows), row (u mod 8 rows) / 8, k-quad u mod 8 of the panel; the
+    // destination of a quad is 4 u (panels are consecutive, rows 32 elements apart in a panel)
+    const int quads = b.rows * (ks32 >> 2);
+    for (int u = threadIdx.x; u < quads; u += blockDim.x) {
+      const int pr = u / (b.rows * 8), e = u - pr * (b.rows * 8);
+      const int r = e >> 3, k = pr * kSliceK + ((e & 7) << 2);
+      const double* row = sb + int64_t(r) * b.ld_src;
+      double v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = k + j < b.ks ? row[k + j] : 0.0;
+      split_store4(v, d0, d1, d2, int64_t(u) << 2);
     }
     return;
   }
@@ -87,16 +105,15 @@ __global__ __launch_bounds__(256) void split_bf16x3(const SplitBlock* __restrict
         tile[kk][cc] = (k < b.ks && c < b.rows) ? sb[int64_t(k) * b.ld_src + c] : 0.0;
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
-        const int cc = e >> 5, kk = e & 31;
+      // 64 columns x 8 k-quads: thread f takes column f / 8, quad f mod 8
+      for (int f = threadIdx.x; f < 64 * 8; f += blockDim.x) {
+        const int cc = f >> 3, q = (f & 7) << 2;
         const int c = c0 + cc;
         if (c < b.rows) {
-          uint16_t x0, x1, x2;
-          split3(tile[kk][cc], x0, x1, x2);
-          const int64_t o = int64_t(k0) * b.rows + int64_t(c) * kSliceK + kk;
-          d0[o] = x0;
-          d1[o] = x1;
-          d2[o] = x2;
+          double v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = tile[q + j][cc];
+          split_store4(v, d0, d1, d2, int64_t(k0) * b.rows + int64_t(c) * kSliceK + q);
         }
       }
       __syncthreads();

@@ -200,6 +200,17 @@ static void batch_device_klists(HostPlan& p) {
 
 // Deals the tasks of one segment (indices `idx` into the canonically ordered task list) to the
 // XCDs; returns one list of task indices per XCD.
+// Split-pass table entries of one operand block (written at plane offset dst, rows x pad_k(ks)):
+// one piece per 32-wide k-panel, so that every workgroup of the pass moves at most 256 x 32
+// elements whatever the block size.  A piece of a block stored rows x ks (transpose = 0) starts
+// 32 columns further on; one of a block stored ks x rows (transpose = 1) 32 source rows further.
+static void push_split(std::vector<SplitBlock>& out, int64_t src, int64_t dst, int64_t rows,
+                       int64_t ks, int64_t ld, int transpose) {
+  for (int64_t k0 = 0; k0 < ks; k0 += kSliceK)
+    out.push_back(SplitBlock{src + (transpose ? k0 * ld : k0), dst + k0 * rows, int32_t(rows),
+                             int32_t(std::min<int64_t>(kSliceK, ks - k0)), int32_t(ld), transpose});
+}
+
 static std::vector<std::vector<size_t>> deal(const HostPlan& p, const std::vector<size_t>& idx,
                                              const std::vector<double>& cost) {
   std::vector<std::vector<size_t>> bins(kXcds);
@@ -575,11 +586,10 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
         a_off32[size_t(i * K + k)] = pos;
         // stored as r_i x s_k, or (transposed) as s_k x r_i
         if (ta)
-          p.split_a.push_back(SplitBlock{st_a[size_t(k * M + i)], pos, int32_t(p.rows[size_t(i)]),
-                                         int32_t(p.inner[size_t(k)]), int32_t(p.rows[size_t(i)]), 1});
+          push_split(p.split_a, st_a[size_t(k * M + i)], pos, p.rows[size_t(i)], p.inner[size_t(k)],
+                     p.rows[size_t(i)], 1);
         else
-          p.split_a.push_back(SplitBlock{o, pos, int32_t(p.rows[size_t(i)]), int32_t(p.inner[size_t(k)]),
-                                         int32_t(p.inner[size_t(k)]), 0});
+          push_split(p.split_a, o, pos, p.rows[size_t(i)], p.inner[size_t(k)], p.inner[size_t(k)], 0);
         pos += p.rows[size_t(i)] * pad_k(p.inner[size_t(k)]);
       }
     p.a_elems32 = pos;
@@ -591,11 +601,10 @@ std::string build_plan(HostPlan& p, int64_t M, const int64_t* rows, int64_t K,
         b_off32[size_t(k * N + j)] = pos;
         // stored as s_k x t_j (written transposed), or (transposed) as t_j x s_k
         if (tb)
-          p.split_b.push_back(SplitBlock{st_b[size_t(j * K + k)], pos, int32_t(p.cols[size_t(j)]),
-                                         int32_t(p.inner[size_t(k)]), int32_t(p.inner[size_t(k)]), 0});
+          push_split(p.split_b, st_b[size_t(j * K + k)], pos, p.cols[size_t(j)], p.inner[size_t(k)],
+                     p.inner[size_t(k)], 0);
         else
-          p.split_b.push_back(SplitBlock{o, pos, int32_t(p.cols[size_t(j)]), int32_t(p.inner[size_t(k)]),
-                                         int32_t(p.cols[size_t(j)]), 1});
+          push_split(p.split_b, o, pos, p.cols[size_t(j)], p.inner[size_t(k)], p.cols[size_t(j)], 1);
         pos += p.cols[size_t(j)] * pad_k(p.inner[size_t(k)]);
       }
     p.b_elems32 = pos;

@@ -41,8 +41,9 @@ constexpr int kXcds = 8;                       // MI355X: 8 accelerator dies, ea
 constexpr int kSliceK = 32;
 BSM_HD inline int64_t pad_k(int64_t ks) { return (ks + kSliceK - 1) / kSliceK * kSliceK; }
 
-// One block of an operand as the split pass sees it: src_off in the packed FP64 tiles, dst_off in
-// a slice plane, `rows` output rows (A rows, or B columns when transposed), inner size ks.
+// One piece of an operand block as the split pass sees it (the planner cuts each block into its
+// 32-wide k-panels): src_off in the packed FP64 tiles, dst_off in a slice plane, `rows` output
+// rows (A rows, or B columns when transposed), inner size ks of the piece.
 struct SplitBlock {
   int64_t src_off;
   int64_t dst_off;
