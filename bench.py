@@ -201,12 +201,55 @@ def cpu_baseline(p, got_c, c_off, target_s: float, seed: int = 12345):
         g = got_c[o:o + blk.size].reshape(blk.shape)
         num += float(np.sum((g - blk) ** 2))
         den += float(np.sum(blk ** 2))
+    # the same oracle on one thread: a prefix of the sample (~3 s), and the whole uniform_1024
+    # product (single-thread and all-thread times)
+    from paper_1504_05046_amd import gen
+    threads = oracle.threads()
+    budget1 = fl / dt / threads * 3.0
+    sel1, fl1 = [], 0.0
+    for ij in sel:
+        if fl1 >= budget1 and sel1:
+            break
+        sel1.append(ij)
+        fl1 += flops_of(ij)
+    u = gen.uniform_1024()
+    uargs = (u.rows, u.inner, u.cols, u.a_bits(), u.b_bits(), u.a_data, u.b_data)
+    t0 = time.perf_counter()
+    oracle.bsmm(*uargs)
+    u_all = time.perf_counter() - t0
+    prev = oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.bsmm_blocks(*args, sel1)
+        dt1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.bsmm(*uargs)
+        u_one = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(prev)
     return {
-        "value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+        "value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
         "sample": f"{len(sel)} random present C blocks of {len(present)} ({fl / 1e9:.1f} GFLOP useful, "
                   f"{dt:.1f} s), plain FP64 C oracle, OpenMP over C blocks",
-        "seconds": dt,
+        "seconds": dt, "cpu_model": cpu_model(),
+        "single_thread": {
+            "value": fl1 / dt1 / 1e12, "unit": "TFLOP/s",
+            "sample": f"the first {len(sel1)} blocks of that sample ({fl1 / 1e9:.1f} GFLOP, {dt1:.1f} s)"},
+        "uniform_1024_full_product_ms": {"threads": threads, "all_threads": round(u_all * 1e3, 1),
+                                          "single_thread": round(u_one * 1e3, 1)},
     }, (num / den) ** 0.5 if den > 0 else 0.0
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first processor entry of /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # ---- sections ------------------------------------------------------------------------------------

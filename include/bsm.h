@@ -37,8 +37,8 @@
  * Streams   `stream` is a hipStream_t (NULL = the default stream); work is queued on it and the
  *           call returns without waiting.  A plan runs on one stream at a time.  A call that must
  *           replace a device table a queued launch may still read (new task order after
- *           bsm_plan_set_costs, new operand pointers of a batch) first waits for the work queued
- *           on `stream`.
+ *           bsm_plan_set_costs, new operand pointers of a batch or of a plan with k_split > 1)
+ *           first waits for the work queued on `stream`.
  * Errors    every call returns a bsm_status; nothing is thrown across the ABI.  The text of the
  *           last failure on the calling thread is available from bsm_last_error().  Device faults
  *           appear as BSM_E_HIP at the next call that synchronises.  Every launch counts, per

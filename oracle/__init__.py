@@ -41,6 +41,8 @@ def lib() -> ctypes.CDLL:
             build_library()
         L = ctypes.CDLL(LIB_PATH)
         L.oracle_threads.restype = ctypes.c_int
+        L.oracle_set_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_words.restype = _i64
         L.oracle_words.argtypes = [_i64]
         L.oracle_shape_product.argtypes = [_i64, _i64, _i64, _p, _p, _p]
@@ -84,6 +86,11 @@ def _c64(a, dtype) -> np.ndarray:
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> int:
+    """Sets the OpenMP threads of later oracle calls (timing only); returns the previous count."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 # ---- block-sparse product ---------------------------------------------------------------------

@@ -72,6 +72,18 @@ int oracle_threads(void) {
 #endif
 }
 
+/* Sets the threads of the OpenMP loops below (n >= 1) for later calls from the calling thread;
+ * returns the previous count.  Timing only: the results do not depend on it. */
+int oracle_set_threads(int n) {
+  const int prev = oracle_threads();
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+  return prev;
+}
+
 /* Chat = boolean product of the two shapes, by the definition: a triple loop over (i, j, k). */
 int oracle_shape_product(int64_t M, int64_t K, int64_t N, const uint64_t* a_bits,
                          const uint64_t* b_bits, uint64_t* c_bits) {
