@@ -5,8 +5,8 @@
  * The operation (Calvin & Valeev, "Task-Based Algorithm for Matrix Multiplication", SC15):
  * SUMMA builds C = A B up from one rank-k update C_ij <- A_ik B_kj + C_ij per k (Sec. 2.1;
  * Alg. 1's local step C <- alpha A(*,k) B(k,*) + C).  The task-based form over-decomposes the
- * matrices into arbitrarily sized blocks (Sec. 3.2), splits every update into a block product and
- * a reduction into C, and lets many k-iterations run at once (multiple issue, Eq. 1).  This
+ * matrices into blocks of freely chosen sizes (Sec. 3.2), splits every update into a block
+ * product and a reduction into C, and lets many k-iterations run at once (multiple issue, Eq. 1).  This
  * library executes that local multiply for block-sparse operands: for every (i, j) in the
  * C-shape  Chat_ij = OR_k (Ahat_ik AND Bhat_kj)
  *     C_ij = alpha * sum_{k : Ahat_ik and Bhat_kj} A_ik B_kj   (+ C_ij when accumulating).
@@ -173,7 +173,7 @@ typedef struct bsm_plan bsm_plan;
  * order, all k-iterations in flight, no timings, library-chosen tiles, no graph, no tune cache. */
 void bsm_options_default(bsm_options* opt);
 
-/* Build a plan for C = alpha A B (+ C) over problem-given, arbitrarily sized blocks (Sec. 3.2's
+/* Build a plan for C = alpha A B (+ C) over problem-given blocks of any size (Sec. 3.2's
  * over-decomposition; Fig. 3 splits one iteration into tasks, each producing one piece of the
  * process's part of C).  Host-only work: validates the tilings and shapes, forms the C-shape (the
  * boolean product of the two shapes), the packed offsets, the task list (each present C block,

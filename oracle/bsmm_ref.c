@@ -9,7 +9,7 @@
  * C^(k)_ij = A_ik B_kj and a reduction C_ij += C^(k)_ij, which changes only when the terms are
  * added, not which terms are added):
  *
- *   tilings r[0..M), s[0..K), t[0..N) (block sizes, Sec. 3.2 "arbitrarily sized blocks");
+ *   tilings r[0..M), s[0..K), t[0..N) (block sizes of any value, Sec. 3.2);
  *   block-shape masks Ahat (M x K) and Bhat (K x N);
  *   C-shape   Chat_ij = OR_k (Ahat_ik AND Bhat_kj);
  *   values    C_ij = alpha * sum_{k : Ahat_ik and Bhat_kj} A_ik B_kj  (+ C_ij when accumulating),

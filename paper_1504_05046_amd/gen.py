@@ -5,8 +5,8 @@ described the way the library consumes it:
 
 * three tilings (vectors of block sizes): ``rows`` (M blocks of C and A), ``inner`` (K blocks
   shared by A's columns and B's rows) and ``cols`` (N blocks of C and B) -- the problem-given,
-  possibly nonuniform blocking of the matrix dimensions (paper Sec. 3.2, over-decomposition into
-  arbitrarily sized blocks);
+  possibly nonuniform blocking of the matrix dimensions (paper Sec. 3.2: the matrices are cut
+  into many more blocks than processes, of sizes the problem chooses);
 * two block-shape masks ``a_mask`` (M x K) and ``b_mask`` (K x N) saying which blocks are present
   (block sparsity, paper Sec. 1);
 * the present blocks' values, packed: blocks in row-major block order (i, then k), each block
