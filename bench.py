@@ -18,11 +18,22 @@ Beside it, in the same JSON line:
   batch64         64 independent products (N in {1024..8192}, sizes U{16..192}, density U[0.1,0.9])
                   in one graph launch: total useful TFLOP/s and sampled per-product error
   uniform_1024    N = 1024, 64 x 64 blocks, Bernoulli(0.5): latency of one graph replay
+  operands        the headline workload with B handed over transposed, and with complex FP64
+                  elements and B read as its adjoint
+  uneven_schedules  a product of ~2000 uneven tasks under the interleaved and LPT orders, each with
+                  flop-count and learned costs
+  block_rank_8192, ladder_contraction, gram_65536x2048
+                  block-rank-sparse A, a block-sparse tensor contraction, and the reduction
+                  variant (k_split) on a product with few C tiles
   roofline        the headline FP64 tile kernel against the FP64 MFMA peak
   cpu_baseline    the oracle on the host cores, on a sample of the headline workload's C blocks
 
-Prints ONE JSON line on stdout (progress goes to stderr).  --gpus above 1 is refused: this build
-measures one GPU.
+Workloads run on their own (--workload): decay_cloud_4000 (the distance-decay product, flop-count
+vs learned task order) and paper_dense_32768 (dense N = 32768, uniform blocks of 256 vs the
+paper's nonuniform blocking of the same mean).
+
+Prints ONE JSON line on stdout (progress goes to stderr).  --gpus above 1 is refused: the
+benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -816,13 +827,86 @@ def decay_main(args, torch, bsm):
     print(json.dumps(result), flush=True)
 
 
+def paper_dense_main(args, torch, bsm):
+    """The paper's dense square experiment on one GPU (Sec. 4.1): C = A B with every block present,
+    N = 32768, uniform blocks of 256 against the paper's nonuniform blocking of the same mean (one
+    row at a time to a randomly chosen block).  FP64, graph replay, n launches each (HIP events),
+    16 sampled C blocks of each against the oracle.  Context for the paper's uniform-versus-
+    nonuniform comparison, not a default bench line."""
+    import oracle
+    from paper_1504_05046_amd import gen
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n, reps = args.dense_n, args.ab_reps
+    out = {}
+    for label, nonuni in (("uniform_256", False), ("add_one_row_mean_256", True)):
+        say(f"paper_dense_{n}: generating {label}")
+        p = gen.paper_dense(8000 + int(nonuni), n, 256, nonuni)
+        plan = bsm.Plan.from_problem(p, use_graph=1)
+        info = plan.info()
+        A = torch.from_numpy(p.a_data).to(dev)
+        B = torch.from_numpy(p.b_data).to(dev)
+        C = torch.empty(info.c_elems, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            plan.execute(A, B, C, stream=stream)
+        torch.cuda.synchronize()
+        ev = []
+        for r in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            plan.execute(A, B, C, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            ev.append(e0.elapsed_time(e1))
+        plan.verify(stream=stream)
+        ev = np.array(ev)
+        say(f"paper_dense_{n}: {label}: {ev.mean():.1f} ms per product")
+        off = plan.c_offsets()
+        present = np.argwhere(off >= 0)
+        pick = np.random.default_rng(6).choice(len(present), 16, replace=False)
+        sel = [tuple(int(v) for v in present[q]) for q in pick]
+        got = [C[int(off[i, j]):int(off[i, j]) + int(p.rows[i] * p.cols[j])].cpu().numpy() for i, j in sel]
+        blocks, _ = oracle.bsmm_blocks(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data,
+                                       p.b_data, sel)
+        num = sum(float(np.sum((g.reshape(b.shape) - b) ** 2)) for g, b in zip(got, blocks))
+        den = sum(float(np.sum(b ** 2)) for b in blocks)
+        r16 = (p.rows + 15) // 16 * 16
+        c16 = (p.cols + 15) // 16 * 16
+        issued = 2.0 * float(r16.sum()) * float(((p.inner + 3) // 4 * 4).sum()) * float(c16.sum())
+        out[label] = {
+            "blocks_per_dim": int(p.rows.size), "block_min": int(p.rows.min()), "block_max": int(p.rows.max()),
+            "tasks": info.tasks, "useful_gflop": round(info.useful_flops / 1e9, 1),
+            "ms_mean": round(float(ev.mean()), 3), "ms_sd": round(float(ev.std(ddof=1)) if reps > 1 else 0.0, 3),
+            "value": round(info.useful_flops / (ev.mean() * 1e-3) / 1e12, 3), "unit": "TFLOP/s",
+            "useful_share_of_mfma_work": round(info.useful_flops / issued, 4),
+            "sampled_rel_err": (num / den) ** 0.5,
+        }
+        plan.close()
+        del A, B, C, p
+        torch.cuda.empty_cache()
+    u, v = out["uniform_256"], out["add_one_row_mean_256"]
+    result = {
+        "metric": "useful TFLOP/s, dense square product, uniform vs the paper's nonuniform blocking",
+        "value": v["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": reps, "warmup": 2,
+        "ms_per_step": v["ms_mean"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"paper_dense_{n}: N={n}, every block present, N(0,1); uniform blocks "
+                               f"of 256 vs add-one-row blocks of mean 256"},
+        "uniform_256": u, "add_one_row_mean_256": v,
+        "nonuniform_over_uniform": round(v["value"] / u["value"], 4),
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nonuniform_16384",
-                    choices=["nonuniform_16384", "uniform_1024", "precision_32768", "decay_cloud_4000"])
+                    choices=["nonuniform_16384", "uniform_1024", "precision_32768", "decay_cloud_4000",
+                             "paper_dense_32768"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the split-bf16 and FP32 forms")
     ap.add_argument("--no-learned", action="store_true", help="flop-count schedule only")
@@ -837,17 +921,21 @@ def main():
     ap.add_argument("--ab-reps", type=int, default=30)
     ap.add_argument("--decay-points", type=int, default=4000,
                     help="points of the decay_cloud workload (4000 = the configured size)")
+    ap.add_argument("--dense-n", type=int, default=32768,
+                    help="paper_dense_32768: the matrix size (blocks of 256)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", type=int, default=0, help="0 = library choice, else variant id + 1")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is a design in DESIGN.md, not a measured path", file=sys.stderr)
+              "layout is a design only, not a measured path", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_1504_05046_amd import bsm
 
+    if args.workload == "paper_dense_32768":
+        return paper_dense_main(args, torch, bsm)
     if args.workload == "decay_cloud_4000":
         args.ab_reps = min(args.ab_reps, 5)
         return decay_main(args, torch, bsm)

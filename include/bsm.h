@@ -61,7 +61,7 @@ typedef enum {
   BSM_E_MISMATCH = -2,    /* arguments disagree with each other or with the plan */
   BSM_E_NOMEM = -3,       /* host or device allocation failed, or a stated limit was exceeded */
   BSM_E_HIP = -4,         /* a HIP runtime call failed (text in bsm_last_error) */
-  BSM_E_UNSUPPORTED = -5, /* no gfx950 device, or an option this build does not provide */
+  BSM_E_UNSUPPORTED = -5, /* no gfx950 device, or an option the library does not provide */
   BSM_E_STATE = -6        /* call out of order, e.g. timings requested but never recorded */
 } bsm_status;
 
