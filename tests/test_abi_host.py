@@ -524,3 +524,16 @@ def test_k_split_plans_on_host():
     assert e.value.code == bsm.E_UNSUPPORTED
     L = bsm.load()
     assert L.bsm_execute_static(sp.handle, 1.0, 1 << 32, 1 << 36, 1 << 40, 0, None) == bsm.E_UNSUPPORTED
+
+
+def test_add_one_row_blocking():
+    """The paper's nonuniform blocking (Sec. 4.1): rows handed out one at a time to uniformly
+    chosen blocks.  Sizes sum to N, no block is empty, and for N = 32768 over 128 blocks the sizes
+    have the multinomial mean 256 and a spread near sqrt(256 (1 - 1/128))."""
+    rng = np.random.default_rng(3)
+    sizes = gen.tiling_add_one(32768, 128, rng)
+    assert sizes.sum() == 32768 and sizes.size == 128 and sizes.min() >= 1
+    assert abs(sizes.mean() - 256) < 1e-9
+    assert 12.0 < sizes.std() < 20.0
+    few = gen.tiling_add_one(5, 40, np.random.default_rng(4))   # most blocks stay empty: dropped
+    assert few.sum() == 5 and few.min() >= 1 and few.size <= 5

@@ -82,6 +82,22 @@ def test_random_nonuniform(seed):
     check(gen.random_problem(100 + seed, 9, 11, 8, 1, 200, 0.35, 0.4))
 
 
+def test_paper_dense_blockings():
+    """The paper's dense square product at N = 1536: uniform blocks of 256, and the add-one-row
+    blocking of the same mean (Sec. 4.1), whose blocks above 256 rows are cut into three
+    sub-tiles per side; FP64 to the FP64 gates, the FP32 and split-bf16 forms to theirs."""
+    uni = gen.paper_dense(8100, 1536, 256, False)
+    assert set(uni.rows.tolist()) == {256}
+    check(uni)
+    p = gen.paper_dense(8100, 1536, 256, True)
+    assert p.rows.sum() == p.inner.sum() == p.cols.sum() == 1536
+    assert p.rows.max() > 256 and p.cols.max() > 256      # three-way cuts on both sides
+    _, ref, _ = check(p)
+    for precision, gate in ((bsm.FP32, 1e-5), (bsm.BF16X3, 1e-6)):
+        got, _ = run_gpu(p, precision=precision)
+        assert rel_fro(got, ref) <= gate
+
+
 @pytest.mark.parametrize("tile", range(1, len(bsm.tile_variants()) + 1))
 def test_every_tile_variant(tile):
     check(gen.random_problem(200 + tile, 6, 7, 6, 1, 300, 0.5, 0.5), tile=tile)
