@@ -863,7 +863,7 @@ def paper_dense_main(args, torch, bsm):
         say(f"paper_dense_{n}: {label}: {ev.mean():.1f} ms per product")
         off = plan.c_offsets()
         present = np.argwhere(off >= 0)
-        pick = np.random.default_rng(6).choice(len(present), 16, replace=False)
+        pick = np.random.default_rng(6).choice(len(present), min(16, len(present)), replace=False)
         sel = [tuple(int(v) for v in present[q]) for q in pick]
         got = [C[int(off[i, j]):int(off[i, j]) + int(p.rows[i] * p.cols[j])].cpu().numpy() for i, j in sel]
         blocks, _ = oracle.bsmm_blocks(p.rows, p.inner, p.cols, p.a_bits(), p.b_bits(), p.a_data,
