@@ -101,6 +101,19 @@ def test_invalid_inputs_rejected():
     _expect(bsm.E_INVALID, lambda: bsm.Plan([1], [1], [1], ok_bits, ok_bits, precision=7))
 
 
+def test_block_size_limit_is_exact():
+    """Block sizes up to 65535 (16-bit task fields) are accepted on every dimension, 65536 is not."""
+    ok_bits = gen.pack_bits(np.ones((1, 1), bool))
+    for rows, inner, cols in (([65535], [1], [1]), ([1], [65535], [1]), ([1], [1], [65535])):
+        plan = bsm.Plan(rows, inner, cols, ok_bits, ok_bits)
+        info = plan.info()
+        assert info.c_blocks == 1 and info.useful_flops == 2.0 * 65535
+        plan.close()
+    for rows, inner, cols in (([65536], [1], [1]), ([1], [65536], [1]), ([1], [1], [65536])):
+        msg = _expect(bsm.E_INVALID, lambda: bsm.Plan(rows, inner, cols, ok_bits, ok_bits))
+        assert "65535" in msg
+
+
 def test_execute_argument_errors_need_no_device():
     p = gen.random_problem(8, 2, 2, 2, 2, 4, 1.0, 1.0)
     plan = bsm.Plan.from_problem(p)
