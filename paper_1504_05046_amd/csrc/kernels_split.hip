@@ -1,8 +1,9 @@
 // Operand preparation passes (HBM-bound, ahead of the tile kernels): conversion for the
-// reduced-precision forms (the packed layout is kept, only the element type changes), and the
+// reduced-precision forms (FP32: the packed layout is kept, only the element type changes;
+// split-bf16: three slice planes in 32-wide k-panels, transposing on the way where needed), the
 // transposition of an operand that the product reads as X^T (Sec. 2.1's transposed variants) into
-// the product's packed layout, and for complex elements the real embedding of the operands and
-// the complex epilogue.
+// the product's packed layout, the real embedding of complex operands and the complex epilogue,
+// and the copies, permutations and reductions of the low-rank, contraction and k_split paths.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
