@@ -169,9 +169,10 @@ hipError_t launch_transpose_f32(const XposeBlock* blocks, int64_t nblocks, const
   return launch_transpose(blocks, nblocks, src, dst, stream);
 }
 
-// One workgroup per complex block: op(X) goes through LDS in 32 x 32 tiles of complex elements
-// (reads along the stored rows, transposed or not; writes along the embedded rows) and is written
-// as [[Re, -Im], [Im, Re]] (left operand, row pitch 2 cols) or [Re; Im] (right operand).
+// One workgroup per piece (up to kZBand rows of a complex block): op(X) goes through LDS in
+// 32 x 32 tiles of complex elements (reads along the stored rows, transposed or not; writes along
+// the embedded rows) and is written as [[Re, -Im], [Im, Re]] (left operand, row pitch 2 cols) or
+// [Re; Im] (right operand); the imaginary half starts full_rows rows below the real one.
 __global__ __launch_bounds__(256) void embed_complex(const ZBlock* __restrict__ blocks,
                                                      const double2* __restrict__ src,
                                                      double* __restrict__ dst) {
@@ -181,13 +182,13 @@ __global__ __launch_bounds__(256) void embed_complex(const ZBlock* __restrict__ 
   const bool right = (b.mode & kZRight) != 0;
   const double2* sb = src + b.src_off;
   double* db = dst + b.dst_off;
-  const int R = b.rows, W = b.cols;
+  const int R = b.rows, W = b.cols, RF = b.full_rows;
   for (int x0 = 0; x0 < R; x0 += 32)
     for (int y0 = 0; y0 < W; y0 += 32) {
       for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
         const int xx = tr ? (e & 31) : (e >> 5), yy = tr ? (e >> 5) : (e & 31);
         if (x0 + xx < R && y0 + yy < W) {
-          const int64_t idx = tr ? int64_t(y0 + yy) * R + x0 + xx : int64_t(x0 + xx) * W + y0 + yy;
+          const int64_t idx = tr ? int64_t(y0 + yy) * RF + x0 + xx : int64_t(x0 + xx) * W + y0 + yy;
           double2 v = sb[idx];
           if (cj) v.y = -v.y;
           tile[xx][yy] = v;
@@ -200,13 +201,13 @@ __global__ __launch_bounds__(256) void embed_complex(const ZBlock* __restrict__ 
           const double2 v = tile[xx][yy];
           if (right) {
             db[int64_t(x) * W + y] = v.x;
-            db[int64_t(R + x) * W + y] = v.y;
+            db[int64_t(RF + x) * W + y] = v.y;
           } else {
             const int64_t ld = 2 * int64_t(W);
             db[int64_t(x) * ld + y] = v.x;
             db[int64_t(x) * ld + W + y] = -v.y;
-            db[int64_t(R + x) * ld + y] = v.y;
-            db[int64_t(R + x) * ld + W + y] = v.x;
+            db[int64_t(RF + x) * ld + y] = v.y;
+            db[int64_t(RF + x) * ld + W + y] = v.x;
           }
         }
       }
@@ -222,8 +223,9 @@ hipError_t launch_embed_complex(const ZBlock* blocks, int64_t nblocks, const dou
   return hipGetLastError();
 }
 
-// One workgroup per complex C block: C = alpha (Re + i Im) (+ C) from the real product's
-// [Re; Im] block, stored interleaved as complex FP64 (V = double2) or complex FP32 (float2).
+// One workgroup per piece of a complex C block: C = alpha (Re + i Im) (+ C) from the real
+// product's [Re; Im] block, stored interleaved as complex FP64 (V = double2) or complex FP32
+// (float2), for the piece's elements [e0, e1).
 template <typename V>
 __global__ __launch_bounds__(256) void complex_epilogue(const ZCBlock* __restrict__ blocks,
                                                         const double* __restrict__ P,
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(256) void complex_epilogue(const ZCBlock* __restric
   const double* pr = P + 2 * b.off;
   const double* pi = pr + b.n;
   V* c = C + b.off;
-  for (int64_t e = threadIdx.x; e < b.n; e += blockDim.x) {
+  for (int64_t e = b.e0 + threadIdx.x; e < b.e1; e += blockDim.x) {
     const double xr = pr[e], xi = pi[e];
     double vr = ar * xr - ai * xi, vi = ar * xi + ai * xr;
     if (accumulate) {

@@ -480,19 +480,28 @@ static std::string build_complex_plan(HostPlan& p, int64_t M, const int64_t* row
       const int64_t o = p.a_off[size_t(i * K + k)];
       if (o < 0) continue;
       const int64_t so = oa ? st_a[size_t(k * M + i)] : st_a[size_t(i * K + k)];
-      p.zembed_a.push_back(ZBlock{so, o, int32_t(rows[i]), int32_t(inner[k]), ma, 0});
+      const int64_t R = rows[i], W = inner[k];  // embedded as 2R x 2W
+      for (int64_t x = 0; x < R; x += kZBand)
+        p.zembed_a.push_back(ZBlock{so + (oa ? x : x * W), o + x * 2 * W,
+                                    int32_t(std::min<int64_t>(kZBand, R - x)), int32_t(W), ma, int32_t(R)});
     }
   for (int64_t k = 0; k < K; ++k)
     for (int64_t j = 0; j < N; ++j) {
       const int64_t o = p.b_off[size_t(k * N + j)];
       if (o < 0) continue;
       const int64_t so = ob ? st_b[size_t(j * K + k)] : st_b[size_t(k * N + j)];
-      p.zembed_b.push_back(ZBlock{so, o, int32_t(inner[k]), int32_t(cols[j]), mb, 0});
+      const int64_t R = inner[k], W = cols[j];  // embedded as 2R x W
+      for (int64_t x = 0; x < R; x += kZBand)
+        p.zembed_b.push_back(ZBlock{so + (ob ? x : x * W), o + x * W,
+                                    int32_t(std::min<int64_t>(kZBand, R - x)), int32_t(W), mb, int32_t(R)});
     }
   for (int64_t i = 0; i < M; ++i)
     for (int64_t j = 0; j < N; ++j) {
       const int64_t o = p.c_off[size_t(i * N + j)];
-      if (o >= 0) p.zc.push_back(ZCBlock{o / 2, rows[i] * cols[j]});
+      if (o < 0) continue;
+      const int64_t n = rows[i] * cols[j];
+      for (int64_t e = 0; e < n; e += kZCPiece)
+        p.zc.push_back(ZCBlock{o / 2, n, e, std::min(n, e + kZCPiece)});
     }
   *code = BSM_OK;
   return "";

@@ -90,26 +90,33 @@ struct PermBlock {
   int64_t e0, e1;
 };
 
-// Complex elements run as a real product: one block of a complex operand as the embedding pass
-// sees it.  The op(X) block is rows x cols complex elements; src_off counts complex elements of the
-// caller's buffer, dst_off real elements of the embedded operand.  mode: bit 0 = stored transposed
-// (the source block is cols x rows), bit 1 = conjugate, bit 2 = right operand (written as the
-// 2 rows x cols real block [Re; Im]; otherwise the 2 rows x 2 cols block [[Re, -Im], [Im, Re]]).
+// Complex elements run as a real product: one piece of a block of a complex operand as the
+// embedding pass sees it.  The op(X) block is full_rows x cols complex elements; a piece is `rows`
+// of its rows (the planner cuts blocks into bands of kZBand rows), src_off and dst_off already
+// point at the piece's first row.  src_off counts complex elements of the caller's buffer, dst_off
+// real elements of the embedded operand.  mode: bit 0 = stored transposed (the source block is
+// cols x full_rows), bit 1 = conjugate, bit 2 = right operand (written as the 2 full_rows x cols
+// real block [Re; Im]; otherwise the 2 full_rows x 2 cols block [[Re, -Im], [Im, Re]]); full_rows
+// places the imaginary half and is the row pitch of a transposed source.
 struct ZBlock {
   int64_t src_off;
   int64_t dst_off;
   int32_t rows;
   int32_t cols;
   int32_t mode;
-  int32_t pad_;
+  int32_t full_rows;
 };
 constexpr int kZTrans = 1, kZConj = 2, kZRight = 4;
+constexpr int kZBand = 32;         // complex rows per embedding piece
+constexpr int64_t kZCPiece = 1 << 14;  // complex elements per epilogue piece
 
-// One complex C block for the epilogue: its offset (complex elements; the real product's
-// [Re; Im] block starts at 2 off) and its element count.
+// One piece of a complex C block for the epilogue: the block's offset (complex elements; the real
+// product's [Re; Im] block starts at 2 off) and element count n, and the piece's elements
+// [e0, e1) of it.
 struct ZCBlock {
   int64_t off;
   int64_t n;
+  int64_t e0, e1;
 };
 
 // One (i,k,j) block triple of a C block's k-list: where A_ik and B_kj start and the inner block
